@@ -1,0 +1,217 @@
+"""FP64 CPU oracle for explicit Hamilton-Jacobi level-set time stepping.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The product path never imports it.
+
+A thin ctypes wrapper over oracle/libhjxo.so (plain C99, built by
+oracle/build.py).  Arrays are numpy float64, C-contiguous, row-major with the
+last axis fastest.  The C source states, function by function, which passage
+of the paper (LevelSetPy, arXiv 2411.03501) it follows.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhjxo.so")
+
+MAXD = 4
+SCHEME = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
+HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("gmin", ctypes.c_double * MAXD),
+        ("gmax", ctypes.c_double * MAXD),
+        ("n", ctypes.c_long * MAXD),
+        ("periodic_mask", ctypes.c_uint),
+        ("ham_kind", ctypes.c_int),
+        ("hp", ctypes.c_double * 8),
+        ("scheme", ctypes.c_int),
+        ("rk", ctypes.c_int),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
+                 cfl=0.75):
+    """Build an oracle problem.  `periodic` lists periodic axes."""
+    P = Problem()
+    P.dim = len(n)
+    for d in range(len(n)):
+        P.gmin[d] = float(gmin[d])
+        P.gmax[d] = float(gmax[d])
+        P.n[d] = int(n[d])
+    P.periodic_mask = sum(1 << d for d in periodic)
+    P.ham_kind = HAM[ham] if isinstance(ham, str) else int(ham)
+    for k, v in enumerate(params):
+        P.hp[k] = float(v)
+    P.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
+    P.rk = int(rk)
+    P.cfl = float(cfl)
+    return P
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        PP = ctypes.POINTER(Problem)
+        L.hjxo_set_threads.argtypes = [ctypes.c_int]
+        L.hjxo_max_threads.restype = ctypes.c_int
+        L.hjxo_grid.argtypes = [PP, ctypes.c_int, dp, dp]
+        L.hjxo_deriv_line.argtypes = [ctypes.c_int, dp, ctypes.c_long, ctypes.c_int,
+                                      ctypes.c_double, dp, dp]
+        L.hjxo_weno5.argtypes = [ctypes.c_double] * 5
+        L.hjxo_weno5.restype = ctypes.c_double
+        L.hjxo_deriv_axis.argtypes = [PP, dp, ctypes.c_int, dp, dp]
+        L.hjxo_ham.argtypes = [PP, ctypes.c_long, dp]
+        L.hjxo_ham.restype = ctypes.c_double
+        L.hjxo_alpha.argtypes = [PP, dp]
+        L.hjxo_cfl_dt.argtypes = [PP]
+        L.hjxo_cfl_dt.restype = ctypes.c_double
+        L.hjxo_rhs.argtypes = [PP, dp, dp]
+        L.hjxo_step.argtypes = [PP, dp, dp, ctypes.c_double]
+        L.hjxo_solve.argtypes = [PP, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.hjxo_solve.restype = ctypes.c_long
+        L.hjxo_cs_solve_loss.argtypes = [PP, dp, dp, dp, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         dp, dp, dp, dp]
+        L.hjxo_cs_solve_loss.restype = ctypes.c_long
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise ValueError(f"oracle {what} rejected its arguments (code {rc})")
+    return rc
+
+
+def set_threads(n):
+    lib().hjxo_set_threads(int(n))
+
+
+def max_threads():
+    return lib().hjxo_max_threads()
+
+
+def shape(P):
+    return tuple(P.n[d] for d in range(P.dim))
+
+
+def grid(P, d):
+    """(dx, coordinates) of axis d."""
+    dx = ctypes.c_double()
+    xs = np.empty(P.n[d], np.float64)
+    _check(lib().hjxo_grid(ctypes.byref(P), d, ctypes.byref(dx), _ptr(xs)), "grid")
+    return dx.value, xs
+
+
+def deriv_line(scheme, phi, dx, periodic=False):
+    """(p-, p+) along a 1-D line, with ghost cells."""
+    phi = _f64(phi)
+    pm = np.empty_like(phi)
+    pp = np.empty_like(phi)
+    s = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
+    _check(lib().hjxo_deriv_line(s, _ptr(phi), phi.size, int(bool(periodic)), float(dx),
+                                 _ptr(pm), _ptr(pp)), "deriv_line")
+    return pm, pp
+
+
+def weno5(v1, v2, v3, v4, v5):
+    return lib().hjxo_weno5(v1, v2, v3, v4, v5)
+
+
+def deriv_axis(P, phi, d):
+    phi = _f64(phi)
+    pm = np.empty_like(phi)
+    pp = np.empty_like(phi)
+    _check(lib().hjxo_deriv_axis(ctypes.byref(P), _ptr(phi), d, _ptr(pm), _ptr(pp)), "deriv")
+    return pm, pp
+
+
+def ham(P, flat_index, p):
+    p = _f64(p)
+    return lib().hjxo_ham(ctypes.byref(P), int(flat_index), _ptr(p))
+
+
+def alpha(P):
+    a = np.zeros(MAXD, np.float64)
+    _check(lib().hjxo_alpha(ctypes.byref(P), _ptr(a)), "alpha")
+    return a[:P.dim].copy()
+
+
+def cfl_dt(P):
+    return lib().hjxo_cfl_dt(ctypes.byref(P))
+
+
+def rhs(P, phi):
+    phi = _f64(phi)
+    L = np.empty_like(phi)
+    _check(lib().hjxo_rhs(ctypes.byref(P), _ptr(phi), _ptr(L)), "rhs")
+    return L
+
+
+def step(P, phi, dt, target=None):
+    out = _f64(phi).copy()
+    tgt = None if target is None else _f64(target)
+    _check(lib().hjxo_step(ctypes.byref(P), _ptr(out), _ptr(tgt), float(dt)), "step")
+    return out
+
+
+def solve(P, phi0, t1, t0=0.0, target=None):
+    """Returns (phi(t1), number of steps, first dt)."""
+    phi0 = _f64(phi0)
+    out = np.empty_like(phi0)
+    tgt = None if target is None else _f64(target)
+    dt0 = ctypes.c_double(0.0)
+    n = _check(lib().hjxo_solve(ctypes.byref(P), _ptr(phi0), _ptr(tgt), float(t0), float(t1),
+                                _ptr(out), ctypes.byref(dt0)), "solve")
+    return out, n, dt0.value
+
+
+def cs_solve_loss(P, phi0, t1, dphi0=None, dparams=None, with_target=True, t0=0.0, eps_h=None,
+                  h=1e-20, want_state=False):
+    """Complex-step directional derivative of the smoothed-Heaviside volume
+    loss after a solve.  Returns (loss, dloss, steps[, phi_T, dphi_T])."""
+    phi0 = _f64(phi0)
+    if eps_h is None:
+        eps_h = 1.5 * max(grid(P, 0)[0], grid(P, 1)[0])
+    d0 = None if dphi0 is None else _f64(dphi0)
+    dh = None
+    if dparams is not None:
+        dh = np.zeros(8, np.float64)
+        dh[:len(dparams)] = dparams
+    loss = ctypes.c_double()
+    dloss = ctypes.c_double()
+    phT = np.empty_like(phi0) if want_state else None
+    tan = np.empty_like(phi0) if want_state else None
+    n = _check(lib().hjxo_cs_solve_loss(ctypes.byref(P), _ptr(phi0), _ptr(d0), _ptr(dh),
+                                        int(bool(with_target)), float(t0), float(t1),
+                                        float(eps_h), float(h), ctypes.byref(loss),
+                                        ctypes.byref(dloss), _ptr(phT), _ptr(tan)), "cs_solve")
+    if want_state:
+        return loss.value, dloss.value, n, phT, tan
+    return loss.value, dloss.value, n

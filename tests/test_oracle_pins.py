@@ -1,0 +1,554 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden/), closed forms, polynomial exactness, formal order
+of accuracy, brute force over the classical ENO construction or over the
+control sets, exact invariants and symmetries.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_03501_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SCHEMES = ["first", "eno2", "eno3", "weno5"]
+
+
+def _golden(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            rows.setdefault(key, []).append([float(Fraction(v)) for v in vals])
+    return rows
+
+
+# --------------------------------------------------------------------------
+# WENO5: the printed optimal combination (Sec. IV-C)
+
+def _weno_smoothness(v):
+    v1, v2, v3, v4, v5 = v
+    s0 = 13 / 12 * (v1 - 2 * v2 + v3) ** 2 + 0.25 * (v1 - 4 * v2 + 3 * v3) ** 2
+    s1 = 13 / 12 * (v2 - 2 * v3 + v4) ** 2 + 0.25 * (v2 - v4) ** 2
+    s2 = 13 / 12 * (v3 - 2 * v4 + v5) ** 2 + 0.25 * (3 * v3 - 4 * v4 + v5) ** 2
+    return s0, s1, s2
+
+
+def _equal_smoothness_samples(count, seed):
+    """Difference vectors, not from a polynomial, whose three smoothness
+    indicators are equal: there the weights are the optimal ones."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        v2, v3, v4 = rng.normal(size=3) * 2
+        s1 = 13 / 12 * (v2 - 2 * v3 + v4) ** 2 + 0.25 * (v2 - v4) ** 2
+        # s2(v5) = s1 and s0(v1) = s1 are quadratics in v5 and v1
+        a5 = 13 / 12 + 0.25
+        b5 = 2 * 13 / 12 * (v3 - 2 * v4) + 2 * 0.25 * (3 * v3 - 4 * v4)
+        c5 = 13 / 12 * (v3 - 2 * v4) ** 2 + 0.25 * (3 * v3 - 4 * v4) ** 2 - s1
+        a1 = 13 / 12 + 0.25
+        b1 = 2 * 13 / 12 * (-2 * v2 + v3) + 2 * 0.25 * (-4 * v2 + 3 * v3)
+        c1 = 13 / 12 * (-2 * v2 + v3) ** 2 + 0.25 * (-4 * v2 + 3 * v3) ** 2 - s1
+        d5 = b5 * b5 - 4 * a5 * c5
+        d1 = b1 * b1 - 4 * a1 * c1
+        if d5 <= 0 or d1 <= 0:
+            continue
+        v5 = (-b5 + math.sqrt(d5)) / (2 * a5)
+        v1 = (-b1 - math.sqrt(d1)) / (2 * a1)
+        v = (v1, v2, v3, v4, v5)
+        # reject vectors that are (close to) linear: those are exact for any weights
+        if abs(v1 - 2 * v2 + v3) < 0.1:
+            continue
+        out.append(v)
+    return out
+
+
+def test_weno5_equal_smoothness_gives_printed_combination():
+    comb = np.array(_golden("weno5_optimal_combination.txt")["combination"][0])
+    assert abs(comb.sum() - 1.0) < 1e-15
+    for v in _equal_smoothness_samples(200, seed=11):
+        s = _weno_smoothness(v)
+        assert max(s) - min(s) < 1e-9 * max(s)
+        got = O.weno5(*v)
+        want = float(np.dot(comb, v))
+        assert abs(got - want) <= 1e-9 * (1 + abs(want)), (v, got, want)
+
+
+def test_weno5_flat_and_scaled():
+    # consistency: equal differences give that difference
+    for c in (0.0, 1.0, -3.5, 1e-7, 1e5):
+        assert O.weno5(c, c, c, c, c) == pytest.approx(c, rel=1e-15, abs=0)
+    # odd symmetry, bit for bit
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        v = rng.normal(size=5)
+        assert O.weno5(*v) == -O.weno5(*(-v))
+
+
+def test_weno5_is_homogeneous_of_degree_one():
+    # the smoothness indicators scale with the square of the differences, so
+    # eps must too (eps = 1e-6 max v^2 + tiny): then the approximation does not
+    # depend on the units of phi.  Pick near-smooth data where the indicators
+    # are comparable to eps, so a differently scaled eps would show.
+    rng = np.random.default_rng(53)
+    for _ in range(200):
+        base = rng.normal() * np.ones(5) + rng.normal() * np.arange(5) * 1e-2
+        v = base + rng.normal(size=5) * 1e-3 * abs(base[0])
+        ref = O.weno5(*v)
+        for lam in (1e-3, 7.0, 1e3):
+            assert abs(O.weno5(*(lam * v)) - lam * ref) <= 1e-12 * abs(lam * ref) + 1e-300
+
+
+def test_weno5_weights_follow_smoothness():
+    # a jump inside the first two substencils: the result follows the smooth third one
+    v = (0.0, 50.0, 1.0, 1.0, 1.0)
+    assert abs(O.weno5(*v) - 1.0) < 1e-6
+    # jump only in the last substencil: first two agree on the value 1
+    v = (1.0, 1.0, 1.0, 1.0, 40.0)
+    assert abs(O.weno5(*v) - 1.0) < 1e-4
+
+
+# --------------------------------------------------------------------------
+# polynomial exactness and formal order (Sec. IV-A..IV-C)
+
+DEGREE = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 3}
+RADIUS = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 3}
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_polynomial_exactness(scheme):
+    rng = np.random.default_rng(5)
+    n, dx = 17, 0.13
+    x = -1.0 + dx * np.arange(n)
+    r = RADIUS[scheme]
+    for _ in range(20):
+        c = rng.normal(size=DEGREE[scheme] + 1)
+        phi = np.polyval(c, x)
+        dphi = np.polyval(np.polyder(c), x)
+        pm, pp = O.deriv_line(scheme, phi, dx)
+        sl = slice(r, n - r)
+        scale = 1 + np.abs(dphi[sl]).max()
+        assert np.abs(pm[sl] - dphi[sl]).max() < 1e-11 * scale
+        assert np.abs(pp[sl] - dphi[sl]).max() < 1e-11 * scale
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_linear_data_exact_through_ghosts(scheme):
+    # non-periodic ghosts extrapolate linearly: linear data stay exact up to the ends
+    n, dx = 11, 0.3
+    x = 2.0 + dx * np.arange(n)
+    phi = -1.7 * x + 0.4
+    pm, pp = O.deriv_line(scheme, phi, dx)
+    assert np.abs(pm + 1.7).max() < 1e-12
+    assert np.abs(pp + 1.7).max() < 1e-12
+
+
+@pytest.mark.parametrize("scheme,order", [("first", 1), ("eno2", 2), ("eno3", 3), ("weno5", 5)])
+def test_order_of_accuracy(scheme, order):
+    errs = []
+    for n in (21, 41, 81, 161):
+        x = np.linspace(-1.0, 1.0, n)
+        dx = x[1] - x[0]
+        phi = np.exp(x) + 0.3 * x * x
+        exact = np.exp(x) + 0.6 * x
+        pm, pp = O.deriv_line(scheme, phi, dx)
+        sl = slice(3, n - 3)
+        errs.append(max(np.abs(pm - exact)[sl].max(), np.abs(pp - exact)[sl].max()))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(rates[1:]) > order - 0.25, (errs, rates)
+    assert max(rates[1:]) < order + 0.6, (errs, rates)
+
+
+# --------------------------------------------------------------------------
+# ENO: brute force over the classical construction (Sec. IV-B)
+
+def _divided_difference(x, f):
+    if len(x) == 1:
+        return f[0]
+    return (_divided_difference(x[1:], f[1:]) - _divided_difference(x[:-1], f[:-1])) / (x[-1] - x[0])
+
+
+def _eno_brute(x, f, i, side, order):
+    """Grow a stencil from the interval next to node i by the smaller
+    |divided difference|, fit the interpolant through it, differentiate."""
+    a = i - 1 if side < 0 else i
+    b = a + 1
+    while b - a < order:
+        left = _divided_difference(x[a - 1:b + 1], f[a - 1:b + 1])
+        right = _divided_difference(x[a:b + 2], f[a:b + 2])
+        if abs(left) <= abs(right):
+            a -= 1
+        else:
+            b += 1
+    xs = x[a:b + 1]
+    coef = np.polyfit(xs - x[i], f[a:b + 1], b - a)
+    return np.polyder(coef)[-1]
+
+
+@pytest.mark.parametrize("scheme,order", [("first", 1), ("eno2", 2), ("eno3", 3)])
+def test_eno_matches_interpolant_bruteforce(scheme, order):
+    rng = np.random.default_rng(17)
+    n, dx = 14, 0.1
+    x = dx * np.arange(n)
+    for trial in range(60):
+        f = rng.normal(size=n) * (1 + 3 * (trial % 3))
+        pm, pp = O.deriv_line(scheme, f, dx)
+        for i in range(4, n - 4):
+            bm = _eno_brute(x, f, i, -1, order)
+            bp = _eno_brute(x, f, i, +1, order)
+            assert abs(pm[i] - bm) <= 1e-8 * (1 + abs(bm))
+            assert abs(pp[i] - bp) <= 1e-8 * (1 + abs(bp))
+
+
+def test_eno_closed_form_multipliers():
+    # the printed Q2', Q3' multipliers against the derivative of the Newton basis
+    g = _golden("eno_closed_forms.txt")
+    for m, mult in g["q2"]:
+        # d/dx (x - x_k)(x - x_{k+1}) at x_i, in units of dx, with m = i - k
+        assert mult == (m - 0) + (m - 1)
+    for m, mult in g["q3"]:
+        assert mult == (m - 1) * (m - 2) + m * (m - 2) + m * (m - 1)
+        assert mult == 3 * m * m - 6 * m + 2
+
+
+def test_eno_ties_go_left():
+    # integer data on dx = 1: |D2_k| = |D2_{k+1}| exactly with opposite signs
+    phi = np.array([0, 0, 0, 0, 1, 0, 0, 0, 0], dtype=np.float64)
+    pm, pp = O.deriv_line("eno2", phi, 1.0)
+    # node 4, left-biased: k = 3, D1_{3.5} = 1, D2_3 = 1/2, D2_4 = -1: no tie;
+    # node 5, left-biased: k = 4, D1_{4.5} = -1, D2_4 = -1, D2_5 = 1/2 -> right
+    assert pm[5] == -1.0 + 0.5 * 1.0
+    # node 4, right-biased: k = 4, D2_4 = -1, D2_5 = 1/2: right choice, c = 1/2
+    assert pp[4] == -1.0 - 0.5
+    # exact tie: D2_k = -D2_{k+1}
+    phi = np.array([0, 0, 0, 1, 1, 0, 0, 0, 0], dtype=np.float64)
+    pm, pp = O.deriv_line("eno2", phi, 1.0)
+    # node 4, left: k = 3, D1_{3.5} = 0, D2_3 = -1/2, D2_4 = -1/2 -> tie, left (c = -1/2, m = 1)
+    assert pm[4] == 0.0 + (-0.5) * 1
+    # node 3, right: k = 3, D1 = 0, D2_3 = -1/2, D2_4 = -1/2: tie goes left, multiplier -1
+    assert pp[3] == 0.0 + (-0.5) * (-1)
+
+
+# --------------------------------------------------------------------------
+# symmetries and ghost cells
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("periodic", [False, True])
+def test_mirror_symmetry_bitwise(scheme, periodic):
+    rng = np.random.default_rng(23)
+    for _ in range(10):
+        phi = rng.normal(size=19)
+        pm, pp = O.deriv_line(scheme, phi, 0.37, periodic)
+        qm, qp = O.deriv_line(scheme, phi[::-1].copy(), 0.37, periodic)
+        assert np.array_equal(pp, -qm[::-1])
+        assert np.array_equal(pm, -qp[::-1])
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_periodic_shift_invariance_bitwise(scheme):
+    rng = np.random.default_rng(29)
+    phi = rng.normal(size=16)
+    pm, pp = O.deriv_line(scheme, phi, 0.25, True)
+    for s in (1, 3, 7, 15):
+        qm, qp = O.deriv_line(scheme, np.roll(phi, s), 0.25, True)
+        assert np.array_equal(qm, np.roll(pm, s))
+        assert np.array_equal(qp, np.roll(pp, s))
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_axis_layout_matches_line_extraction(scheme):
+    n = (7, 9, 8)
+    P = O.make_problem([0, 0, 0], [1, 2, 3], n, periodic=[1], scheme=scheme)
+    phi = np.random.default_rng(31).normal(size=n)
+    for d in range(3):
+        dx = O.grid(P, d)[0]
+        pm, pp = O.deriv_axis(P, phi, d)
+        lines = np.moveaxis(phi, d, -1).reshape(-1, n[d])
+        em = np.empty_like(lines)
+        ep = np.empty_like(lines)
+        for k, line in enumerate(lines):
+            em[k], ep[k] = O.deriv_line(scheme, line, dx, d == 1)
+        shp = np.moveaxis(phi, d, -1).shape
+        assert np.array_equal(np.moveaxis(pm, d, -1), em.reshape(shp))
+        assert np.array_equal(np.moveaxis(pp, d, -1), ep.reshape(shp))
+
+
+def test_grid_spacing_and_coordinates():
+    P = O.make_problem([-6, -10, 0], [20, 10, 2 * math.pi], [101, 101, 101], periodic=[2],
+                       ham="dubins3_pe", params=[5, 5, 1, 1])
+    dx, xs = O.grid(P, 0)
+    assert dx == 26 / 100 and xs[0] == -6 and abs(xs[-1] - 20) < 1e-13
+    dth, th = O.grid(P, 2)
+    assert dth == 2 * math.pi / 101 and th[0] == 0 and th[-1] < 2 * math.pi
+    # the periodic axis has no node on gmax: one more step lands on it
+    assert abs(th[-1] + dth - 2 * math.pi) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Hamiltonians against brute force over the control sets
+
+def _dubins3_bruteforce(x, y, th, p, ve, vp, we, wp):
+    best = -np.inf
+    for ue in np.linspace(-we, we, 21):           # evader maximises
+        worst = np.inf
+        for up in np.linspace(-wp, wp, 21):       # pursuer minimises
+            f = (-ve + vp * math.cos(th) + ue * y, vp * math.sin(th) - ue * x, up - ue)
+            worst = min(worst, p[0] * f[0] + p[1] * f[1] + p[2] * f[2])
+        best = max(best, worst)
+    return -best
+
+
+def _car4_bruteforce(th, v, p, wb, ab):
+    best = np.inf
+    for w in np.linspace(-wb, wb, 21):            # control minimises (reach)
+        for a in np.linspace(-ab, ab, 21):
+            f = (v * math.cos(th), v * math.sin(th), w, a)
+            best = min(best, sum(p[d] * f[d] for d in range(4)))
+    return -best
+
+
+def test_dubins3_hamiltonian_bruteforce():
+    n = (5, 6, 7)
+    prm = (1.3, 2.1, 0.7, 0.4)
+    P = O.make_problem([-2, -3, 0], [3, 1, 2 * math.pi], n, periodic=[2], ham="dubins3_pe",
+                       params=prm)
+    ax = [O.grid(P, d)[1] for d in range(3)]
+    rng = np.random.default_rng(37)
+    for _ in range(200):
+        f = int(rng.integers(0, np.prod(n)))
+        i, j, k = np.unravel_index(f, n)
+        p = rng.normal(size=3)
+        want = _dubins3_bruteforce(ax[0][i], ax[1][j], ax[2][k], p, *prm)
+        assert abs(O.ham(P, f, p) - want) < 1e-12 * (1 + abs(want))
+
+
+def test_car4_hamiltonian_bruteforce():
+    n = (3, 4, 5, 6)
+    prm = (0.8, 1.7)
+    P = O.make_problem([-1, -1, 0, 0], [1, 1, 2 * math.pi, 2], n, periodic=[2], ham="dubins4",
+                       params=prm)
+    ax = [O.grid(P, d)[1] for d in range(4)]
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        f = int(rng.integers(0, np.prod(n)))
+        idx = np.unravel_index(f, n)
+        p = rng.normal(size=4)
+        want = _car4_bruteforce(ax[2][idx[2]], ax[3][idx[3]], p, *prm)
+        assert abs(O.ham(P, f, p) - want) < 1e-12 * (1 + abs(want))
+
+
+def test_normal_hamiltonian():
+    P = O.make_problem([-1, -1], [1, 1], [5, 5], ham="normal", params=[2.5])
+    p = np.array([3.0, -4.0])
+    assert O.ham(P, 7, p) == 2.5 * 5.0
+
+
+# --------------------------------------------------------------------------
+# dissipation bounds, CFL step and step counts (Sec. IV-D, Sec. V)
+
+def test_alpha_closed_form_and_step_counts():
+    w = inputs.DUBINS3D
+    P = O.make_problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params)
+    x, y, th = inputs.node_axes(w)
+    ve, vp, we, wp = w.params
+    # the per-node bounds separate over axes, so their maxima add exactly
+    a0 = np.abs(-ve + vp * np.cos(th)).max() + we * np.abs(y).max()
+    a1 = np.abs(vp * np.sin(th)).max() + we * np.abs(x).max()
+    alpha = O.alpha(P)
+    assert alpha[0] == a0 and alpha[1] == a1 and alpha[2] == we + wp
+    dxs = [O.grid(P, d)[0] for d in range(3)]
+    dt = 0.75 / sum(alpha[d] / dxs[d] for d in range(3))
+    assert O.cfl_dt(P) == dt
+    assert math.ceil(2.8 / dt) == 874
+    # the other workloads
+    assert math.ceil(0.3 / O.cfl_dt(O.make_problem([-1, -1], [1, 1], [101, 101], params=[1]))) == 40
+    w3 = inputs.DUBINS3D_81
+    P3 = O.make_problem(w3.gmin, w3.gmax, w3.n, w3.periodic, w3.ham, w3.params)
+    assert math.ceil(2.8 / O.cfl_dt(P3)) == 700
+
+
+def test_car4_alpha_closed_form():
+    # small grid with the car4d extents; the bounds are |v cos th|, |v sin th|, wbar, abar
+    n = (9, 9, 81, 81)
+    w = inputs.CAR4D
+    P = O.make_problem(w.gmin, w.gmax, n, w.periodic, w.ham, w.params)
+    th = O.grid(P, 2)[1]
+    v = O.grid(P, 3)[1]
+    alpha = O.alpha(P)
+    assert alpha[0] == np.abs(np.outer(np.cos(th), v)).max()
+    assert alpha[1] == np.abs(np.outer(np.sin(th), v)).max()
+    assert alpha[2] == 1.0 and alpha[3] == 1.0
+    dxs = [O.grid(P, d)[0] for d in range(4)]
+    assert O.cfl_dt(P) == 0.75 / sum(alpha[d] / dxs[d] for d in range(4))
+    # the theta and v axes are those of car4d, so its bounds are these; with
+    # its 81-node x, y spacing the horizon 1.5 takes 170 steps
+    full = [10 / 80, 10 / 80, 2 * math.pi / 81, 2 / 80]
+    assert math.ceil(1.5 / (0.75 / sum(alpha[d] / full[d] for d in range(4)))) == 170
+
+
+# --------------------------------------------------------------------------
+# LF reduces to upwinding for a linear Hamiltonian (Sec. IV-A, IV-D)
+
+@pytest.mark.parametrize("ve", [1.7, -2.3])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_lf_reduces_to_upwinding(ve, scheme):
+    n = (12, 5, 4)
+    # v_p = 0 and no turning: pure transport along x at speed -v_e
+    P = O.make_problem([0, 0, 0], [1, 1, 2 * math.pi], n, periodic=[0, 2], ham="dubins3_pe",
+                       params=[ve, 0.0, 0.0, 0.0], scheme=scheme)
+    phi = inputs.smooth_field(n, seed=43)
+    L = O.rhs(P, phi)
+    pm, pp = O.deriv_axis(P, phi, 0)
+    up = pm if ve > 0 else pp
+    assert np.abs(L - (-ve * up)).max() < 1e-13 * (1 + np.abs(up).max())
+
+
+# --------------------------------------------------------------------------
+# TVD-RK: on a linear semi-discrete system one step is the truncated
+# exponential (Sec. V)
+
+@pytest.mark.parametrize("rk", [1, 2, 3])
+def test_rk_step_is_truncated_exponential(rk):
+    n = (16, 3, 3)
+    P = O.make_problem([0, 0, 0], [1, 1, 2 * math.pi], n, periodic=[0, 2], ham="dubins3_pe",
+                       params=[1.3, 0.0, 0.0, 0.0], scheme="first", rk=rk)
+    phi = inputs.smooth_field(n, seed=47)
+    dt = 0.05
+    term = phi.copy()
+    want = phi.copy()
+    for k in range(1, rk + 1):
+        term = dt * O.rhs(P, term) / k
+        want = want + term
+    got = O.step(P, phi, dt)
+    assert np.abs(got - want).max() < 1e-13 * (1 + np.abs(phi).max())
+
+
+def test_rk_golden_averaging_coefficients():
+    g = _golden("tvd_rk_coefficients.txt")
+    # one RK2/RK3 step on a constant-slope field reproduces the averaging weights:
+    # with L constant (= c), every Euler move adds dt*c and the averages must
+    # give phi + dt*c, which needs the weights of each average to sum to one
+    for key in ("rk2_final", "rk3_half", "rk3_final"):
+        a, b = g[key][0]
+        assert a + b == 1.0
+    # and the stages times of RK3 follow: 1/4 * 2 dt = dt/2, then 2/3 * (dt/2 + dt) = dt
+    a, b = g["rk3_half"][0]
+    half = b * 2
+    a3, b3 = g["rk3_final"][0]
+    assert b3 * (half + 1) == 1.0
+
+
+# --------------------------------------------------------------------------
+# closed forms of whole solves
+
+def test_normal_motion_closed_form_first_order():
+    errs = []
+    for n in (51, 101, 201):
+        w = inputs.NORMAL2D.with_(n=(n, n))
+        P = O.make_problem(w.gmin, w.gmax, w.n, ham="normal", params=[1.0], scheme="first", rk=1)
+        phi0 = inputs.initial_surface(w)
+        out, steps, dt = O.solve(P, phi0, 0.3)
+        if n == 101:
+            assert steps == 40 and dt == 0.0075
+        x = inputs.node_axes(w)[0]
+        X, Y = np.meshgrid(x, x, indexing="ij")
+        r = np.sqrt(X * X + Y * Y)
+        exact = np.maximum(r - 0.3, 0.0) - 0.5   # Hopf-Lax
+        # a fixed distance away from the kink at |x| = t and from the boundary
+        m = (r >= 0.45) & (np.abs(X) <= 0.9) & (np.abs(Y) <= 0.9)
+        errs.append(np.abs(out - exact)[m].max())
+    assert errs[1] < 0.015
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(0.8 < r < 1.3 for r in rates), (errs, rates)
+
+
+def _translation_problem(nxy, nth, target):
+    L = 2 * math.pi
+    n = (nxy, nxy, nth)
+    P = O.make_problem([0, 0, 0], [L, L, 2 * math.pi], n, periodic=[0, 1, 2], ham="dubins3_pe",
+                       params=[1.0, 1.0, 0.0, 0.0], scheme="weno5", rk=3)
+    ax = [O.grid(P, d)[1] for d in range(3)]
+    X, Y, TH = np.meshgrid(*ax, indexing="ij")
+    phi0 = np.sin(X) + 0.5 * np.cos(Y) + 0.3 * np.sin(X + Y)
+    return P, X, Y, TH, phi0
+
+
+def _translated(X, Y, TH, s):
+    fx = -1.0 + np.cos(TH)
+    fy = np.sin(TH)
+    Xs, Ys = X + s * fx, Y + s * fy
+    return np.sin(Xs) + 0.5 * np.cos(Ys) + 0.3 * np.sin(Xs + Ys)
+
+
+def test_zero_turn_dubins_is_translation():
+    errs = []
+    for nxy in (24, 48):
+        P, X, Y, TH, phi0 = _translation_problem(nxy, 6, False)
+        out, steps, dt = O.solve(P, phi0, 0.6)
+        errs.append(np.abs(out - _translated(X, Y, TH, 0.6)).max())
+    assert errs[1] < 2e-4
+    assert math.log2(errs[0] / errs[1]) > 2.7, errs
+
+
+def test_zero_turn_tube_is_min_over_step_times():
+    # with min-with-target after every full step, the discrete tube of a pure
+    # translation is the minimum of the translates at the step times; the
+    # minimum has kinks, so convergence is measured in the mean
+    means = []
+    for nxy in (24, 48):
+        P, X, Y, TH, phi0 = _translation_problem(nxy, 6, True)
+        out, steps, dt = O.solve(P, phi0, 0.6, target=phi0)
+        times = [min(k * dt, 0.6) for k in range(steps + 1)]
+        want = np.min([_translated(X, Y, TH, s) for s in times], axis=0)
+        means.append(np.abs(out - want).mean())
+    assert means[1] < 5e-4
+    assert means[0] / means[1] > 3.0, means
+
+
+# --------------------------------------------------------------------------
+# reachable-tube invariants on the pursuit-evasion game
+
+def _small_dubins(n=(21, 21, 16)):
+    w = inputs.DUBINS3D.with_(n=n)
+    P = O.make_problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params)
+    return w, P, inputs.initial_surface(w)
+
+
+def test_min_with_target_invariants():
+    w, P, phi0 = _small_dubins()
+    out, steps, _ = O.solve(P, phi0, 0.8, target=phi0)
+    assert np.all(out <= phi0)                       # exact: min after every step
+    assert np.all(out[phi0 <= 0] <= 0)               # the tube contains the target
+    assert (out <= 0).sum() > (phi0 <= 0).sum()      # and has grown
+
+
+def test_reflection_symmetry():
+    # (x, y, theta) -> (x, -y, -theta) maps the game to itself
+    w, P, phi0 = _small_dubins(n=(21, 21, 16))
+    out, _, _ = O.solve(P, phi0, 0.8, target=phi0)
+    ny, nth = w.n[1], w.n[2]
+    jy = ny - 1 - np.arange(ny)
+    jth = (nth - np.arange(nth)) % nth
+    mirrored = out[:, jy][:, :, jth]
+    assert np.abs(out - mirrored).max() < 1e-10
+
+
+def test_time_reversal_of_sign_convention():
+    # H = a|p| grows the sublevel set: phi decreases at speed a where |grad phi| = 1
+    w = inputs.NORMAL2D.with_(n=(41, 41))
+    P = O.make_problem(w.gmin, w.gmax, w.n, ham="normal", params=[1.0], scheme="weno5", rk=3)
+    phi0 = inputs.initial_surface(w)
+    L = O.rhs(P, phi0)
+    x = inputs.node_axes(w)[0]
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    r = np.sqrt(X * X + Y * Y)
+    m = (r > 0.3) & (np.abs(X) < 0.8) & (np.abs(Y) < 0.8)
+    assert np.abs(L[m] + 1.0).max() < 1e-3
