@@ -1,0 +1,183 @@
+"""Throughput of the level-set hot path on one MI355X.
+
+A bench step is one whole solve of the workload: the dissipation reduction,
+the CFL step and every WENO5 + Lax-Friedrichs + TVD-RK3 step with
+min-with-target to the horizon, on synthetic inputs already resident in HBM.
+Default workload: 3-D pursuit-evasion game (relative Dubins cars,
+v_e = v_p = 5, |w| <= 1), 101^3 nodes over [-6,20]x[-10,10]x[0,2pi), cylinder
+of radius 5 as target, horizon 2.8 (874 RK3 steps).
+
+Prints ONE JSON line.  value = grid-point updates/s, a grid-point update
+being one node advanced by one full RK3 step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one FP32 or FP64 operation, FMA counted once, per lane per clock; packed
+# FP32 is not used)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_ops_per_point(scheme, ham, dim):
+    """Arithmetic operations per node per stage, counted from the formulas of
+    the method (FMA = 1, reciprocal = 1, |.|/max/min = 1)."""
+    per_dim = {
+        "first": 4,     # two differences, two scalings
+        "weno5": 136,   # six scaled differences + two WENO5 evaluations of 62
+    }[scheme]
+    ham_lf = {"normal": 2 * dim + 2 + 2 * dim, "dubins3_pe": 27, "dubins4": 26}[ham]
+    rk = 4
+    return per_dim * dim + ham_lf + rk
+
+
+def stage_bytes_per_point(rk, with_target, elem):
+    reads_writes = {1: 2, 2: 5, 3: 8}[rk] + (1 if with_target else 0)
+    return reads_writes * elem / rk
+
+
+def run_gpu(w, dtype, steps, warmup):
+    import torch
+
+    from paper_2411_03501_amd import hjx, inputs
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    P = hjx.Problem.from_workload(w, dtype)
+    phi0 = torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=tdt)
+    target = phi0 if w.with_target else None
+    out = torch.empty_like(phi0)
+    for i in range(warmup):
+        P.solve(phi0, w.t1, target=target, out=out)
+        log(f"  warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    loop_ms = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, st = P.solve(phi0, w.t1, target=target, out=out)
+        loop_ms.append(st["elapsed_ms"])
+        log(f"  step {i + 1}/{steps}: {st['steps']} RK steps, loop {st['elapsed_ms']:.2f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.close()
+    return elapsed, st, loop_ms
+
+
+def run_cpu_baseline(w, budget_s=15.0):
+    """The oracle as it stands, on the host's cores, for a bounded number of
+    RK steps of the same workload."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2411_03501_amd import inputs
+
+    threads = min(os.cpu_count() or 1, 16)
+    O.set_threads(threads)
+    Po = O.make_problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params, w.scheme, w.rk, w.cfl)
+    phi = inputs.initial_surface(w)
+    dt = O.cfl_dt(Po)
+    tgt = phi.copy() if w.with_target else None
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        phi = O.step(Po, phi, dt, target=tgt)
+        done += 1
+        el = time.perf_counter() - t0
+        log(f"  oracle step {done}: {el:.1f} s")
+        if el > budget_s or done >= 50:
+            break
+    assert np.isfinite(phi).all()
+    return {"value": w.points * done / el, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} RK3 steps of the full {w.name} grid ({w.points} nodes), FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="dubins3d")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the solver would shard by slabs with halo exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2411_03501_amd import inputs
+
+    w = inputs.WORKLOADS[args.workload]
+    log(f"bench {w.name} {args.dtype}: {w.points} nodes, K={args.steps} W={args.warmup}")
+    elapsed, st, loop_ms = run_gpu(w, args.dtype, args.steps, args.warmup)
+    rk_steps = st["steps"]
+    elem = 4 if args.dtype == "f32" else 8
+    updates = w.points * rk_steps * args.steps
+    value = updates / elapsed
+
+    launches = rk_steps * w.rk
+    kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / launches   # mean stage-kernel duration
+    ops = alg_ops_per_point(w.scheme, w.ham, w.dim) * w.points
+    achieved_tops = ops / kern_s / 1e12
+    bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
+    achieved_gbs = bytes_launch / kern_s / 1e9
+    if w.scheme == "weno5":
+        roof = {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
+                "kernel": "stage_kernel", "kernel_us": kern_s * 1e6,
+                "hbm_alg_gbs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": None,
+                "kernel": "stage_kernel", "kernel_us": kern_s * 1e6}
+
+    extra = {}
+    if not args.no_extra:
+        other = "f64" if args.dtype == "f32" else "f32"
+        log(f"secondary: {w.name} {other}")
+        e2, st2, _ = run_gpu(w, other, 2, 1)
+        extra[f"{w.name}_{other}_updates_per_s"] = w.points * st2["steps"] * 2 / e2
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: oracle")
+        cpu = run_cpu_baseline(w)
+
+    line = {
+        "metric": "grid-point updates/s per WENO5-RK3 step",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: 3-D pursuit-evasion BRT, {'x'.join(map(str, w.n))} nodes, "
+                               f"{w.scheme.upper()}+LF+TVD-RK{w.rk}, min-with-target, horizon {w.t1} "
+                               f"({rk_steps} RK steps per solve)",
+                   "nodes": w.points, "rk_steps_per_solve": rk_steps, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * hjx.h -- C ABI of libhjx, MI355X (gfx950) explicit time stepping of the
+ * Hamilton-Jacobi initial-value problem on dense Cartesian grids, after the
+ * level-set toolbox of LevelSetPy (arXiv 2411.03501).
+ *
+ * The problem (Sec. II, eq. (ivp)): find phi(x, tau) with
+ *     phi_tau + H(x, grad phi) = 0,   phi(x, 0) = phi0(x),
+ * tau being time to go.  Its zero sublevel set is a backward reachable set;
+ * with min-with-target after every step it is a reachable tube (Sec. VI,
+ * variational HJ PDE).  One step of the solver:
+ *   1. upwind one-sided derivatives p-_d, p+_d along every axis, with ghost
+ *      cells (first order, ENO2, ENO3 or WENO5; Sec. IV-A..IV-C);
+ *   2. the Lax-Friedrichs numerical Hamiltonian
+ *      Hhat = H(x, (p- + p+)/2) - sum_d alpha_d (p+_d - p-_d)/2 with
+ *      alpha_d the grid-wide maximum of |dH/dp_d| (Sec. IV-D, Listing 4);
+ *   3. dt = cfl / sum_d alpha_d / dx_d (Sec. IV-D CFL condition, Sec. V);
+ *   4. TVD Runge-Kutta of order 1, 2 or 3 on L = -Hhat (Sec. V, odeCFL1/2/3),
+ *      then phi <- min(phi, target) if a target is given (Sec. VI).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Arrays: device memory owned by the caller, contiguous, row-major with the
+ *   LAST axis fastest, n[0]*...*n[dim-1] elements of the problem's dtype
+ *   (float for HJX_F32, double for HJX_F64).  The library never frees,
+ *   keeps or copies to the host any caller array.
+ * Streams: every call that touches the device enqueues on `stream`
+ *   (a hipStream_t; NULL is the null stream).  Calls that return host values
+ *   (hjx_dissipation, hjx_solve) synchronise that stream.
+ * Errors: every call returns an hjx_status; on failure hjx_last_error()
+ *   describes it.  Arguments are validated before anything is enqueued.
+ * Threads: a problem handle may be used by one thread at a time; distinct
+ *   handles are independent.
+ * Limits: 1 <= dim <= 4; 3 <= n[d]; total nodes < 2^31.
+ */
+#ifndef HJX_H
+#define HJX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HJX_OK = 0,
+    HJX_ERR_INVALID_ARG = 1, /* a NULL pointer, a value out of range, an inconsistent descriptor */
+    HJX_ERR_UNSUPPORTED = 2, /* a combination the library does not implement */
+    HJX_ERR_DEVICE = 3,      /* a HIP runtime call failed */
+    HJX_ERR_NONFINITE = 4,   /* NaN or Inf in the data (the output is still written) */
+    HJX_ERR_OOM = 5          /* device memory could not be allocated */
+} hjx_status;
+
+typedef enum { HJX_F32 = 0, HJX_F64 = 1 } hjx_dtype;
+
+/* Spatial derivative scheme ('CoStateCalc', Listing 4): Sec. IV-A upwindFirstFirst,
+ * Sec. IV-B upwindFirstENO2 / upwindFirstENO3, Sec. IV-C upwindFirstWENO5. */
+typedef enum {
+    HJX_DERIV_FIRST = 1,
+    HJX_DERIV_ENO2 = 2,
+    HJX_DERIV_ENO3 = 3,
+    HJX_DERIV_WENO5 = 5
+} hjx_deriv;
+
+/* TVD Runge-Kutta order, Sec. V (odeCFL1, odeCFL2, odeCFL3). */
+typedef enum { HJX_RK1 = 1, HJX_RK2 = 2, HJX_RK3 = 3 } hjx_rk;
+
+/* Built-in Hamiltonians (device code cannot call back into Python, so the
+ * 'hamFunc'/'partialFunc' pair of Listing 4 is a kind plus parameters).
+ *   HJX_HAM_NORMAL      any dim, p = {a}: H = a |p|, alpha_d = |a|.
+ *   HJX_HAM_DUBINS3_PE  dim 3, axes (x, y, theta), p = {v_e, v_p, wbar_e, wbar_p}:
+ *       pursuit-evasion of two unicycles in the evader's frame,
+ *       H = -[p1(-v_e + v_p cos th) + p2 v_p sin th
+ *             + wbar_e |p1 y - p2 x - p3| - wbar_p |p3|],
+ *       alpha = (|-v_e + v_p cos th| + wbar_e|y|, |v_p sin th| + wbar_e|x|,
+ *                wbar_e + wbar_p).  Requires wbar_e, wbar_p >= 0.
+ *   HJX_HAM_DUBINS4     dim 4, axes (x, y, theta, v), p = {wbar, abar}:
+ *       car with speed state, reach: H = -v(p1 cos th + p2 sin th)
+ *       + wbar|p3| + abar|p4|, alpha = (|v cos th|, |v sin th|, wbar, abar).
+ *       Requires wbar, abar >= 0. */
+typedef enum {
+    HJX_HAM_NORMAL = 0,
+    HJX_HAM_DUBINS3_PE = 1,
+    HJX_HAM_DUBINS4 = 2
+} hjx_ham_kind;
+
+#define HJX_MAX_DIM 4
+
+/* Grid (Sec. III-B, Listing 1: gmin, gmax, N, periodic dims).  A
+ * non-periodic axis d has n[d] nodes from gmin[d] to gmax[d] inclusive
+ * (dx = (gmax-gmin)/(n-1)); a periodic axis covers [gmin, gmax) with
+ * dx = (gmax-gmin)/n.  Bit d of periodic_mask makes axis d periodic; the
+ * other axes get linearly extrapolated ghost cells. */
+typedef struct {
+    int32_t dim;
+    uint32_t periodic_mask;
+    double gmin[HJX_MAX_DIM];
+    double gmax[HJX_MAX_DIM];
+    int64_t n[HJX_MAX_DIM];
+} hjx_grid_desc;
+
+typedef struct {
+    int32_t kind; /* hjx_ham_kind */
+    int32_t reserved;
+    double p[8];
+} hjx_ham_desc;
+
+typedef struct {
+    int32_t deriv; /* hjx_deriv */
+    int32_t rk;    /* hjx_rk */
+    double cfl;    /* 0 < cfl <= 1 */
+    int32_t dtype; /* hjx_dtype */
+    int32_t reserved;
+} hjx_scheme_desc;
+
+typedef struct {
+    int64_t steps;              /* RK steps taken */
+    double dt;                  /* the CFL step */
+    double dt_last;             /* the last (clamped) step */
+    double t_final;
+    double alpha[HJX_MAX_DIM];  /* dissipation coefficients used */
+    double elapsed_ms;          /* device time of the stepping loop */
+    double alg_bytes;           /* algorithmic HBM bytes of the stepping loop */
+} hjx_stats;
+
+typedef struct hjx_problem hjx_problem;
+
+/* Library version, "major.minor.patch". */
+const char *hjx_version(void);
+
+/* Description of the last failure on the calling thread ("" if none).  The
+ * string stays valid until the next hjx call on that thread. */
+const char *hjx_last_error(void);
+
+/* Create a problem: validates the descriptors, builds the per-axis
+ * coordinate tables (Sec. III-B) on the device and allocates the stage
+ * workspace (two arrays of n[0]*..*n[dim-1] elements).  On success *out owns
+ * that memory until hjx_problem_destroy.  Selects the current HIP device. */
+hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham,
+                              const hjx_scheme_desc *scheme, hjx_problem **out);
+
+/* Free a problem and its device memory (NULL is a no-op).  The caller must
+ * make sure no enqueued work still uses it. */
+hjx_status hjx_problem_destroy(hjx_problem *p);
+
+/* Dissipation coefficients and CFL step (Sec. IV-D, GLF dissipation of
+ * Listing 4): alpha_d = max over all grid nodes of the partial bound,
+ * reduced on the device; dt = cfl / sum_d alpha_d/dx_d (+inf when every
+ * alpha_d is 0).  alpha_out: host array of at least dim doubles; dt_out:
+ * host double.  Synchronises `stream`. */
+hjx_status hjx_dissipation(hjx_problem *p, double *alpha_out, double *dt_out, void *stream);
+
+/* Lax-Friedrichs right-hand side L = -Hhat(phi) at every node (Sec. IV,
+ * steps 1-2 above), with the grid-wide alpha.  phi, L_out: device arrays
+ * (may not alias).  Asynchronous on `stream`. */
+hjx_status hjx_rhs(hjx_problem *p, const void *phi, void *L_out, void *stream);
+
+/* One TVD-RK step of size dt (Sec. V), in place on phi, followed by
+ * phi <- min(phi, target) when target != NULL (Sec. VI).  phi: device
+ * array, read and written; target: device array or NULL, which must not
+ * alias phi.  dt > 0.  Asynchronous on `stream`. */
+hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, void *stream);
+
+/* Solve from t0 to t1 (Listing 3 odeCFLx(schemeFunc, tspan, y0, ...)):
+ * steps of the CFL size dt, the one that would reach t1 (or come within
+ * 1e-12 max(1,|t1|) of it) clamped to land on t1.  phi0: initial data;
+ * target: device array for min-with-target, or NULL for none (target may be
+ * phi0, but not phi_out); phi_out: result (may be phi0 itself).  t1 >= t0.
+ * Synchronises
+ * `stream`.  stats (optional, host) receives the step record.  Returns
+ * HJX_ERR_NONFINITE without stepping if phi0 holds NaN/Inf, and after the
+ * solve (phi_out written) if the result does. */
+hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void *phi_out,
+                     double t0, double t1, void *stream, hjx_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJX_H */

@@ -1,0 +1,485 @@
+// C ABI of libhjx (include/hjx.h): argument validation, per-axis tables,
+// workspace ownership and the explicit time loop (LevelSetPy, arXiv
+// 2411.03501, Sec. V: odeCFL1/2/3 with the CFL step of Sec. IV-D).
+#include "../../include/hjx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hjx_internal.h"
+
+using namespace hjx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hjx_status fail(hjx_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+hjx_status ok()
+{
+    g_last_error.clear();
+    return HJX_OK;
+}
+
+#define HIP_TRY(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "%s: %s (%s)", \
+                        #call, hipGetErrorString(e_), __func__);                              \
+    } while (0)
+
+int n_params(int kind)
+{
+    switch (kind) {
+    case HJX_HAM_NORMAL: return 1;
+    case HJX_HAM_DUBINS3_PE: return 4;
+    case HJX_HAM_DUBINS4: return 2;
+    }
+    return 0;
+}
+
+}  // namespace
+
+struct hjx_problem {
+    hjx_grid_desc grid;
+    hjx_ham_desc ham;
+    hjx_scheme_desc scheme;
+    int device = 0;
+    int64_t total = 0;
+    double dx[kMaxDim] = {0, 0, 0, 0};
+    size_t elem = 0;           // bytes per value
+    void *tables = nullptr;    // device: per axis coord, cos, sin (elem bytes each)
+    size_t table_off[kMaxDim][3] = {};
+    void *ws[2] = {nullptr, nullptr};
+    double *dalpha = nullptr;  // device: alpha[kMaxDim] + reduction partials
+    int *dflag = nullptr;      // device: non-finite flag
+    double *hbuf = nullptr;    // pinned host: alpha[kMaxDim], flag
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+GridGeom geometry(const hjx_problem *p)
+{
+    GridGeom g{};
+    g.dim = p->grid.dim;
+    int s = 1;
+    for (int d = g.dim - 1; d >= 0; --d) {
+        g.n[d] = (int)p->grid.n[d];
+        g.stride[d] = s;
+        s *= g.n[d];
+    }
+    for (int d = g.dim; d < kMaxDim; ++d) {
+        g.n[d] = 1;
+        g.stride[d] = 0;
+    }
+    g.periodic = p->grid.periodic_mask;
+    if (g.dim == 1) {
+        g.plane = g.n[0];
+        g.slow = 1;
+    } else {
+        g.plane = g.n[g.dim - 2] * g.n[g.dim - 1];
+        g.slow = 1;
+        for (int d = 0; d < g.dim - 2; ++d) g.slow *= g.n[d];
+    }
+    return g;
+}
+
+template <typename T>
+AxisTables<T> tables(const hjx_problem *p)
+{
+    AxisTables<T> t{};
+    const char *base = static_cast<const char *>(p->tables);
+    for (int d = 0; d < p->grid.dim; ++d) {
+        t.coord[d] = reinterpret_cast<const T *>(base + p->table_off[d][0]);
+        t.cosv[d] = reinterpret_cast<const T *>(base + p->table_off[d][1]);
+        t.sinv[d] = reinterpret_cast<const T *>(base + p->table_off[d][2]);
+    }
+    return t;
+}
+
+hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_scheme_desc *s)
+{
+    if (!g || !h || !s) return fail(HJX_ERR_INVALID_ARG, "NULL descriptor");
+    if (g->dim < 1 || g->dim > HJX_MAX_DIM)
+        return fail(HJX_ERR_INVALID_ARG, "grid dim %d outside [1, %d]", g->dim, HJX_MAX_DIM);
+    if (g->periodic_mask >> g->dim)
+        return fail(HJX_ERR_INVALID_ARG, "periodic_mask 0x%x names an axis >= dim %d", g->periodic_mask, g->dim);
+    int64_t total = 1;
+    for (int d = 0; d < g->dim; ++d) {
+        if (g->n[d] < 3) return fail(HJX_ERR_INVALID_ARG, "n[%d] = %lld < 3", d, (long long)g->n[d]);
+        if (!std::isfinite(g->gmin[d]) || !std::isfinite(g->gmax[d]) || !(g->gmax[d] > g->gmin[d]))
+            return fail(HJX_ERR_INVALID_ARG, "axis %d extent [%g, %g] is not a finite increasing interval", d,
+                        g->gmin[d], g->gmax[d]);
+        total *= g->n[d];
+        if (total >= (int64_t(1) << 31))
+            return fail(HJX_ERR_INVALID_ARG, "grid has 2^31 nodes or more");
+    }
+    const int np = n_params(h->kind);
+    if (np == 0) return fail(HJX_ERR_INVALID_ARG, "unknown Hamiltonian kind %d", h->kind);
+    for (int k = 0; k < np; ++k)
+        if (!std::isfinite(h->p[k])) return fail(HJX_ERR_INVALID_ARG, "Hamiltonian parameter %d is not finite", k);
+    if (h->kind == HJX_HAM_DUBINS3_PE) {
+        if (g->dim != 3) return fail(HJX_ERR_INVALID_ARG, "DUBINS3_PE needs dim 3, got %d", g->dim);
+        if (h->p[2] < 0 || h->p[3] < 0) return fail(HJX_ERR_INVALID_ARG, "turn-rate bounds must be >= 0");
+    }
+    if (h->kind == HJX_HAM_DUBINS4) {
+        if (g->dim != 4) return fail(HJX_ERR_INVALID_ARG, "DUBINS4 needs dim 4, got %d", g->dim);
+        if (h->p[0] < 0 || h->p[1] < 0) return fail(HJX_ERR_INVALID_ARG, "control bounds must be >= 0");
+    }
+    if (s->deriv != HJX_DERIV_FIRST && s->deriv != HJX_DERIV_ENO2 && s->deriv != HJX_DERIV_ENO3 &&
+        s->deriv != HJX_DERIV_WENO5)
+        return fail(HJX_ERR_INVALID_ARG, "unknown derivative scheme %d", s->deriv);
+    if (s->rk < 1 || s->rk > 3) return fail(HJX_ERR_INVALID_ARG, "rk order %d outside [1, 3]", s->rk);
+    if (!(s->cfl > 0.0) || !(s->cfl <= 1.0)) return fail(HJX_ERR_INVALID_ARG, "cfl %g outside (0, 1]", s->cfl);
+    if (s->dtype != HJX_F32 && s->dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", s->dtype);
+    return HJX_OK;
+}
+
+// ---------------------------------------------------------------- launches
+
+template <typename T>
+StageArgs<T> stage_args(const hjx_problem *p, const double *alpha)
+{
+    StageArgs<T> a{};
+    a.g = geometry(p);
+    a.tab = tables<T>(p);
+    for (int d = 0; d < kMaxDim; ++d) {
+        a.inv_dx[d] = d < p->grid.dim ? T(1.0 / p->dx[d]) : T(0);
+        a.dx[d] = d < p->grid.dim ? T(p->dx[d]) : T(0);
+        a.alpha[d] = d < p->grid.dim ? T(alpha[d]) : T(0);
+    }
+    for (int k = 0; k < 8; ++k) a.hp[k] = T(p->ham.p[k]);
+    return a;
+}
+
+hipError_t launch_stage(const hjx_problem *p, const double *alpha, const void *in, const void *phin,
+                        const void *target, void *out, double dt, double ca, double cb, bool rhs_only,
+                        hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32) {
+        StageArgs<float> a = stage_args<float>(p, alpha);
+        a.phi_in = static_cast<const float *>(in);
+        a.phi_n = static_cast<const float *>(phin);
+        a.target = static_cast<const float *>(target);
+        a.out = static_cast<float *>(out);
+        a.dt = float(dt);
+        a.ca = float(ca);
+        a.cb = float(cb);
+        a.rhs_only = rhs_only;
+        return launch_stage_f32(a, p->scheme.deriv, p->ham.kind, s);
+    }
+    StageArgs<double> a = stage_args<double>(p, alpha);
+    a.phi_in = static_cast<const double *>(in);
+    a.phi_n = static_cast<const double *>(phin);
+    a.target = static_cast<const double *>(target);
+    a.out = static_cast<double *>(out);
+    a.dt = dt;
+    a.ca = ca;
+    a.cb = cb;
+    a.rhs_only = rhs_only;
+    return launch_stage_f64(a, p->scheme.deriv, p->ham.kind, s);
+}
+
+hipError_t launch_copy(const hjx_problem *p, const void *src, void *dst, hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32)
+        return launch_copy_f32(static_cast<const float *>(src), static_cast<float *>(dst), (int)p->total, s);
+    return launch_copy_f64(static_cast<const double *>(src), static_cast<double *>(dst), (int)p->total, s);
+}
+
+// One RK step of size dt: phi (in place) with the problem workspace.
+hipError_t rk_step(const hjx_problem *p, const double *alpha, void *phi, const void *target, double dt,
+                   hipStream_t s)
+{
+    hipError_t e;
+    void *a = p->ws[0], *b = p->ws[1];
+    switch (p->scheme.rk) {
+    case 1:  // odeCFL1: phi + dt L(phi)
+        if ((e = launch_stage(p, alpha, phi, nullptr, target, a, dt, 0.0, 1.0, false, s)) != hipSuccess) return e;
+        return launch_copy(p, a, phi, s);
+    case 2:  // odeCFL2: two Euler moves, then the average with phi^n
+        if ((e = launch_stage(p, alpha, phi, nullptr, nullptr, a, dt, 0.0, 1.0, false, s)) != hipSuccess) return e;
+        return launch_stage(p, alpha, a, phi, target, phi, dt, 0.5, 0.5, false, s);
+    default:  // odeCFL3: Shu-Osher stages with averages 3/4, 1/4 and 1/3, 2/3
+        if ((e = launch_stage(p, alpha, phi, nullptr, nullptr, a, dt, 0.0, 1.0, false, s)) != hipSuccess) return e;
+        if ((e = launch_stage(p, alpha, a, phi, nullptr, b, dt, 0.75, 0.25, false, s)) != hipSuccess) return e;
+        return launch_stage(p, alpha, b, phi, target, phi, dt, 1.0 / 3.0, 2.0 / 3.0, false, s);
+    }
+}
+
+// alpha on the device -> pinned host buffer; synchronises s.
+hjx_status device_alpha(hjx_problem *p, hipStream_t s, double *alpha_host)
+{
+    hipError_t e;
+    if (p->scheme.dtype == HJX_F32) {
+        AlphaArgs<float> a{};
+        a.g = geometry(p);
+        a.tab = tables<float>(p);
+        for (int k = 0; k < 8; ++k) a.hp[k] = float(p->ham.p[k]);
+        a.ham = p->ham.kind;
+        a.partial = p->dalpha + kMaxDim;
+        a.total = (int)p->total;
+        e = launch_alpha_f32(a, p->dalpha, s);
+    } else {
+        AlphaArgs<double> a{};
+        a.g = geometry(p);
+        a.tab = tables<double>(p);
+        for (int k = 0; k < 8; ++k) a.hp[k] = p->ham.p[k];
+        a.ham = p->ham.kind;
+        a.partial = p->dalpha + kMaxDim;
+        a.total = (int)p->total;
+        e = launch_alpha_f64(a, p->dalpha, s);
+    }
+    HIP_TRY(e);
+    HIP_TRY(hipMemcpyAsync(p->hbuf, p->dalpha, sizeof(double) * kMaxDim, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int d = 0; d < kMaxDim; ++d) alpha_host[d] = d < p->grid.dim ? p->hbuf[d] : 0.0;
+    return HJX_OK;
+}
+
+double cfl_dt(const hjx_problem *p, const double *alpha)
+{
+    double rate = 0.0;
+    for (int d = 0; d < p->grid.dim; ++d) rate += alpha[d] / p->dx[d];
+    if (!(rate > 0.0)) return INFINITY;
+    return p->scheme.cfl / rate;
+}
+
+// any NaN/Inf in x?  synchronises s.
+hjx_status any_nonfinite(hjx_problem *p, const void *x, hipStream_t s, bool *bad)
+{
+    HIP_TRY(hipMemsetAsync(p->dflag, 0, sizeof(int), s));
+    if (p->scheme.dtype == HJX_F32)
+        HIP_TRY(launch_nonfinite_f32(static_cast<const float *>(x), (int)p->total, p->dflag, s));
+    else
+        HIP_TRY(launch_nonfinite_f64(static_cast<const double *>(x), (int)p->total, p->dflag, s));
+    int *hflag = reinterpret_cast<int *>(p->hbuf + kMaxDim);
+    HIP_TRY(hipMemcpyAsync(hflag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *bad = *hflag != 0;
+    return HJX_OK;
+}
+
+void release(hjx_problem *p)
+{
+    if (!p) return;
+    if (p->tables) (void)hipFree(p->tables);
+    for (void *w : p->ws)
+        if (w) (void)hipFree(w);
+    if (p->dalpha) (void)hipFree(p->dalpha);
+    if (p->dflag) (void)hipFree(p->dflag);
+    if (p->hbuf) (void)hipHostFree(p->hbuf);
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+}
+
+}  // namespace
+
+// ==================================================================== ABI
+
+extern "C" {
+
+const char *hjx_version(void) { return "0.1.0"; }
+
+const char *hjx_last_error(void) { return g_last_error.c_str(); }
+
+hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham, const hjx_scheme_desc *scheme,
+                              hjx_problem **out)
+{
+    if (!out) return fail(HJX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hjx_status st = validate(grid, ham, scheme);
+    if (st != HJX_OK) return st;
+
+    hjx_problem *p = new (std::nothrow) hjx_problem;
+    if (!p) return fail(HJX_ERR_OOM, "host allocation failed");
+    p->grid = *grid;
+    p->ham = *ham;
+    p->scheme = *scheme;
+    p->total = 1;
+    for (int d = 0; d < grid->dim; ++d) {
+        p->total *= grid->n[d];
+        const double len = grid->gmax[d] - grid->gmin[d];
+        p->dx[d] = ((grid->periodic_mask >> d) & 1u) ? len / (double)grid->n[d] : len / (double)(grid->n[d] - 1);
+    }
+    p->elem = scheme->dtype == HJX_F32 ? sizeof(float) : sizeof(double);
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        release(p);
+        return fail(HJX_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+
+    // per-axis tables: coordinates gmin + j dx, their cosine and sine
+    size_t bytes = 0;
+    for (int d = 0; d < grid->dim; ++d)
+        for (int k = 0; k < 3; ++k) {
+            p->table_off[d][k] = bytes;
+            bytes += ((size_t)grid->n[d] * p->elem + 255) & ~size_t(255);
+        }
+    std::vector<unsigned char> host(bytes);
+    for (int d = 0; d < grid->dim; ++d)
+        for (int64_t j = 0; j < grid->n[d]; ++j) {
+            const double x = grid->gmin[d] + (double)j * p->dx[d];
+            const double v[3] = {x, std::cos(x), std::sin(x)};
+            for (int k = 0; k < 3; ++k) {
+                unsigned char *dst = host.data() + p->table_off[d][k] + (size_t)j * p->elem;
+                if (p->elem == sizeof(float)) {
+                    const float f = (float)v[k];
+                    std::memcpy(dst, &f, sizeof f);
+                } else {
+                    std::memcpy(dst, &v[k], sizeof(double));
+                }
+            }
+        }
+
+    const size_t field = (size_t)p->total * p->elem;
+    const int partials = alpha_blocks((int)p->total);
+    if ((e = hipMalloc(&p->tables, bytes)) != hipSuccess ||
+        (e = hipMemcpy(p->tables, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMalloc(&p->ws[0], field)) != hipSuccess || (e = hipMalloc(&p->ws[1], field)) != hipSuccess ||
+        (e = hipMalloc(&p->dalpha, sizeof(double) * kMaxDim * (1 + (size_t)partials))) != hipSuccess ||
+        (e = hipMalloc(&p->dflag, sizeof(int))) != hipSuccess ||
+        (e = hipHostMalloc(&p->hbuf, sizeof(double) * (kMaxDim + 1), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreate(&p->ev[0])) != hipSuccess || (e = hipEventCreate(&p->ev[1])) != hipSuccess) {
+        release(p);
+        return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "problem allocation: %s",
+                    hipGetErrorString(e));
+    }
+    *out = p;
+    return ok();
+}
+
+hjx_status hjx_problem_destroy(hjx_problem *p)
+{
+    release(p);
+    return ok();
+}
+
+hjx_status hjx_dissipation(hjx_problem *p, double *alpha_out, double *dt_out, void *stream)
+{
+    if (!p || !alpha_out || !dt_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    double alpha[kMaxDim];
+    hjx_status st = device_alpha(p, static_cast<hipStream_t>(stream), alpha);
+    if (st != HJX_OK) return st;
+    for (int d = 0; d < p->grid.dim; ++d) alpha_out[d] = alpha[d];
+    *dt_out = cfl_dt(p, alpha);
+    return ok();
+}
+
+hjx_status hjx_rhs(hjx_problem *p, const void *phi, void *L_out, void *stream)
+{
+    if (!p || !phi || !L_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (phi == L_out) return fail(HJX_ERR_INVALID_ARG, "phi and L_out alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double alpha[kMaxDim];
+    hjx_status st = device_alpha(p, s, alpha);
+    if (st != HJX_OK) return st;
+    HIP_TRY(launch_stage(p, alpha, phi, nullptr, nullptr, L_out, 0.0, 0.0, 1.0, true, s));
+    return ok();
+}
+
+hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, void *stream)
+{
+    if (!p || !phi) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (target == phi) return fail(HJX_ERR_INVALID_ARG, "target aliases phi");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HJX_ERR_INVALID_ARG, "dt %g is not a positive finite step", dt);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double alpha[kMaxDim];
+    hjx_status st = device_alpha(p, s, alpha);
+    if (st != HJX_OK) return st;
+    HIP_TRY(rk_step(p, alpha, phi, target, dt, s));
+    return ok();
+}
+
+hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void *phi_out, double t0, double t1,
+                     void *stream, hjx_stats *stats)
+{
+    if (!p || !phi0 || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (target && target == phi_out) return fail(HJX_ERR_INVALID_ARG, "target aliases phi_out");
+    if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0))
+        return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    bool bad = false;
+    hjx_status st = any_nonfinite(p, phi0, s, &bad);
+    if (st != HJX_OK) return st;
+    if (bad) return fail(HJX_ERR_NONFINITE, "phi0 holds NaN or Inf");
+
+    double alpha[kMaxDim];
+    if ((st = device_alpha(p, s, alpha)) != HJX_OK) return st;
+    const double dt = cfl_dt(p, alpha);
+
+    if (phi_out != phi0) HIP_TRY(launch_copy(p, phi0, phi_out, s));
+    if (stats) HIP_TRY(hipEventRecord(p->ev[0], s));
+
+    // time loop: the step that would reach t1 (within a relative 1e-12) lands on it
+    const double slack = 1e-12 * (std::fabs(t1) > 1.0 ? std::fabs(t1) : 1.0);
+    double t = t0, dt_last = 0.0;
+    int64_t steps = 0;
+    void *cur = phi_out;  // forward Euler alternates between phi_out and the workspace
+    while (t < t1) {
+        double h = dt;
+        bool last = false;
+        if (t + h >= t1 - slack) {
+            h = t1 - t;
+            last = true;
+        }
+        if (p->scheme.rk == 1) {
+            void *nxt = cur == phi_out ? p->ws[0] : phi_out;
+            HIP_TRY(launch_stage(p, alpha, cur, nullptr, target, nxt, h, 0.0, 1.0, false, s));
+            cur = nxt;
+        } else {
+            HIP_TRY(rk_step(p, alpha, phi_out, target, h, s));
+        }
+        ++steps;
+        dt_last = h;
+        t = last ? t1 : t + h;
+    }
+    if (cur != phi_out) HIP_TRY(launch_copy(p, cur, phi_out, s));
+    if (stats) HIP_TRY(hipEventRecord(p->ev[1], s));
+
+    if ((st = any_nonfinite(p, phi_out, s, &bad)) != HJX_OK) return st;
+    if (stats) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+        stats->steps = steps;
+        stats->dt = dt;
+        stats->dt_last = dt_last;
+        stats->t_final = t;
+        for (int d = 0; d < kMaxDim; ++d) stats->alpha[d] = alpha[d];
+        stats->elapsed_ms = ms;
+        // algorithmic bytes per step: every stage reads its input and writes
+        // its output once; stages after the first also read phi^n; the last
+        // stage reads the target.  Halo re-reads are not counted.
+        const double f = (double)p->total * (double)p->elem;
+        const int rk = p->scheme.rk;
+        double per_step = rk == 1 ? 2.0 : (rk == 2 ? 2.0 + 3.0 : 2.0 + 3.0 + 3.0);
+        if (target) per_step += 1.0;
+        stats->alg_bytes = per_step * f * (double)steps;
+    }
+    if (bad) return fail(HJX_ERR_NONFINITE, "the solution holds NaN or Inf");
+    return ok();
+}
+
+}  // extern "C"

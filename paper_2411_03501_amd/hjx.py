@@ -1,0 +1,227 @@
+"""ctypes binding of libhjx (include/hjx.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library.  The functions below carry
+the C entry points' names and arguments; `Problem` wraps a handle for
+convenience.  Arrays are torch tensors on the GPU, contiguous, of the
+problem's dtype; the stream defaults to torch's current stream.  If the
+library is not built this module raises: there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhjx.so")
+
+HJX_OK, HJX_ERR_INVALID_ARG, HJX_ERR_UNSUPPORTED, HJX_ERR_DEVICE, HJX_ERR_NONFINITE, HJX_ERR_OOM = range(6)
+HJX_F32, HJX_F64 = 0, 1
+DERIV = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
+HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2}
+MAX_DIM = 4
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("periodic_mask", ctypes.c_uint32),
+                ("gmin", ctypes.c_double * MAX_DIM), ("gmax", ctypes.c_double * MAX_DIM),
+                ("n", ctypes.c_int64 * MAX_DIM)]
+
+
+class HamDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p", ctypes.c_double * 8)]
+
+
+class SchemeDesc(ctypes.Structure):
+    _fields_ = [("deriv", ctypes.c_int32), ("rk", ctypes.c_int32), ("cfl", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("dt", ctypes.c_double), ("dt_last", ctypes.c_double),
+                ("t_final", ctypes.c_double), ("alpha", ctypes.c_double * MAX_DIM),
+                ("elapsed_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k == "alpha" else getattr(self, k)) for k, _ in self._fields_}
+
+
+class HjxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hjx status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# exported symbols and their signatures (kept in step with include/hjx.h)
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "hjx_version": ([], ctypes.c_char_p),
+    "hjx_last_error": ([], ctypes.c_char_p),
+    "hjx_problem_create": ([ctypes.POINTER(GridDesc), ctypes.POINTER(HamDesc), ctypes.POINTER(SchemeDesc),
+                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hjx_problem_destroy": ([_P], ctypes.c_int),
+    "hjx_dissipation": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    "hjx_rhs": ([_P, _P, _P, _P], ctypes.c_int),
+    "hjx_step": ([_P, _P, _P, ctypes.c_double, _P], ctypes.c_int),
+    "hjx_solve": ([_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(Stats)], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libhjx.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != HJX_OK:
+        raise HjxError(status, lib().hjx_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev(t, dtype, numel, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name}: need a contiguous {dtype} tensor of {numel} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} contiguous={t.is_contiguous()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ C names
+
+def hjx_version():
+    return lib().hjx_version().decode()
+
+
+def hjx_last_error():
+    return lib().hjx_last_error().decode()
+
+
+def hjx_problem_create(grid, ham, scheme):
+    h = ctypes.c_void_p()
+    _check(lib().hjx_problem_create(ctypes.byref(grid), ctypes.byref(ham), ctypes.byref(scheme),
+                                    ctypes.byref(h)))
+    return h
+
+
+def hjx_problem_destroy(handle):
+    _check(lib().hjx_problem_destroy(handle))
+
+
+def hjx_dissipation(handle, dim, stream=None):
+    a = (ctypes.c_double * MAX_DIM)()
+    dt = ctypes.c_double()
+    _check(lib().hjx_dissipation(handle, a, ctypes.byref(dt), _stream(stream)))
+    return [a[d] for d in range(dim)], dt.value
+
+
+def hjx_rhs(handle, phi_ptr, L_ptr, stream=None):
+    _check(lib().hjx_rhs(handle, phi_ptr, L_ptr, _stream(stream)))
+
+
+def hjx_step(handle, phi_ptr, target_ptr, dt, stream=None):
+    _check(lib().hjx_step(handle, phi_ptr, target_ptr, float(dt), _stream(stream)))
+
+
+def hjx_solve(handle, phi0_ptr, target_ptr, out_ptr, t0, t1, stream=None, stats=True):
+    st = Stats() if stats else None
+    _check(lib().hjx_solve(handle, phi0_ptr, target_ptr, out_ptr, float(t0), float(t1), _stream(stream),
+                           ctypes.byref(st) if st is not None else None))
+    return st
+
+
+# ------------------------------------------------------------------ handle wrapper
+
+def descriptors(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3, cfl=0.75,
+                dtype="f64"):
+    g = GridDesc()
+    g.dim = len(n)
+    g.periodic_mask = sum(1 << d for d in periodic)
+    for d in range(len(n)):
+        g.gmin[d], g.gmax[d], g.n[d] = float(gmin[d]), float(gmax[d]), int(n[d])
+    h = HamDesc()
+    h.kind = HAM[ham] if isinstance(ham, str) else int(ham)
+    for k, v in enumerate(params):
+        h.p[k] = float(v)
+    s = SchemeDesc()
+    s.deriv = DERIV[scheme] if isinstance(scheme, str) else int(scheme)
+    s.rk = int(rk)
+    s.cfl = float(cfl)
+    s.dtype = HJX_F32 if dtype in ("f32", torch.float32) else HJX_F64
+    return g, h, s
+
+
+class Problem:
+    """A problem handle: grid, Hamiltonian and scheme (see include/hjx.h)."""
+
+    def __init__(self, gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
+                 cfl=0.75, dtype="f64"):
+        self.shape = tuple(int(v) for v in n)
+        self.dim = len(self.shape)
+        self.numel = 1
+        for v in self.shape:
+            self.numel *= v
+        self.dtype = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
+        self.handle = None
+        self.handle = hjx_problem_create(*descriptors(gmin, gmax, n, periodic, ham, params, scheme, rk, cfl,
+                                                      dtype))
+
+    @classmethod
+    def from_workload(cls, w, dtype=None):
+        return cls(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params, w.scheme, w.rk, w.cfl, dtype or w.dtype)
+
+    def close(self):
+        if self.handle is not None:
+            hjx_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _t(self, t, name):
+        return _dev(t, self.dtype, self.numel, name)
+
+    def dissipation(self, stream=None):
+        return hjx_dissipation(self.handle, self.dim, stream)
+
+    def rhs(self, phi, out=None, stream=None):
+        if out is None:
+            out = torch.empty_like(phi)
+        hjx_rhs(self.handle, self._t(phi, "phi"), self._t(out, "L_out"), stream)
+        return out
+
+    def step(self, phi, dt, target=None, stream=None):
+        """One RK step in place on phi."""
+        hjx_step(self.handle, self._t(phi, "phi"), self._t(target, "target"), dt, stream)
+        return phi
+
+    def solve(self, phi0, t1, t0=0.0, target=None, out=None, stream=None):
+        """Returns (phi(t1), stats dict)."""
+        if out is None:
+            out = torch.empty_like(phi0)
+        st = hjx_solve(self.handle, self._t(phi0, "phi0"), self._t(target, "target"), self._t(out, "phi_out"),
+                       t0, t1, stream)
+        return out, st.as_dict()

@@ -105,7 +105,7 @@ def initial_surface(w):
         phi = np.sqrt(axes[0].reshape(shp0) ** 2 + axes[1].reshape(shp1) ** 2) - w.radius
     else:
         raise ValueError(w.surface)
-    return np.ascontiguousarray(np.broadcast_to(phi, w.n), dtype=np.float64)
+    return np.array(np.broadcast_to(phi, w.n), dtype=np.float64, order="C", copy=True)
 
 
 def smooth_field(shape, seed, modes=4, amplitude=1.0):

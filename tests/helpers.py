@@ -1,0 +1,78 @@
+"""Shared test helpers: problem construction on both sides from one seeded
+workload description, and the comparison rules."""
+import numpy as np
+
+import oracle as O
+from paper_2411_03501_amd import inputs
+
+# FP64: max-abs difference to the oracle; FP32: relative to the oracle's range
+TOL_F64 = 1e-10
+TOL_F32_REL = 1e-4
+
+
+def oracle_problem(w, **over):
+    kw = dict(gmin=w.gmin, gmax=w.gmax, n=w.n, periodic=w.periodic, ham=w.ham, params=w.params,
+              scheme=w.scheme, rk=w.rk, cfl=w.cfl)
+    kw.update(over)
+    return O.make_problem(**kw)
+
+
+def gpu_problem(w, dtype=None, **over):
+    from paper_2411_03501_amd import hjx
+    kw = dict(gmin=w.gmin, gmax=w.gmax, n=w.n, periodic=w.periodic, ham=w.ham, params=w.params,
+              scheme=w.scheme, rk=w.rk, cfl=w.cfl, dtype=dtype or w.dtype)
+    kw.update(over)
+    return hjx.Problem(**kw)
+
+
+def to_dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def to_host(t):
+    return t.detach().to("cpu", dtype=__import__("torch").float64).numpy()
+
+
+def near_zero_mask(ref, periodic=(), width=2):
+    """Nodes with a node of the opposite sign (or a zero) of `ref` within
+    `width` cells in the max-norm: separable min/max filters, wrapping on
+    periodic axes and clipping elsewhere."""
+    lo = ref.copy()
+    hi = ref.copy()
+    for d in range(ref.ndim):
+        n = ref.shape[d]
+        new_lo = lo.copy()
+        new_hi = hi.copy()
+        for k in range(-width, width + 1):
+            if k == 0:
+                continue
+            if d in periodic:
+                sl = np.roll(lo, -k, axis=d), np.roll(hi, -k, axis=d)
+            else:
+                idx = np.clip(np.arange(n) + k, 0, n - 1)
+                sl = np.take(lo, idx, axis=d), np.take(hi, idx, axis=d)
+            new_lo = np.minimum(new_lo, sl[0])
+            new_hi = np.maximum(new_hi, sl[1])
+        lo, hi = new_lo, new_hi
+    # some neighbour has the other sign (or is zero)
+    return ((ref > 0) & (lo <= 0)) | ((ref < 0) & (hi >= 0)) | (ref == 0)
+
+
+def assert_close(got, ref, dtype, periodic=(), what=""):
+    """FP64: |got - ref| <= 1e-10.  FP32: |got - ref| <= 1e-4 * range(ref) and
+    sign(got) == sign(ref) beyond two cells from the zero level set."""
+    err = np.abs(got - ref).max()
+    if dtype == "f64":
+        assert err <= TOL_F64, f"{what}: max |gpu - oracle| = {err:.3e} > {TOL_F64}"
+        return err
+    rng = ref.max() - ref.min()
+    assert err <= TOL_F32_REL * rng, f"{what}: max |gpu - oracle| = {err:.3e} > 1e-4 * range {rng:.3e}"
+    far = ~near_zero_mask(ref, periodic)
+    bad = far & (np.sign(got) != np.sign(ref))
+    assert not bad.any(), f"{what}: {bad.sum()} sign disagreements beyond two cells of the zero set"
+    return err
+
+
+def workload_phi0(w):
+    return inputs.initial_surface(w)

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.  FP64 within 1e-10 max-abs; FP32 within 1e-4 of the
+oracle's range with sign agreement beyond two cells of the zero level set."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_03501_amd import inputs
+from helpers import assert_close, gpu_problem, oracle_problem, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - only on a GPU machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_03501_amd import hjx  # noqa: E402
+
+TDT = {"f32": torch.float32, "f64": torch.float64}
+SCHEMES = ["first", "eno2", "eno3", "weno5"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _w(name, gmin, gmax, n, periodic=(), ham="normal", params=(1.3,), scheme="weno5", rk=3):
+    return inputs.Workload(name, tuple(gmin), tuple(gmax), tuple(n), tuple(periodic), ham, tuple(params), scheme,
+                           rk)
+
+
+# small ragged grids: tiles are 256 nodes, so each spans several tiles plus a tail
+CASES = {
+    "normal1d": _w("normal1d", [-1], [2], [37], params=(1.3,)),
+    "normal1d_per": _w("normal1d_per", [0], [1], [29], periodic=(0,), params=(-0.7,)),
+    "normal2d": _w("normal2d", [-1, -2], [1, 1], [13, 29], params=(0.9,)),
+    "normal3d": _w("normal3d", [-1, -1, 0], [1, 2, 1], [11, 17, 23], periodic=(1,), params=(1.1,)),
+    "normal4d": _w("normal4d", [0, 0, 0, 0], [1, 1, 1, 1], [7, 9, 11, 13], periodic=(0, 3), params=(0.6,)),
+    "dubins3": _w("dubins3", [-6, -10, 0], [20, 10, 2 * math.pi], [11, 13, 17], periodic=(2,), ham="dubins3_pe",
+                  params=(5, 4, 1, 0.7)),
+    "car4": _w("car4", [-5, -5, 0, 0], [5, 5, 2 * math.pi, 2], [7, 9, 10, 11], periodic=(2,), ham="dubins4",
+               params=(1, 0.8)),
+}
+
+
+def _field(w, kind, seed):
+    if kind == "smooth":
+        return inputs.smooth_field(w.n, seed, amplitude=1.5)
+    return inputs.rough_field(w.n, seed)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rhs_parity(case, scheme, dtype):
+    w = CASES[case].with_(scheme=scheme)
+    kinds = ["smooth", "rough"] if (dtype == "f64" or scheme in ("first", "weno5")) else ["smooth"]
+    for kind in kinds:
+        say(f"rhs {case} {scheme} {dtype} {kind} n={w.n}")
+        phi = _field(w, kind, seed=101)
+        ref = O.rhs(oracle_problem(w), phi)
+        P = gpu_problem(w, dtype)
+        got = to_host(P.rhs(to_dev(phi, TDT[dtype])))
+        torch.cuda.synchronize()
+        scale = max(1.0, np.abs(ref).max())
+        tol = 1e-12 if dtype == "f64" else 1e-4
+        err = np.abs(got - ref).max()
+        assert err <= tol * scale, f"{case} {scheme} {dtype} {kind}: {err:.3e} vs scale {scale:.3e}"
+
+
+@pytest.mark.parametrize("case", ["normal2d", "normal4d", "dubins3", "car4"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dissipation_parity(case, dtype):
+    w = CASES[case]
+    alpha_ref = O.alpha(oracle_problem(w))
+    dt_ref = O.cfl_dt(oracle_problem(w))
+    alpha, dt = gpu_problem(w, dtype).dissipation()
+    tol = 1e-15 if dtype == "f64" else 1e-6
+    assert np.allclose(alpha, alpha_ref, rtol=tol, atol=0), (alpha, alpha_ref)
+    assert abs(dt - dt_ref) <= tol * 4 * dt_ref
+
+
+@pytest.mark.parametrize("case", ["normal2d", "normal3d", "dubins3", "car4"])
+@pytest.mark.parametrize("rk", [1, 2, 3])
+@pytest.mark.parametrize("with_target", [False, True])
+def test_step_parity_f64(case, rk, with_target):
+    w = CASES[case].with_(rk=rk)
+    phi = inputs.smooth_field(w.n, 7, amplitude=2.0)
+    tgt = inputs.smooth_field(w.n, 8, amplitude=2.0) if with_target else None
+    dt = 0.9 * O.cfl_dt(oracle_problem(w))
+    say(f"step {case} rk{rk} target={with_target} dt={dt:.4g}")
+    ref = O.step(oracle_problem(w), phi, dt, target=tgt)
+    P = gpu_problem(w, "f64")
+    dphi = to_dev(phi, torch.float64)
+    P.step(dphi, dt, target=None if tgt is None else to_dev(tgt, torch.float64))
+    assert_close(to_host(dphi), ref, "f64", w.periodic, what=f"step {case} rk{rk}")
+
+
+# whole solves at reduced sizes (the oracle finishes in seconds)
+SOLVES = [
+    ("normal2d_full", inputs.NORMAL2D, None),
+    ("dubins3d_31", inputs.DUBINS3D.with_(n=(31, 29, 27)), None),
+    ("dubins3d_31_eno3_rk2", inputs.DUBINS3D.with_(n=(25, 23, 21), scheme="eno3", rk=2, t1=1.0), None),
+    ("dubins3d_31_eno2_rk1", inputs.DUBINS3D.with_(n=(25, 23, 21), scheme="eno2", rk=1, t1=0.5), None),
+    ("car4d_15", inputs.CAR4D.with_(n=(15, 15, 16, 11)), None),
+]
+
+
+@pytest.mark.parametrize("name,w,_", SOLVES, ids=[s[0] for s in SOLVES])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_solve_parity(name, w, _, dtype):
+    if dtype == "f32" and w.scheme in ("eno2", "eno3"):
+        pytest.skip("ENO stencil choices on near-ties differ between precisions; FP64 covers ENO")
+    say(f"solve {name} {dtype} n={w.n} t1={w.t1}")
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+    ref, steps, dt0 = O.solve(Po, phi0, w.t1, target=phi0 if w.with_target else None)
+    P = gpu_problem(w, dtype)
+    d0 = to_dev(phi0, TDT[dtype])
+    out, st = P.solve(d0, w.t1, target=d0 if w.with_target else None)
+    assert st["steps"] == steps
+    assert abs(st["dt"] - dt0) <= 1e-12 * dt0 if dtype == "f64" else abs(st["dt"] - dt0) <= 1e-5 * dt0
+    assert st["t_final"] == w.t1
+    err = assert_close(to_host(out), ref, dtype, w.periodic, what=f"solve {name}")
+    say(f"  steps {steps} max err {err:.3e}")
+
+
+@pytest.mark.parametrize("wname", ["dubins3d", "car4d"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_single_step(wname, dtype):
+    """One RK3 step at the full workload size, in the bench's launch setup."""
+    w = inputs.WORKLOADS[wname]
+    if wname == "car4d" and dtype == "f64":
+        pytest.skip("car4d is an FP32 workload")
+    say(f"full-size step {wname} {dtype} n={w.n}")
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+    dt = O.cfl_dt(Po)
+    O.set_threads(16)
+    ref = O.step(Po, phi0, dt, target=phi0 if w.with_target else None)
+    P = gpu_problem(w, dtype)
+    d = to_dev(phi0, TDT[dtype])
+    t = to_dev(phi0, TDT[dtype]) if w.with_target else None
+    P.step(d, dt, target=t)
+    assert_close(to_host(d), ref, dtype, w.periodic, what=f"full {wname}")
+
+
+def test_zero_span_copies_input():
+    w = CASES["dubins3"]
+    phi = inputs.smooth_field(w.n, 3)
+    P = gpu_problem(w, "f64")
+    d = to_dev(phi, torch.float64)
+    out, st = P.solve(d, 0.5, t0=0.5)
+    assert st["steps"] == 0
+    assert np.array_equal(to_host(out), phi)
+
+
+def test_no_motion_takes_one_step_to_the_horizon():
+    w = CASES["normal2d"].with_(params=(0.0,))
+    phi = inputs.smooth_field(w.n, 4)
+    out, st = gpu_problem(w, "f64").solve(to_dev(phi, torch.float64), 0.7)
+    assert st["steps"] == 1 and math.isinf(st["dt"]) and st["dt_last"] == 0.7
+    # L = 0, so the RK3 averages return phi up to their rounding
+    assert np.abs(to_host(out) - phi).max() <= 4e-16 * np.abs(phi).max()
+
+
+def test_smallest_grids():
+    for w in (_w("tiny1", [0], [1], [3], scheme="weno5"), _w("tiny2p", [0, 0], [1, 1], [3, 3], periodic=(0, 1)),
+              _w("tiny3", [0, 0, 0], [1, 1, 1], [3, 4, 3], scheme="eno3")):
+        phi = inputs.rough_field(w.n, 9)
+        ref = O.rhs(oracle_problem(w), phi)
+        got = to_host(gpu_problem(w, "f64").rhs(to_dev(phi, torch.float64)))
+        assert np.abs(got - ref).max() <= 1e-12 * max(1, np.abs(ref).max()), w.name
+
+
+def test_in_place_solve_and_target_rules():
+    w = CASES["dubins3"]
+    phi = inputs.smooth_field(w.n, 5)
+    P = gpu_problem(w, "f64")
+    ref, _, _ = O.solve(oracle_problem(w), phi, 0.3, target=phi)
+    d = to_dev(phi, torch.float64)
+    tgt = d.clone()
+    P.solve(d, 0.3, target=tgt, out=d)           # phi_out == phi0 is allowed
+    assert_close(to_host(d), ref, "f64", w.periodic, what="in place")
+    with pytest.raises(hjx.HjxError) as e:        # target == phi_out is not
+        P.solve(d, 0.3, target=d, out=d)
+    assert e.value.status == hjx.HJX_ERR_INVALID_ARG
+
+
+def test_nonfinite_input_is_reported():
+    w = CASES["normal2d"]
+    phi = inputs.smooth_field(w.n, 6)
+    phi[3, 4] = np.nan
+    with pytest.raises(hjx.HjxError) as e:
+        gpu_problem(w, "f64").solve(to_dev(phi, torch.float64), 0.1)
+    assert e.value.status == hjx.HJX_ERR_NONFINITE
+
+
+def test_binding_rejects_wrong_dtype_and_shape():
+    w = CASES["normal2d"]
+    P = gpu_problem(w, "f64")
+    with pytest.raises(ValueError):
+        P.rhs(torch.zeros(w.n, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        P.rhs(torch.zeros((3, 3), dtype=torch.float64, device="cuda"))
+
+
+def test_repeat_runs_are_bitwise_identical():
+    w = inputs.DUBINS3D.with_(n=(21, 19, 17), dtype="f32")
+    phi0 = to_dev(inputs.initial_surface(w), torch.float32)
+    P = gpu_problem(w)
+    a, _ = P.solve(phi0, 0.5, target=phi0)
+    b, _ = P.solve(phi0, 0.5, target=phi0)
+    assert torch.equal(a, b)
