@@ -160,6 +160,36 @@ hjx_status hjx_rhs(hjx_problem *p, const void *phi, void *L_out, void *stream);
  * alias phi.  dt > 0.  Asynchronous on `stream`. */
 hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, void *stream);
 
+/* Launch shape of the stage kernel (no counterpart in the paper, whose
+ * stages are whole-array expressions).  Two variants compute the same
+ * arithmetic, so results are bit-for-bit the same for every shape:
+ *   HJX_TILE_PLANE_MARCH: a block covers tx nodes of the fastest axis by ty
+ *     nodes of the second-fastest (ty = 1 when dim = 1), stages that plane
+ *     tile with its halo in LDS, evaluates each stencil interval once and
+ *     marches over `march` nodes of the third axis (ignored when dim < 3);
+ *     1 <= tx*ty <= 256;
+ *   HJX_TILE_DIRECT: one thread per node, stencils gathered through the
+ *     caches (tx, ty, march ignored); arrays must be under 4 GiB, else
+ *     HJX_ERR_UNSUPPORTED.
+ * hjx_problem_create picks a default; hjx_tune may replace it. */
+#define HJX_TILE_PLANE_MARCH 0
+#define HJX_TILE_DIRECT 1
+hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int32_t ty, int32_t march);
+hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t *tx, int32_t *ty,
+                                int32_t *march);
+
+/* Autotuner: times the stage kernel on this problem for a set of candidate
+ * launch shapes (row widths that split the fastest axis evenly, 64..256
+ * threads per block, march lengths 1..32) and keeps the fastest with
+ * hjx_problem_set_tile.  Each candidate is timed on whole RK steps taken
+ * from a copy of phi with phi as the target, as in a solve.  phi: device
+ * array of the problem's size and dtype, read only.  reps: timed steps per
+ * candidate (>= 1).  best_us (host, optional): the winner's mean time per
+ * stage launch.  Allocates one temporary array of the problem's size for the
+ * duration of the call.  Results do not depend on the choice.  Synchronises
+ * `stream`. */
+hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream, double *best_us);
+
 /* Solve from t0 to t1 (Listing 3 odeCFLx(schemeFunc, tspan, y0, ...)):
  * steps of the CFL size dt, the one that would reach t1 (or come within
  * 1e-12 max(1,|t1|) of it) clamped to land on t1.  phi0: initial data;

@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -73,6 +75,7 @@ struct hjx_problem {
     int *dflag = nullptr;      // device: non-finite flag
     double *hbuf = nullptr;    // pinned host: alpha[kMaxDim], flag
     hipEvent_t ev[2] = {nullptr, nullptr};
+    Tile tile{};               // stage-kernel launch shape
 };
 
 namespace {
@@ -156,11 +159,49 @@ hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_sch
 
 // ---------------------------------------------------------------- launches
 
+// Default launch shape, from autotuner sweeps on MI355X: small grids (a few
+// million nodes) do best with near-square plane tiles of ~256 threads and a
+// march of 2 (many waves in flight); large grids with whole rows of the
+// fastest axis (up to 128 nodes) and a march of 8 (fewer halo re-reads).
+// hjx_tune refines the choice per problem.
+// the direct variant addresses arrays through 32-bit byte offsets
+bool direct_ok(const GridGeom &g, size_t elem)
+{
+    uint64_t total = 1;
+    for (int d = 0; d < g.dim; ++d) total *= (uint64_t)g.n[d];
+    return total * elem < (uint64_t(1) << 32);
+}
+
+Tile default_tile(const GridGeom &g, size_t elem)
+{
+    Tile t{};
+    const int nf = g.n[g.dim - 1];
+    const int nm = g.dim >= 2 ? g.n[g.dim - 2] : 1;
+    long total = 1;
+    for (int d = 0; d < g.dim; ++d) total *= g.n[d];
+    const bool large = total >= (8l << 20);
+    t.variant = large || !direct_ok(g, elem) ? kVariantPlaneMarch : kVariantDirect;
+    const int width = large ? 128 : 16;
+    const int pieces = (nf + width - 1) / width;
+    t.tx = std::min((nf + pieces - 1) / pieces, 256);
+    t.ty = g.dim >= 2 ? std::max(1, std::min(256 / t.tx, nm)) : 1;
+    t.march = 1;
+    if (g.dim >= 3) {
+        const int nk = g.n[g.dim - 3];
+        const long outer = g.dim == 4 ? g.n[0] : 1;
+        int m = std::min(large ? 8 : 2, nk);
+        while ((long)((nk + m - 1) / m) * outer > 65535) m *= 2;
+        t.march = m;
+    }
+    return t;
+}
+
 template <typename T>
 StageArgs<T> stage_args(const hjx_problem *p, const double *alpha)
 {
     StageArgs<T> a{};
     a.g = geometry(p);
+    a.tile = p->tile;
     a.tab = tables<T>(p);
     for (int d = 0; d < kMaxDim; ++d) {
         a.inv_dx[d] = d < p->grid.dim ? T(1.0 / p->dx[d]) : T(0);
@@ -366,6 +407,7 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
         return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "problem allocation: %s",
                     hipGetErrorString(e));
     }
+    p->tile = default_tile(geometry(p), p->elem);
     *out = p;
     return ok();
 }
@@ -373,6 +415,116 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
 hjx_status hjx_problem_destroy(hjx_problem *p)
 {
     release(p);
+    return ok();
+}
+
+hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int32_t ty, int32_t march)
+{
+    if (!p) return fail(HJX_ERR_INVALID_ARG, "NULL problem");
+    const GridGeom g = geometry(p);
+    if (variant == HJX_TILE_DIRECT) {
+        if (!direct_ok(g, p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the direct variant needs arrays under 4 GiB");
+        p->tile = Tile{256, 1, 1, kVariantDirect};
+        return ok();
+    }
+    if (variant != HJX_TILE_PLANE_MARCH) return fail(HJX_ERR_INVALID_ARG, "unknown tile variant %d", variant);
+    if (tx < 1 || ty < 1 || (int64_t)tx * ty > 256)
+        return fail(HJX_ERR_INVALID_ARG, "tile %d x %d: need 1 <= tx*ty <= 256", tx, ty);
+    if (g.dim == 1 && ty != 1) return fail(HJX_ERR_INVALID_ARG, "a 1-D grid needs ty = 1");
+    if (march < 1) return fail(HJX_ERR_INVALID_ARG, "march %d < 1", march);
+    if (g.dim >= 3) {
+        const int64_t gy = (int64_t)((g.n[g.dim - 3] + march - 1) / march) * (g.dim == 4 ? g.n[0] : 1);
+        if (gy > 65535) return fail(HJX_ERR_INVALID_ARG, "march %d leaves %lld block rows (> 65535)", march, (long long)gy);
+    }
+    p->tile = Tile{tx, ty, g.dim >= 3 ? march : 1, kVariantPlaneMarch};
+    return ok();
+}
+
+hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t *tx, int32_t *ty, int32_t *march)
+{
+    if (!p || !variant || !tx || !ty || !march) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    *variant = p->tile.variant == kVariantDirect ? HJX_TILE_DIRECT : HJX_TILE_PLANE_MARCH;
+    *tx = p->tile.tx;
+    *ty = p->tile.ty;
+    *march = p->tile.march;
+    return ok();
+}
+
+hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream, double *best_us)
+{
+    if (!p || !phi) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps %d < 1", reps);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double alpha[kMaxDim];
+    hjx_status st = device_alpha(p, s, alpha);
+    if (st != HJX_OK) return st;
+    const double dt = cfl_dt(p, alpha);
+    const double h = std::isfinite(dt) ? dt : 1.0;
+    const GridGeom g = geometry(p);
+    const int nf = g.n[g.dim - 1], nm = g.dim >= 2 ? g.n[g.dim - 2] : 1;
+    const int nk = g.dim >= 3 ? g.n[g.dim - 3] : 1;
+    const int outer = g.dim == 4 ? g.n[0] : 1;
+
+    std::vector<Tile> cands;
+    for (int pieces = 1; pieces <= 8; ++pieces) {
+        const int tx = (nf + pieces - 1) / pieces;
+        if (tx > 256 || (pieces > 1 && tx < 8)) continue;
+        for (int threads : {64, 128, 192, 256}) {
+            int ty = g.dim >= 2 ? std::max(1, std::min(threads / tx, nm)) : 1;
+            if (tx * ty > 256) continue;
+            for (int m : {1, 2, 4, 8, 16, 32}) {
+                if (g.dim < 3 && m > 1) break;
+                if (m > nk && m > 1) break;
+                if ((long)((nk + m - 1) / m) * outer > 65535) continue;
+                const Tile t{tx, ty, m, kVariantPlaneMarch};
+                bool seen = false;
+                for (const Tile &c : cands) seen |= c.tx == t.tx && c.ty == t.ty && c.march == t.march;
+                if (!seen) cands.push_back(t);
+            }
+        }
+    }
+    if (direct_ok(g, p->elem)) cands.push_back(Tile{256, 1, 1, kVariantDirect});
+    const char *env = std::getenv("HJX_TUNE_VERBOSE");
+    const bool verbose = env && env[0] && env[0] != '0';
+    const Tile keep = p->tile;
+    Tile best = keep;
+    float best_ms = INFINITY;
+    // time whole RK steps (all stages, phi itself as the target) on a copy of
+    // phi, as a solve runs them
+    void *work = nullptr;
+    HIP_TRY(hipMalloc(&work, (size_t)p->total * p->elem));
+    auto timed = [&](float *ms) -> hipError_t {
+        hipError_t e;
+        if ((e = launch_copy(p, phi, work, s)) != hipSuccess) return e;
+        if ((e = rk_step(p, alpha, work, phi, h, s)) != hipSuccess) return e;  // untimed
+        if ((e = hipEventRecord(p->ev[0], s)) != hipSuccess) return e;
+        for (int r = 0; r < reps; ++r)
+            if ((e = rk_step(p, alpha, work, phi, h, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(p->ev[1], s)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(p->ev[1])) != hipSuccess) return e;
+        return hipEventElapsedTime(ms, p->ev[0], p->ev[1]);
+    };
+    for (const Tile &t : cands) {
+        p->tile = t;
+        float ms = 0.f;
+        const hipError_t e = timed(&ms);
+        if (e != hipSuccess) {
+            (void)hipFree(work);
+            p->tile = keep;
+            return fail(HJX_ERR_DEVICE, "hjx_tune: %s", hipGetErrorString(e));
+        }
+        ms /= (float)p->scheme.rk;  // per stage launch
+        if (verbose)
+            fprintf(stderr, "hjx_tune: %s tile %3d x %3d march %2d: %9.2f us\n",
+                    t.variant == kVariantDirect ? "direct" : "plane ", t.tx, t.ty, t.march, (double)ms * 1e3 / reps);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    HIP_TRY(hipFree(work));
+    p->tile = best;
+    if (best_us) *best_us = (double)best_ms * 1e3 / reps;
     return ok();
 }
 

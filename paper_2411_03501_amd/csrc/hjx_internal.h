@@ -28,6 +28,21 @@ struct GridGeom {
     int slow;           // product of the remaining axes
 };
 
+// Launch shape of the stage kernel.  A block covers tx nodes of the fastest
+// axis by ty nodes of the second-fastest ("plane tile", staged in LDS with its
+// halo) and marches over `march` consecutive nodes of the third-fastest axis
+// (dim >= 3).  tx * ty <= 256.
+struct Tile {
+    int tx, ty, march;
+    int variant;  // kVariantPlaneMarch or kVariantDirect
+};
+
+// Stage-kernel variants (the same arithmetic, bit for bit):
+//   plane-march: the tiling above, each interval evaluated once and shared;
+//   direct: one thread per node, gathering its stencils through the caches
+//           and evaluating both halves at the node (no LDS, no barriers).
+enum : int { kVariantPlaneMarch = 0, kVariantDirect = 1 };
+
 // One fused stage: out = ca * phi_n + cb * (phi_in + dt * L(phi_in)),
 // then out = min(out, target) if target != nullptr; with rhs_only the
 // kernel writes L(phi_in) itself.
@@ -45,6 +60,7 @@ struct StageArgs {
     T hp[8];
     T dt, ca, cb;
     int rhs_only;
+    Tile tile;
 };
 
 // Dissipation reduction over all nodes (first pass: one partial per block).
@@ -57,6 +73,13 @@ struct AlphaArgs {
     double *partial;  // [blocks][kMaxDim]
     int total;
 };
+
+// LDS of one stage block: the staged plane with a 3-node halo on both plane
+// axes, and the right-biased derivatives exchanged along each plane axis.
+inline size_t stage_lds_bytes(const Tile &t, size_t elem)
+{
+    return elem * ((size_t)(t.ty + 6) * (t.tx + 6) + (size_t)t.ty * (t.tx + 1) + (size_t)(t.ty + 1) * t.tx);
+}
 
 enum : int { kSchemeFirst = 1, kSchemeEno2 = 2, kSchemeEno3 = 3, kSchemeWeno5 = 5 };
 enum : int { kHamNormal = 0, kHamDubins3 = 1, kHamDubins4 = 2 };

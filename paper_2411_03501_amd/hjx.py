@@ -64,6 +64,9 @@ SIGNATURES = {
     "hjx_dissipation": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "hjx_rhs": ([_P, _P, _P, _P], ctypes.c_int),
     "hjx_step": ([_P, _P, _P, ctypes.c_double, _P], ctypes.c_int),
+    "hjx_problem_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "hjx_problem_get_tile": ([_P] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
+    "hjx_tune": ([_P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hjx_solve": ([_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(Stats)], ctypes.c_int),
 }
 
@@ -126,6 +129,26 @@ def hjx_problem_create(grid, ham, scheme):
 
 def hjx_problem_destroy(handle):
     _check(lib().hjx_problem_destroy(handle))
+
+
+TILE_PLANE_MARCH, TILE_DIRECT = 0, 1
+
+
+def hjx_problem_set_tile(handle, variant, tx, ty, march):
+    _check(lib().hjx_problem_set_tile(handle, int(variant), int(tx), int(ty), int(march)))
+
+
+def hjx_problem_get_tile(handle):
+    """(variant, tx, ty, march)"""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().hjx_problem_get_tile(handle, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def hjx_tune(handle, phi_ptr, reps=5, stream=None):
+    us = ctypes.c_double()
+    _check(lib().hjx_tune(handle, phi_ptr, int(reps), _stream(stream), ctypes.byref(us)))
+    return us.value
 
 
 def hjx_dissipation(handle, dim, stream=None):
@@ -203,6 +226,24 @@ class Problem:
 
     def _t(self, t, name):
         return _dev(t, self.dtype, self.numel, name)
+
+    @property
+    def tile(self):
+        """(variant, tx, ty, march); variant 0 = plane-march, 1 = direct."""
+        return hjx_problem_get_tile(self.handle)
+
+    @tile.setter
+    def tile(self, shape):
+        """(variant, tx, ty, march), or (tx, ty, march) for the plane-march variant."""
+        if len(shape) == 3:
+            shape = (TILE_PLANE_MARCH,) + tuple(shape)
+        hjx_problem_set_tile(self.handle, *shape)
+
+    def tune(self, phi, reps=5, stream=None):
+        """Pick the fastest stage-kernel launch shape for this problem; returns
+        (tile, mean launch time in us)."""
+        us = hjx_tune(self.handle, self._t(phi, "phi"), reps, stream)
+        return self.tile, us
 
     def dissipation(self, stream=None):
         return hjx_dissipation(self.handle, self.dim, stream)

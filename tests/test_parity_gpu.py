@@ -216,3 +216,58 @@ def test_repeat_runs_are_bitwise_identical():
     a, _ = P.solve(phi0, 0.5, target=phi0)
     b, _ = P.solve(phi0, 0.5, target=phi0)
     assert torch.equal(a, b)
+
+
+TILES = [(8, 8, 1), (16, 4, 3), (13, 7, 2), (32, 8, 5), (64, 4, 16), (5, 3, 1), (1, 1, 1)]
+
+
+@pytest.mark.parametrize("case", ["normal1d", "normal2d", "normal3d", "normal4d", "dubins3", "car4"])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_results_do_not_depend_on_the_tile(case, scheme):
+    """Every interval is evaluated by the same arithmetic whatever the launch
+    shape: results must agree bit for bit (an LDS race would show here)."""
+    w = CASES[case].with_(scheme=scheme)
+    phi = inputs.rough_field(w.n, 12)
+    tgt = inputs.rough_field(w.n, 13)
+    dt = 0.5 * O.cfl_dt(oracle_problem(w))
+    ref_rhs = ref_step = None
+    for dtype in ("f64", "f32"):
+        P = gpu_problem(w, dtype)
+        default = P.tile
+        for tile in [default, (1, 256, 1, 1)] + [(0,) + t for t in TILES]:
+            if w.dim == 1 and tile[0] == 0:
+                tile = (0, tile[1], 1, 1)
+            P.tile = tile
+            assert P.tile[:3] == tile[:3] or tile[0] == 1
+            L = P.rhs(to_dev(phi, TDT[dtype]))
+            d = to_dev(phi, TDT[dtype])
+            P.step(d, dt, target=to_dev(tgt, TDT[dtype]))
+            L, d = L.cpu(), d.cpu()
+            if tile == default:
+                ref_rhs, ref_step = L, d
+            else:
+                assert torch.equal(L, ref_rhs), f"rhs differs for tile {tile} ({dtype})"
+                assert torch.equal(d, ref_step), f"step differs for tile {tile} ({dtype})"
+
+
+def test_tile_validation():
+    P = gpu_problem(CASES["dubins3"], "f32")
+    for bad in [(0, 4, 1), (17, 16, 1), (8, 8, 0)]:
+        with pytest.raises(hjx.HjxError) as e:
+            P.tile = bad
+        assert e.value.status == hjx.HJX_ERR_INVALID_ARG
+    P1 = gpu_problem(CASES["normal1d"], "f32")
+    with pytest.raises(hjx.HjxError):
+        P1.tile = (8, 2, 1)
+
+
+def test_autotuner_picks_a_valid_tile_and_keeps_results():
+    w = inputs.DUBINS3D.with_(n=(23, 21, 19))
+    phi0 = inputs.initial_surface(w)
+    P = gpu_problem(w, "f32")
+    d = to_dev(phi0, torch.float32)
+    before, _ = P.solve(d, 0.3, target=d)
+    tile, us = P.tune(d, reps=2)
+    assert us > 0 and tile[1] * tile[2] <= 256
+    after, _ = P.solve(d, 0.3, target=d)
+    assert torch.equal(before, after)
