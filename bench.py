@@ -76,6 +76,81 @@ def run_gpu(w, dtype, steps, warmup):
     return elapsed, st, loop_ms
 
 
+def run_adjoint(w, reps=2):
+    """Gradient workload: forward solve (plain) vs backward (segment replay +
+    reverse sweep, checkpoint every 8 steps) of the smoothed-volume loss,
+    and a central-difference check of dL/dv_e and of dL/dphi0 along a smooth
+    direction on the same GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2411_03501_amd import hjx, inputs
+
+    P = hjx.Problem.from_workload(w, "f32")
+    phi0 = torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=torch.float32)
+    P.tune(phi0, reps=2)
+    dx = [(w.gmax[d] - w.gmin[d]) / (w.n[d] if d in w.periodic else w.n[d] - 1) for d in range(w.dim)]
+    eps = 1.5 * max(dx[0], dx[1])
+    out = torch.empty_like(phi0)
+    P.solve(phi0, w.t1, target=phi0, out=out)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.solve(phi0, w.t1, target=phi0, out=out)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / reps
+    tape = P.tape(w.t1, ckpt_every=8)
+    tape.solve(phi0, target=phi0, out=out)
+    loss, g = P.loss_volume(out, eps)
+    tape.adjoint(g)  # warm-up
+    torch.cuda.synchronize()
+    bwd_times = []
+    for _ in range(reps):
+        tape.solve(phi0, target=phi0, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, g = P.loss_volume(out, eps)
+        g0, gt, dp = tape.adjoint(g)
+        torch.cuda.synchronize()
+        bwd_times.append(time.perf_counter() - t0)
+    bwd = min(bwd_times)
+    log(f"  adjoint: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms")
+    grad_phi0 = (g0 + gt).double()
+
+    # central differences of FP64 solves with small steps (the loss is only
+    # piecewise smooth: a large step crosses changes of the step count, and
+    # the theta-independent surface sits on a kink of WENO5 for directions
+    # that vary with theta, so the phi0 direction here does not)
+    phi64 = phi0.double()
+
+    def loss_at(params, f0):
+        Q = hjx.Problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, params, w.scheme, w.rk, w.cfl, "f64")
+        o, _ = Q.solve(f0, w.t1, target=f0)
+        v = Q.loss_volume(o, eps, grad=False)
+        Q.close()
+        return v
+
+    h = 1e-5 * w.params[0]
+    pp = list(w.params)
+    pm = list(w.params)
+    pp[0] += h
+    pm[0] -= h
+    fd_ve = (loss_at(pp, phi64) - loss_at(pm, phi64)) / (2 * h)
+    d2 = inputs.smooth_field(w.n[:2], 5)
+    delta = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(d2[:, :, None], w.n))).to("cuda")
+    hd = 1e-5
+    fd_phi = (loss_at(w.params, phi64 + hd * delta) - loss_at(w.params, phi64 - hd * delta)) / (2 * hd)
+    adj_phi = float((grad_phi0 * delta).sum())
+    tape.close()
+    P.close()
+    return {"workload": f"{w.name}: {'x'.join(map(str, w.n))} FP32, horizon {w.t1}, checkpoint every 8 steps",
+            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "adjoint_over_forward": bwd / fwd,
+            "loss": loss, "dL_dve_adjoint": dp[0], "dL_dve_central_diff": fd_ve,
+            "dL_dphi0_dir_adjoint": adj_phi, "dL_dphi0_dir_central_diff": fd_phi,
+            "rel_err_ve": abs(dp[0] - fd_ve) / abs(fd_ve), "rel_err_phi0": abs(adj_phi - fd_phi) / abs(fd_phi),
+            "central_diff": "FP64 solves, steps 1e-5 (relative for v_e), phi0 direction independent of theta"}
+
+
 def run_cpu_baseline(w, budget_s=15.0):
     """The oracle as it stands, on the host's cores, for a bounded number of
     RK steps of the same workload."""
@@ -164,6 +239,9 @@ def main():
             "alu_frac": alg_ops_per_point(w4.scheme, w4.ham, w4.dim) * w4.points / k4 / 1e12 / PEAK_VALU_TOPS,
             "hbm_alg_frac": stage_bytes_per_point(w4.rk, w4.with_target, 4) * w4.points / k4 / 1e9 / PEAK_HBM_GBS}
 
+        log("adjoint: dubins3d_81 f32")
+        extra["adjoint"] = run_adjoint(inputs.DUBINS3D_81)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: oracle")
@@ -171,6 +249,7 @@ def main():
 
     line = {
         "metric": "grid-point updates/s per WENO5-RK3 step",
+        "adjoint_over_forward": extra.get("adjoint", {}).get("adjoint_over_forward"),
         "value": value,
         "unit": "grid-point updates/s",
         "n_gpus": 1,

@@ -202,6 +202,55 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream,
 hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void *phi_out,
                      double t0, double t1, void *stream, hjx_stats *stats);
 
+/* ------------------------------------------------------------------ adjoint
+ * Gradients of a loss of phi(t1) through the whole solve (no counterpart in
+ * the paper; the discrete adjoint of the scheme above).  A tape fixes the
+ * time schedule of one solve (the CFL step count and the clamped last step,
+ * as hjx_solve would take them) and holds checkpoints of phi every
+ * ckpt_every steps; hjx_adjoint replays each segment from its checkpoint
+ * and runs the transposed stages backwards:
+ *   dL/dphi0    the adjoint at t0 through phi0 (the initial value only),
+ *   dL/dtarget  through the target of min-with-target, when there is one
+ *               (when the target is phi0 itself, dL/dphi0 of the whole map
+ *               is the sum of the two),
+ *   dL/dparams  through the Hamiltonian parameters, including their effect
+ *               on the dissipation coefficients and on the CFL step (the
+ *               number of steps held fixed).
+ * Subgradient conventions at kinks: d|s|/ds = sign(s) with sign(0) = 0; at
+ * a tie of min-with-target the evolved value is the one kept; a maximum of
+ * the dissipation bound differentiates at its first maximising node. */
+typedef struct hjx_tape hjx_tape;
+
+/* Create a tape for a solve of p from t0 to t1 (t1 >= t0) with a checkpoint
+ * every ckpt_every >= 1 steps.  Runs the dissipation reduction (synchronises
+ * `stream`) and allocates the checkpoints and the replay workspace: about
+ * (steps/ckpt_every + 3 ckpt_every + 12) arrays of the problem's size.
+ * Arrays must be under 4 GiB each (else HJX_ERR_UNSUPPORTED). */
+hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream,
+                           hjx_tape **out);
+hjx_status hjx_tape_destroy(hjx_tape *tape);
+
+/* hjx_solve on the tape's schedule, recording the checkpoints.  The target
+ * (NULL for none; may be phi0, not phi_out) must stay unchanged until
+ * hjx_adjoint has run. */
+hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, const void *target, void *phi_out,
+                           void *stream, hjx_stats *stats);
+
+/* Reverse sweep after hjx_solve_taped.  dL_dphiT: device array, the
+ * gradient of the loss with respect to phi(t1).  dL_dphi0: device array
+ * (output).  dL_dtarget: device array (output) or NULL; must be NULL when
+ * the solve had no target.  dL_dparams: host array of 8 doubles (output, the
+ * entries past the kind's parameter count are 0) or NULL.  Synchronises
+ * `stream`. */
+hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *tape, const void *dL_dphiT, void *dL_dphi0, void *dL_dtarget,
+                       double *dL_dparams, void *stream);
+
+/* Smoothed volume of {phi <= 0}: loss = cell volume * sum_i s(-phi_i / eps),
+ * s the logistic function, and its gradient dL/dphi (device array, may be
+ * NULL).  loss: host double.  eps > 0.  Synchronises `stream`. */
+hjx_status hjx_loss_volume(hjx_problem *p, const void *phi, double eps, double *loss, void *dL_dphi,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,442 @@
+// Adjoint (reverse mode) of the fused level-set stage on gfx950.
+//
+// The forward stage is out = ca phi_n + cb (phi_in + h L(phi_in)), then
+// min with the target, where L = -(H(x, pbar) - sum_d alpha_d (p+_d - p-_d)/2)
+// and p-_d, p+_d are the upwind derivative approximations (LevelSetPy,
+// arXiv 2411.03501: Sec. IV-A..IV-D, Sec. V, Sec. VI).  Its reverse takes
+// two kinds of kernel:
+//   adj_seed_kernel  one thread per node: evaluates p-, p+ and H at phi_in,
+//                    turns lam_out into the seeds w dL/dp-_d, w dL/dp+_d
+//                    (w = cb h lam_out), writes the pass-through parts of the
+//                    adjoint and accumulates dL/dh, dL/dalpha and dL/dtheta
+//                    per block;
+//   adj_axis_kernel  one launch per axis: every derivative interval along
+//                    the axis is recomputed once in an LDS line tile, its
+//                    transpose applied to the seeds of its two nodes, and
+//                    each node gathers the contributions of the six
+//                    intervals whose stencils contain it; contributions to
+//                    extrapolated ghost cells are folded back onto the two
+//                    end nodes they were extrapolated from.
+#include "hjx_device.h"
+
+namespace hjx {
+namespace {
+
+using namespace dev;
+
+constexpr int kSeedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// ---------------------------------------------------------------- seeds
+
+template <typename T, int D, int SCHEME, int HAM>
+__global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a)
+{
+    const StageArgs<T> &st = a.st;
+    const int q = blockIdx.x * kSeedThreads + threadIdx.x;
+    const bool live = q < st.g.plane;
+    double part[kAccCount] = {};
+
+    int j[kMaxDim] = {0, 0, 0, 0};
+    if (live) {
+        if constexpr (D == 1) {
+            j[0] = q;
+        } else {
+            const int nl = st.g.n[D - 1];
+            int jm = (int)((double)q / (double)nl);
+            int jl = q - jm * nl;
+            if (jl < 0) {
+                --jm;
+                jl += nl;
+            } else if (jl >= nl) {
+                ++jm;
+                jl -= nl;
+            }
+            j[D - 2] = jm;
+            j[D - 1] = jl;
+        }
+        const int sy = blockIdx.y;
+        if constexpr (D == 3) j[0] = sy;
+        if constexpr (D == 4) {
+            j[0] = sy / st.g.n[1];
+            j[1] = sy - j[0] * st.g.n[1];
+        }
+        int idx = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) idx += j[d] * st.g.stride[d];
+
+        T lo = ld32(a.lam_out, idx);
+        if (a.mask && a.mask[idx]) {  // the target was kept: its adjoint takes lam_out
+            if (a.lam_target) a.lam_target[idx] += lo;
+            lo = T(0);
+        }
+        T pm[D], pp[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            T v[7];
+            gather7(st.phi_in, idx, j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
+            node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], pm[d], pp[d]);
+        }
+        T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
+#pragma unroll
+        for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (pm[d] + pp[d]);
+        T hhat = ham_grad<T, D, HAM>(st, j, pbar, dHdp, dmH);
+#pragma unroll
+        for (int d = 0; d < D; ++d) hhat = fmaT(-st.alpha[d], T(0.5) * (pp[d] - pm[d]), hhat);
+        const T L = -hhat;
+
+        const T w = a.cb * a.h * lo;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
+            a.seed_m[d][idx] = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
+            a.seed_p[d][idx] = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
+            part[kAccAlpha + d] = (double)(w * T(0.5) * (pp[d] - pm[d]));
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) part[kAccTheta + m] = (double)(w * dmH[m]);
+        part[a.h_slot] = (double)(a.cb * lo) * (double)L;
+
+        const T cin = a.cb * lo;
+        a.lam_in[idx] = a.in_mode ? a.lam_in[idx] + cin : cin;
+        if (a.n_mode) {
+            const T cn = a.ca * lo;
+            a.lam_n[idx] = a.n_mode == 2 ? a.lam_n[idx] + cn : cn;
+        }
+    }
+
+    // block sums, accumulated into this block's slot (a fixed order: deterministic)
+    __shared__ double red[kSeedThreads / 64][kAccCount];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kAccCount; ++k) {
+        const double s = wave_sum(part[k]);
+        if (lane == 0) red[wave][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kAccCount) {
+        double s = 0.0;
+        for (int w = 0; w < kSeedThreads / 64; ++w) s += red[w][threadIdx.x];
+        const int b = blockIdx.y * gridDim.x + blockIdx.x;
+        a.acc[b * kAccCount + threadIdx.x] += s;
+    }
+}
+
+template <typename T, int D, int SCHEME, int HAM>
+hipError_t launch_seed_one(const AdjSeedArgs<T> &a, hipStream_t s)
+{
+    dim3 grid((a.st.g.plane + kSeedThreads - 1) / kSeedThreads, a.st.g.slow);
+    hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM>), grid, dim3(kSeedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int D, int HAM>
+hipError_t launch_seed_scheme(const AdjSeedArgs<T> &a, int scheme, hipStream_t s)
+{
+    switch (scheme) {
+    case kSchemeFirst: return launch_seed_one<T, D, kSchemeFirst, HAM>(a, s);
+    case kSchemeEno2: return launch_seed_one<T, D, kSchemeEno2, HAM>(a, s);
+    case kSchemeEno3: return launch_seed_one<T, D, kSchemeEno3, HAM>(a, s);
+    case kSchemeWeno5: return launch_seed_one<T, D, kSchemeWeno5, HAM>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_seed(const AdjSeedArgs<T> &a, int scheme, int ham, hipStream_t s)
+{
+    if (a.st.g.slow > 65535) return hipErrorInvalidConfiguration;
+    if (ham == kHamDubins3) return a.st.g.dim == 3 ? launch_seed_scheme<T, 3, kHamDubins3>(a, scheme, s)
+                                                   : hipErrorInvalidValue;
+    if (ham == kHamDubins4) return a.st.g.dim == 4 ? launch_seed_scheme<T, 4, kHamDubins4>(a, scheme, s)
+                                                   : hipErrorInvalidValue;
+    switch (a.st.g.dim) {
+    case 1: return launch_seed_scheme<T, 1, kHamNormal>(a, scheme, s);
+    case 2: return launch_seed_scheme<T, 2, kHamNormal>(a, scheme, s);
+    case 3: return launch_seed_scheme<T, 3, kHamNormal>(a, scheme, s);
+    case 4: return launch_seed_scheme<T, 4, kHamNormal>(a, scheme, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- per-axis transpose
+
+// LDS of one block: phi at l0-5 .. l0+tl+4, the two seeds at l0-3 .. l0+tl+2
+// and the five difference adjoints of each interval l0-3 .. l0+tl+1.
+template <typename T>
+__device__ __forceinline__ int lds_at(bool lx, int pos, int col, int npos, int tw)
+{
+    return lx ? col * npos + pos : pos * tw + col;
+}
+
+template <typename T, int SCHEME>
+__global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int tl = a.tl, tw = a.tw;
+    const bool lx = a.d == a.g.dim - 1;  // the line runs along the lanes
+    const int ip = lx ? threadIdx.x : threadIdx.y;
+    const int ic = lx ? threadIdx.y : threadIdx.x;
+    const int NP = tl + 10, NS = tl + 6, NI = tl + 5;
+    T *PH = reinterpret_cast<T *>(smem_raw);   // NP x tw
+    T *SM = PH + NP * tw;                      // NS x tw
+    T *SP = SM + NS * tw;                      // NS x tw
+    T *UB = SP + NS * tw;                      // NI x 5 x tw
+
+    const int d = a.d, nd = a.g.n[d], sd = a.g.stride[d];
+    const bool per = (a.g.periodic >> d) & 1u;
+    const int nc = a.c >= 0 ? a.g.n[a.c] : 1, sc = a.c >= 0 ? a.g.stride[a.c] : 0;
+    const int tiles_d = (nd + tl - 1) / tl;
+    const int l0 = (blockIdx.x % tiles_d) * tl, c0 = (blockIdx.x / tiles_d) * tw;
+    const int col = c0 + ic;
+    const bool col_ok = col < nc;
+    int base = col_ok ? col * sc : 0;
+    {
+        int r = blockIdx.y;
+        for (int k = 1; k >= 0; --k)
+            if (a.rest[k] >= 0) {
+                const int n = a.g.n[a.rest[k]];
+                base += (r % n) * a.g.stride[a.rest[k]];
+                r /= n;
+            }
+    }
+
+    auto phi_at = [&](int gpos) -> T {  // with ghosts along d
+        if (gpos >= 0 && gpos < nd) return a.phi[base + gpos * sd];
+        if (per) return a.phi[base + wrap_index<T>(gpos, nd) * sd];
+        const int e = gpos < 0 ? 0 : nd - 1, e2 = gpos < 0 ? 1 : nd - 2;
+        const T c = T(gpos < 0 ? -gpos : gpos - (nd - 1));
+        const T p0 = a.phi[base + e * sd], p1 = a.phi[base + e2 * sd];
+        return fmaT(c, p0 - p1, p0);
+    };
+
+    // stage phi and the seeds of this axis
+    for (int p = ip; p < NP; p += tl) PH[lds_at<T>(lx, p, ic, NP, tw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
+    for (int p = ip; p < NS; p += tl) {
+        int g = l0 - 3 + p;
+        T m = T(0), pl = T(0);
+        if (col_ok) {
+            if (g < 0 || g >= nd) g = per ? wrap_index<T>(g, nd) : -1;  // ghosts carry no seed
+            if (g >= 0) {
+                m = a.seed_m[base + g * sd];
+                pl = a.seed_p[base + g * sd];
+            }
+        }
+        SM[lds_at<T>(lx, p, ic, NS, tw)] = m;
+        SP[lds_at<T>(lx, p, ic, NS, tw)] = pl;
+    }
+    __syncthreads();
+
+    // transpose every interval I = l0-3+iv once: the NI x tw (interval,
+    // column) pairs are spread evenly over the block's threads, consecutive
+    // lanes taking consecutive intervals of a line (lx) or consecutive
+    // columns (otherwise), as the LDS layout is laid out
+    const int nthr = tl * tw, tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const float inv_ni = 1.0f / (float)NI;
+    for (int e = tid; e < NI * tw; e += nthr) {
+        int iv, cc;
+        if (lx) {
+            cc = (int)(((float)e + 0.5f) * inv_ni);
+            iv = e - cc * NI;
+        } else {
+            cc = e % tw;
+            iv = e / tw;
+        }
+        T ub[5] = {T(0), T(0), T(0), T(0), T(0)};
+        if (c0 + cc < nc) {
+            T v[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[k] = PH[lds_at<T>(lx, iv + k, cc, NP, tw)];
+            const T gm = SM[lds_at<T>(lx, iv + 1, cc, NS, tw)];  // left-biased seed of node I+1
+            const T gp = SP[lds_at<T>(lx, iv, cc, NS, tw)];      // right-biased seed of node I
+            interval_vjp<T, SCHEME>(v, a.inv_dx, a.dx, gm, gp, ub);
+        }
+#pragma unroll
+        for (int r = 0; r < 5; ++r) UB[lds_at<T>(lx, iv * 5 + r, cc, NI * 5, tw)] = ub[r];
+    }
+    __syncthreads();
+
+    // adjoint of the difference at half-node m (between m and m+1): the five
+    // intervals m-2 .. m+2 (those outside this tile carry zero seeds here)
+    auto ubar = [&](int m) -> T {
+        T s = T(0);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int iv = m + 2 - r - (l0 - 3);
+            if (iv >= 0 && iv < NI) s += UB[lds_at<T>(lx, iv * 5 + r, ic, NI * 5, tw)];
+        }
+        return s;
+    };
+    const int g = l0 + ip;
+    if (ip < tl && g < nd && col_ok) {
+        T acc = (ubar(g - 1) - ubar(g)) * a.inv_dx;
+        if (!per) {
+            // ghosts phi[-k] = (1+k) phi_0 - k phi_1 and
+            // phi[nd-1+k] = (1+k) phi_{nd-1} - k phi_{nd-2}, k = 1..3
+            if (g <= 1) {
+                for (int k = 1; k <= 3; ++k) {
+                    const T gb = (ubar(-k - 1) - ubar(-k)) * a.inv_dx;
+                    acc += (g == 0 ? T(1 + k) : T(-k)) * gb;
+                }
+            }
+            if (g >= nd - 2) {
+                for (int k = 1; k <= 3; ++k) {
+                    const int q = nd - 1 + k;
+                    const T gb = (ubar(q - 1) - ubar(q)) * a.inv_dx;
+                    acc += (g == nd - 1 ? T(1 + k) : T(-k)) * gb;
+                }
+            }
+        }
+        a.lam[base + g * sd] += acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_axis(const AdjAxisArgs<T> &a, int scheme, hipStream_t s)
+{
+    const int nd = a.g.n[a.d], nc = a.c >= 0 ? a.g.n[a.c] : 1;
+    if (a.tl < 2 || a.tw < 1 || a.tl * a.tw > 256) return hipErrorInvalidConfiguration;
+    const bool lx = a.d == a.g.dim - 1;
+    int rest = 1;
+    for (int k = 0; k < 2; ++k)
+        if (a.rest[k] >= 0) rest *= a.g.n[a.rest[k]];
+    if (rest > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid(((nd + a.tl - 1) / a.tl) * ((nc + a.tw - 1) / a.tw), rest);
+    const dim3 block(lx ? a.tl : a.tw, lx ? a.tw : a.tl);
+    const size_t lds = sizeof(T) * (size_t)a.tw * ((a.tl + 10) + 2 * (a.tl + 6) + 5 * (a.tl + 5));
+    switch (scheme) {
+    case kSchemeFirst: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeFirst>), grid, block, lds, s, a); break;
+    case kSchemeEno2: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeEno2>), grid, block, lds, s, a); break;
+    case kSchemeEno3: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeEno3>), grid, block, lds, s, a); break;
+    case kSchemeWeno5: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeWeno5>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- helpers
+
+__global__ __launch_bounds__(256) void acc_reduce_kernel(const double *acc, int blocks, double *out)
+{
+    // one block: thread t sums slot t % kAccCount over a strided subset of blocks
+    __shared__ double red[256];
+    const int k = threadIdx.x % kAccCount, lane = threadIdx.x / kAccCount, lanes = 256 / kAccCount;
+    double s = 0.0;
+    for (int b = lane; b < blocks; b += lanes) s += acc[b * kAccCount + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < kAccCount) {
+        double t = 0.0;
+        for (int l = 0; l < lanes; ++l) t += red[l * kAccCount + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_kernel(T *x, int n)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) x[i] = T(0);
+}
+
+int zero_blocks(int n)
+{
+    const int b = (n + 255) / 256;
+    return b < 4096 ? (b > 0 ? b : 1) : 4096;
+}
+
+// smoothed volume: partial[b] = sum over this block's nodes of s(-phi/eps);
+// grad = d(vol * sum)/dphi
+template <typename T>
+__global__ __launch_bounds__(256) void loss_kernel(const T *phi, int n, double inv_eps, double vol, T *grad,
+                                                   double *partial)
+{
+    double acc = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double z = -(double)phi[i] * inv_eps;
+        const double sg = 1.0 / (1.0 + exp(-z));
+        acc += sg;
+        if (grad) grad[i] = T(-vol * inv_eps * sg * (1.0 - sg));
+    }
+    __shared__ double red[4];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void sum_kernel(const double *partial, int n, double scale, double *out)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = scale * (red[0] + red[1] + red[2] + red[3]);
+}
+
+template <typename T>
+hipError_t launch_loss(const T *phi, int n, double eps, double vol, T *grad, double *partial, int blocks,
+                       double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(loss_kernel<T>, dim3(blocks), dim3(256), 0, s, phi, n, 1.0 / eps, vol, grad, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, partial, blocks, vol, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int adj_seed_blocks(const GridGeom &g) { return ((g.plane + kSeedThreads - 1) / kSeedThreads) * g.slow; }
+
+hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, int scheme, int ham, hipStream_t s)
+{
+    return launch_seed<float>(a, scheme, ham, s);
+}
+hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham, hipStream_t s)
+{
+    return launch_seed<double>(a, scheme, ham, s);
+}
+hipError_t launch_adj_axis_f32(const AdjAxisArgs<float> &a, int scheme, hipStream_t s)
+{
+    return launch_axis<float>(a, scheme, s);
+}
+hipError_t launch_adj_axis_f64(const AdjAxisArgs<double> &a, int scheme, hipStream_t s)
+{
+    return launch_axis<double>(a, scheme, s);
+}
+hipError_t launch_acc_reduce(const double *acc, int blocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(acc_reduce_kernel, dim3(1), dim3(256), 0, s, acc, blocks, out);
+    return hipGetLastError();
+}
+hipError_t launch_zero_f32(float *x, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel<float>, dim3(zero_blocks(n)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+hipError_t launch_zero_f64(double *x, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel<double>, dim3(zero_blocks(n)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+hipError_t launch_zero_f64acc(double *x, int n, hipStream_t s) { return launch_zero_f64(x, n, s); }
+hipError_t launch_loss_f32(const float *phi, int n, double eps, double vol, float *grad, double *partial, int blocks,
+                           double *out, hipStream_t s)
+{
+    return launch_loss<float>(phi, n, eps, vol, grad, partial, blocks, out, s);
+}
+hipError_t launch_loss_f64(const double *phi, int n, double eps, double vol, double *grad, double *partial,
+                           int blocks, double *out, hipStream_t s)
+{
+    return launch_loss<double>(phi, n, eps, vol, grad, partial, blocks, out, s);
+}
+
+}  // namespace hjx

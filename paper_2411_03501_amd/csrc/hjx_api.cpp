@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -631,6 +632,468 @@ hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void 
         stats->alg_bytes = per_step * f * (double)steps;
     }
     if (bad) return fail(HJX_ERR_NONFINITE, "the solution holds NaN or Inf");
+    return ok();
+}
+
+}  // extern "C"
+
+// ==================================================================== adjoint (host)
+
+struct hjx_tape {
+    hjx_problem *p = nullptr;
+    double t0 = 0, t1 = 0, dt = 0, dt_last = 0, alpha[kMaxDim] = {0, 0, 0, 0};
+    int64_t steps = 0;
+    int K = 1, nseg = 0;
+    std::vector<void *> ckpt;          // phi at the start of every segment
+    std::vector<void *> phin, x1, xh;  // replay: stage inputs of each step of a segment
+    std::vector<unsigned char *> mask; // replay: where the target was the smaller
+    void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *seed_m[kMaxDim] = {}, *seed_p[kMaxDim] = {};
+    double *acc = nullptr;             // per seed-kernel block
+    int acc_blocks = 0;
+    double *acc_out = nullptr;         // device, kAccCount
+    double *hacc = nullptr;            // pinned, kAccCount
+    const void *target = nullptr;
+    bool solved = false;
+};
+
+namespace {
+
+void tape_release(hjx_tape *t)
+{
+    if (!t) return;
+    auto f = [](void *x) {
+        if (x) (void)hipFree(x);
+    };
+    for (void *x : t->ckpt) f(x);
+    for (void *x : t->phin) f(x);
+    for (void *x : t->x1) f(x);
+    for (void *x : t->xh) f(x);
+    for (unsigned char *x : t->mask) f(x);
+    for (void *x : t->lam) f(x);
+    for (int d = 0; d < kMaxDim; ++d) {
+        f(t->seed_m[d]);
+        f(t->seed_p[d]);
+    }
+    f(t->acc);
+    f(t->acc_out);
+    if (t->hacc) (void)hipHostFree(t->hacc);
+    delete t;
+}
+
+// the steps of a solve from t0 to t1 with CFL step dt (the loop of hjx_solve)
+void schedule(double t0, double t1, double dt, int64_t *steps, double *dt_last)
+{
+    const double slack = 1e-12 * (std::fabs(t1) > 1.0 ? std::fabs(t1) : 1.0);
+    double t = t0, last_h = 0.0;
+    int64_t n = 0;
+    while (t < t1) {
+        double h = dt;
+        bool last = false;
+        if (t + h >= t1 - slack) {
+            h = t1 - t;
+            last = true;
+        }
+        ++n;
+        last_h = h;
+        t = last ? t1 : t + h;
+    }
+    *steps = n;
+    *dt_last = last_h;
+}
+
+// dalpha_d / dtheta_m of the built-in bounds, differentiated at the first
+// node where each maximum is attained (FP64, from the same node formula as
+// the device tables)
+void alpha_jacobian(const hjx_problem *p, double J[kMaxDim][8])
+{
+    for (int d = 0; d < kMaxDim; ++d)
+        for (int m = 0; m < 8; ++m) J[d][m] = 0.0;
+    auto node = [&](int d, int64_t j) { return p->grid.gmin[d] + (double)j * p->dx[d]; };
+    auto sgn = [](double x) { return x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0); };
+    const double *h = p->ham.p;
+    if (p->ham.kind == HJX_HAM_NORMAL) {
+        for (int d = 0; d < p->grid.dim; ++d) J[d][0] = sgn(h[0]);
+    } else if (p->ham.kind == HJX_HAM_DUBINS3_PE) {
+        // alpha_0 = max_th |-v_e + v_p cos th| + wbar_e max_y |y|
+        // alpha_1 = max_th |v_p sin th| + wbar_e max_x |x|,  alpha_2 = wbar_e + wbar_p
+        double b0 = -1, c0 = 0, b1 = -1, s1 = 0, ymax = 0, xmax = 0;
+        for (int64_t k = 0; k < p->grid.n[2]; ++k) {
+            const double th = node(2, k), c = std::cos(th), sn = std::sin(th);
+            const double v0 = std::fabs(-h[0] + h[1] * c), v1 = std::fabs(h[1] * sn);
+            if (v0 > b0) { b0 = v0; c0 = c; }
+            if (v1 > b1) { b1 = v1; s1 = sn; }
+        }
+        for (int64_t j = 0; j < p->grid.n[1]; ++j) ymax = std::max(ymax, std::fabs(node(1, j)));
+        for (int64_t i = 0; i < p->grid.n[0]; ++i) xmax = std::max(xmax, std::fabs(node(0, i)));
+        const double g0 = sgn(-h[0] + h[1] * c0), g1 = sgn(h[1] * s1);
+        J[0][0] = -g0;
+        J[0][1] = g0 * c0;
+        J[0][2] = ymax;
+        J[1][1] = g1 * s1;
+        J[1][2] = xmax;
+        J[2][2] = 1.0;
+        J[2][3] = 1.0;
+    } else {
+        // alpha_0, alpha_1 = max |v cos th|, |v sin th| (no parameters); alpha_2 = wbar, alpha_3 = abar
+        J[2][0] = 1.0;
+        J[3][1] = 1.0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream, hjx_tape **out)
+{
+    if (!p || !out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0))
+        return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
+    if (ckpt_every < 1) return fail(HJX_ERR_INVALID_ARG, "ckpt_every %d < 1", ckpt_every);
+    if (!direct_ok(geometry(p), p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the adjoint needs arrays under 4 GiB");
+    hjx_tape *t = new (std::nothrow) hjx_tape;
+    if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
+    t->p = p;
+    t->t0 = t0;
+    t->t1 = t1;
+    t->K = ckpt_every;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hjx_status st = device_alpha(p, s, t->alpha);
+    if (st != HJX_OK) {
+        tape_release(t);
+        return st;
+    }
+    t->dt = cfl_dt(p, t->alpha);
+    schedule(t0, t1, t->dt, &t->steps, &t->dt_last);
+    t->nseg = (int)((t->steps + t->K - 1) / t->K);
+    const size_t field = (size_t)p->total * p->elem;
+    const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
+    hipError_t e = hipSuccess;
+    auto grab = [&](void **x, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(x, bytes);
+    };
+    t->ckpt.assign(t->nseg, nullptr);
+    for (auto &x : t->ckpt) grab(&x, field);
+    t->phin.assign(K + 1, nullptr);
+    for (int i = 1; i <= K; ++i) grab(&t->phin[i], field);  // phin[0] is the checkpoint itself
+    if (p->scheme.rk >= 2) {
+        t->x1.assign(K, nullptr);
+        for (auto &x : t->x1) grab(&x, field);
+    }
+    if (p->scheme.rk >= 3) {
+        t->xh.assign(K, nullptr);
+        for (auto &x : t->xh) grab(&x, field);
+    }
+    t->mask.assign(K, nullptr);
+    for (auto &x : t->mask) grab(reinterpret_cast<void **>(&x), (size_t)p->total);
+    for (auto &x : t->lam) grab(&x, field);
+    for (int d = 0; d < p->grid.dim; ++d) {
+        grab(&t->seed_m[d], field);
+        grab(&t->seed_p[d], field);
+    }
+    t->acc_blocks = adj_seed_blocks(geometry(p));
+    grab(reinterpret_cast<void **>(&t->acc), sizeof(double) * kAccCount * (size_t)t->acc_blocks);
+    grab(reinterpret_cast<void **>(&t->acc_out), sizeof(double) * kAccCount);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&t->hacc), sizeof(double) * kAccCount,
+                                           hipHostMallocDefault);
+    if (e != hipSuccess) {
+        tape_release(t);
+        return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "tape allocation: %s",
+                    hipGetErrorString(e));
+    }
+    *out = t;
+    return ok();
+}
+
+hjx_status hjx_tape_destroy(hjx_tape *tape)
+{
+    tape_release(tape);
+    return ok();
+}
+
+hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, const void *target, void *phi_out,
+                           void *stream, hjx_stats *stats)
+{
+    if (!p || !tape || !phi0 || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (tape->p != p) return fail(HJX_ERR_INVALID_ARG, "the tape belongs to another problem");
+    if (target && target == phi_out) return fail(HJX_ERR_INVALID_ARG, "target aliases phi_out");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool bad = false;
+    hjx_status st = any_nonfinite(p, phi0, s, &bad);
+    if (st != HJX_OK) return st;
+    if (bad) return fail(HJX_ERR_NONFINITE, "phi0 holds NaN or Inf");
+    if (phi_out != phi0) HIP_TRY(launch_copy(p, phi0, phi_out, s));
+    if (stats) HIP_TRY(hipEventRecord(p->ev[0], s));
+    for (int64_t n = 0; n < tape->steps; ++n) {
+        if (n % tape->K == 0) HIP_TRY(launch_copy(p, phi_out, tape->ckpt[n / tape->K], s));
+        const double h = n == tape->steps - 1 ? tape->dt_last : tape->dt;
+        if (p->scheme.rk == 1) {
+            HIP_TRY(launch_stage(p, tape->alpha, phi_out, nullptr, target, p->ws[0], h, 0.0, 1.0, false, s));
+            HIP_TRY(launch_copy(p, p->ws[0], phi_out, s));
+        } else {
+            HIP_TRY(rk_step(p, tape->alpha, phi_out, target, h, s));
+        }
+    }
+    if (stats) HIP_TRY(hipEventRecord(p->ev[1], s));
+    if ((st = any_nonfinite(p, phi_out, s, &bad)) != HJX_OK) return st;
+    tape->target = target;
+    tape->solved = true;
+    if (stats) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+        stats->steps = tape->steps;
+        stats->dt = tape->dt;
+        stats->dt_last = tape->dt_last;
+        stats->t_final = tape->t1;
+        for (int d = 0; d < kMaxDim; ++d) stats->alpha[d] = tape->alpha[d];
+        stats->elapsed_ms = ms;
+        stats->alg_bytes = 0.0;
+    }
+    if (bad) return fail(HJX_ERR_NONFINITE, "the solution holds NaN or Inf");
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// one forward stage for the replay, writing the min-with-target mask
+hipError_t replay_stage(const hjx_problem *p, const double *alpha, const void *in, const void *phin,
+                        const void *target, void *out, double h, double ca, double cb, unsigned char *mask,
+                        hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32) {
+        StageArgs<float> a = stage_args<float>(p, alpha);
+        a.phi_in = static_cast<const float *>(in);
+        a.phi_n = static_cast<const float *>(phin);
+        a.target = static_cast<const float *>(target);
+        a.out = static_cast<float *>(out);
+        a.dt = float(h);
+        a.ca = float(ca);
+        a.cb = float(cb);
+        a.mask = target ? mask : nullptr;
+        return launch_stage_f32(a, p->scheme.deriv, p->ham.kind, s);
+    }
+    StageArgs<double> a = stage_args<double>(p, alpha);
+    a.phi_in = static_cast<const double *>(in);
+    a.phi_n = static_cast<const double *>(phin);
+    a.target = static_cast<const double *>(target);
+    a.out = static_cast<double *>(out);
+    a.dt = h;
+    a.ca = ca;
+    a.cb = cb;
+    a.mask = target ? mask : nullptr;
+    return launch_stage_f64(a, p->scheme.deriv, p->ham.kind, s);
+}
+
+template <typename T>
+hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,
+                           const unsigned char *mask, void *lam_target, void *lam_in, int in_mode, void *lam_n,
+                           int n_mode, double ca, double cb, double h, int h_slot, hipStream_t s)
+{
+    AdjSeedArgs<T> a{};
+    a.st = stage_args<T>(p, t->alpha);
+    a.st.phi_in = static_cast<const T *>(in);
+    a.lam_out = static_cast<const T *>(lam_out);
+    a.mask = mask;
+    a.lam_target = static_cast<T *>(lam_target);
+    for (int d = 0; d < kMaxDim; ++d) {
+        a.seed_m[d] = static_cast<T *>(t->seed_m[d]);
+        a.seed_p[d] = static_cast<T *>(t->seed_p[d]);
+    }
+    a.lam_in = static_cast<T *>(lam_in);
+    a.in_mode = in_mode;
+    a.lam_n = static_cast<T *>(lam_n);
+    a.n_mode = n_mode;
+    a.ca = T(ca);
+    a.cb = T(cb);
+    a.h = T(h);
+    a.acc = t->acc;
+    a.h_slot = h_slot;
+    hipError_t e;
+    if constexpr (std::is_same<T, float>::value)
+        e = launch_adj_seed_f32(a, p->scheme.deriv, p->ham.kind, s);
+    else
+        e = launch_adj_seed_f64(a, p->scheme.deriv, p->ham.kind, s);
+    if (e != hipSuccess) return e;
+    const GridGeom g = geometry(p);
+    for (int d = 0; d < g.dim; ++d) {
+        AdjAxisArgs<T> x{};
+        x.phi = static_cast<const T *>(in);
+        x.seed_m = static_cast<const T *>(t->seed_m[d]);
+        x.seed_p = static_cast<const T *>(t->seed_p[d]);
+        x.lam = static_cast<T *>(lam_in);
+        x.g = g;
+        x.d = d;
+        // cross axis: the fastest axis (coalesced rows), or the second-fastest
+        // when the line itself is the fastest axis
+        x.c = d != g.dim - 1 ? g.dim - 1 : (g.dim >= 2 ? g.dim - 2 : -1);
+        int r = 0;
+        x.rest[0] = x.rest[1] = -1;
+        for (int k = 0; k < g.dim; ++k)
+            if (k != d && k != x.c) x.rest[r++] = k;
+        x.inv_dx = T(1.0 / p->dx[d]);
+        x.dx = T(p->dx[d]);
+        const int nd = g.n[d], nc = x.c >= 0 ? g.n[x.c] : 1;
+        // line tiles split each axis into equal pieces of at most 64 (fastest
+        // axis, along the lanes) or 32 nodes (other axes, 8 columns of the
+        // fastest axis per block): each piece recomputes 5 intervals beyond it
+        const int cap = d == g.dim - 1 ? 64 : 32;
+        const int pieces = (nd + cap - 1) / cap;
+        x.tl = std::max(2, (nd + pieces - 1) / pieces);
+        if (d == g.dim - 1)
+            x.tw = std::max(1, std::min(256 / x.tl, nc));
+        else
+            x.tw = std::min(nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)), 256 / x.tl);
+        if constexpr (std::is_same<T, float>::value)
+            e = launch_adj_axis_f32(x, p->scheme.deriv, s);
+        else
+            e = launch_adj_axis_f64(x, p->scheme.deriv, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t reverse_stage(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,
+                         const unsigned char *mask, void *lam_target, void *lam_in, int in_mode, void *lam_n,
+                         int n_mode, double ca, double cb, double h, int h_slot, hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32)
+        return reverse_stage_t<float>(p, t, in, lam_out, mask, lam_target, lam_in, in_mode, lam_n, n_mode, ca, cb,
+                                      h, h_slot, s);
+    return reverse_stage_t<double>(p, t, in, lam_out, mask, lam_target, lam_in, in_mode, lam_n, n_mode, ca, cb, h,
+                                   h_slot, s);
+}
+
+hipError_t zero(const hjx_problem *p, void *x, hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32) return launch_zero_f32(static_cast<float *>(x), (int)p->total, s);
+    return launch_zero_f64(static_cast<double *>(x), (int)p->total, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *dL_dphi0, void *dL_dtarget,
+                       double *dL_dparams, void *stream)
+{
+    if (!p || !t || !dL_dphiT || !dL_dphi0) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (t->p != p) return fail(HJX_ERR_INVALID_ARG, "the tape belongs to another problem");
+    if (!t->solved) return fail(HJX_ERR_INVALID_ARG, "the tape holds no solve (call hjx_solve_taped first)");
+    if (dL_dtarget && !t->target) return fail(HJX_ERR_INVALID_ARG, "dL_dtarget given but the solve had no target");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int rk = p->scheme.rk;
+    // stage k of the forward step: out = ca phi_n + cb (in_k + h L(in_k))
+    static const double kCa[3][3] = {{0, 0, 0}, {0, 0.5, 0}, {0, 0.75, 1.0 / 3.0}};
+    static const double kCb[3][3] = {{1, 0, 0}, {1, 0.5, 0}, {1, 0.25, 2.0 / 3.0}};
+
+    void *lbar = t->lam[0], *lnew = t->lam[1];
+    HIP_TRY(launch_copy(p, dL_dphiT, lbar, s));
+    if (dL_dtarget) HIP_TRY(zero(p, dL_dtarget, s));
+    HIP_TRY(launch_zero_f64acc(t->acc, kAccCount * t->acc_blocks, s));
+
+    for (int seg = t->nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
+        const int len = (int)(s1 - s0);
+        auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : t->phin[i]; };
+        // replay the segment, keeping every stage input and the masks
+        for (int i = 0; i < len; ++i) {
+            const double h = s0 + i == t->steps - 1 ? t->dt_last : t->dt;
+            if (rk == 1) {
+                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, t->mask[i], s));
+            } else if (rk == 2) {
+                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, s));
+                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, t->mask[i], s));
+            } else {
+                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, s));
+                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), nullptr, t->xh[i], h, 0.75, 0.25, nullptr, s));
+                HIP_TRY(replay_stage(p, t->alpha, t->xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0,
+                                     t->mask[i], s));
+            }
+        }
+        // reverse steps
+        for (int i = len - 1; i >= 0; --i) {
+            const int64_t n = s0 + i;
+            const double h = n == t->steps - 1 ? t->dt_last : t->dt;
+            const int slot = n == t->steps - 1 ? kAccDhLast : kAccDhMain;
+            const void *inputs[3] = {phin(i), rk >= 2 ? t->x1[i] : nullptr, rk >= 3 ? t->xh[i] : nullptr};
+            bool n_written = false;
+            const void *lout = lbar;
+            void *stage_lam[2] = {t->lam[2], t->lam[3]};
+            for (int k = rk - 1; k >= 0; --k) {
+                const bool last = k == rk - 1;
+                const unsigned char *mk = last && t->target ? t->mask[i] : nullptr;
+                void *ltgt = last && t->target ? dL_dtarget : nullptr;
+                const double ca = kCa[rk - 1][k], cb = kCb[rk - 1][k];
+                void *lin;
+                int in_mode;
+                if (k == 0) {
+                    lin = lnew;
+                    in_mode = n_written ? 1 : 0;
+                } else {
+                    lin = stage_lam[k & 1];
+                    in_mode = 0;
+                }
+                int n_mode = 0;
+                if (k != 0 && ca != 0.0) {
+                    n_mode = n_written ? 2 : 1;
+                    n_written = true;
+                }
+                HIP_TRY(reverse_stage(p, t, inputs[k], lout, mk, ltgt, lin, in_mode, lnew, n_mode, ca, cb, h, slot,
+                                      s));
+                lout = lin;
+            }
+            std::swap(lbar, lnew);
+        }
+    }
+    HIP_TRY(launch_copy(p, lbar, dL_dphi0, s));
+
+    HIP_TRY(launch_acc_reduce(t->acc, t->acc_blocks, t->acc_out, s));
+    HIP_TRY(hipMemcpyAsync(t->hacc, t->acc_out, sizeof(double) * kAccCount, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (dL_dparams) {
+        // the step size depends on alpha: dt = cfl / sum_d alpha_d / dx_d for
+        // every step but the last, which is t1 - t0 - (N-1) dt
+        double ddt = 0.0;
+        if (std::isfinite(t->dt) && t->steps > 0)
+            ddt = t->hacc[kAccDhMain] - (double)(t->steps - 1) * t->hacc[kAccDhLast];
+        double J[kMaxDim][8];
+        alpha_jacobian(p, J);
+        for (int m = 0; m < 8; ++m) {
+            double gsum = t->hacc[kAccTheta + m];
+            for (int d = 0; d < p->grid.dim; ++d) {
+                double dalpha = t->hacc[kAccAlpha + d];
+                if (std::isfinite(t->dt))
+                    dalpha += ddt * (-t->dt * t->dt / (p->scheme.cfl * p->dx[d]));
+                gsum += dalpha * J[d][m];
+            }
+            dL_dparams[m] = m < n_params(p->ham.kind) ? gsum : 0.0;
+        }
+    }
+    return ok();
+}
+
+hjx_status hjx_loss_volume(hjx_problem *p, const void *phi, double eps, double *loss, void *dL_dphi, void *stream)
+{
+    if (!p || !phi || !loss) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(HJX_ERR_INVALID_ARG, "eps %g is not positive", eps);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double vol = 1.0;
+    for (int d = 0; d < p->grid.dim; ++d) vol *= p->dx[d];
+    const int blocks = alpha_blocks((int)p->total);
+    double *partial = p->dalpha + kMaxDim;
+    if (p->scheme.dtype == HJX_F32)
+        HIP_TRY(launch_loss_f32(static_cast<const float *>(phi), (int)p->total, eps, vol, static_cast<float *>(dL_dphi),
+                                partial, blocks, p->dalpha, s));
+    else
+        HIP_TRY(launch_loss_f64(static_cast<const double *>(phi), (int)p->total, eps, vol,
+                                static_cast<double *>(dL_dphi), partial, blocks, p->dalpha, s));
+    HIP_TRY(hipMemcpyAsync(p->hbuf, p->dalpha, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *loss = p->hbuf[0];
     return ok();
 }
 

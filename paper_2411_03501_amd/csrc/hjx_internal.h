@@ -61,7 +61,77 @@ struct StageArgs {
     T dt, ca, cb;
     int rhs_only;
     Tile tile;
+    unsigned char *mask;  // nullable: 1 where the target was the smaller (replay for the adjoint)
 };
+
+// ---------------------------------------------------------------- adjoint
+// Per-block accumulators of the adjoint (doubles per block):
+enum : int {
+    kAccDhMain = 0,   // dL/dh summed over every step but the last
+    kAccDhLast = 1,   // dL/dh of the last (clamped) step
+    kAccAlpha = 2,    // dL/dalpha_d, d < 4
+    kAccTheta = 6,    // dL/dtheta_m at fixed alpha, m < 8
+    kAccCount = 16
+};
+
+// Reverse of one stage out = ca phi_n + cb (phi_in + h L(phi_in)) (then
+// min with the target when `mask` is set), given lam_out = dL/dout:
+//   lam_out' = lam_out where the evolved value was kept (the rest goes to
+//              the target's adjoint),
+//   lam_in  (=, or += when in_mode) cb lam_out' (+ the transposed spatial
+//              operator, added afterwards by the per-axis kernels from the
+//              seeds written here),
+//   lam_n   (=, or += when n_mode == 2) ca lam_out' when n_mode != 0,
+//   seeds   s-_d = w dL/dp-_d, s+_d = w dL/dp+_d with w = cb h lam_out',
+//   acc     dL/dh += cb lam_out' . L, dL/dalpha_d, dL/dtheta (per block).
+template <typename T>
+struct AdjSeedArgs {
+    StageArgs<T> st;  // forward evaluation at st.phi_in (alpha, tables, parameters)
+    const T *lam_out;
+    const unsigned char *mask;
+    T *lam_target;
+    T *seed_m[kMaxDim];
+    T *seed_p[kMaxDim];
+    T *lam_in;
+    int in_mode;
+    T *lam_n;
+    int n_mode;
+    T ca, cb, h;
+    double *acc;
+    int h_slot;
+};
+
+// lam += transposed derivative intervals along axis d, from the seeds of
+// that axis (line tiles of tl nodes along d by tw along the cross axis c).
+template <typename T>
+struct AdjAxisArgs {
+    const T *phi;
+    const T *seed_m, *seed_p;
+    T *lam;
+    GridGeom g;
+    int d, c;        // line axis; cross axis or -1
+    int rest[2];     // remaining axes, or -1
+    T inv_dx, dx;
+    int tl, tw;
+};
+
+hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, int scheme, int ham, hipStream_t s);
+hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham, hipStream_t s);
+hipError_t launch_adj_axis_f32(const AdjAxisArgs<float> &a, int scheme, hipStream_t s);
+hipError_t launch_adj_axis_f64(const AdjAxisArgs<double> &a, int scheme, hipStream_t s);
+int adj_seed_blocks(const GridGeom &g);
+// out[k] = sum over blocks of acc[block * kAccCount + k]
+hipError_t launch_acc_reduce(const double *acc, int blocks, double *out, hipStream_t s);
+// x[i] = 0 for i < n (a kernel, not a memset)
+hipError_t launch_zero_f32(float *x, int n, hipStream_t s);
+hipError_t launch_zero_f64(double *x, int n, hipStream_t s);
+hipError_t launch_zero_f64acc(double *x, int n, hipStream_t s);
+// smoothed-volume loss: out[0] = vol * sum s(-phi/eps); grad (nullable) =
+// its derivative; partial holds `blocks` doubles
+hipError_t launch_loss_f32(const float *phi, int n, double eps, double vol, float *grad, double *partial, int blocks,
+                           double *out, hipStream_t s);
+hipError_t launch_loss_f64(const double *phi, int n, double eps, double vol, double *grad, double *partial,
+                           int blocks, double *out, hipStream_t s);
 
 // Dissipation reduction over all nodes (first pass: one partial per block).
 template <typename T>

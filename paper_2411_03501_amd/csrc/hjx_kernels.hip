@@ -11,281 +11,12 @@
 // Layout: row-major, last axis fastest.  The fastest axis runs along the
 // lanes of a wave, so every row load is coalesced; see the stage kernel for
 // the tiling.
-#include "hjx_internal.h"
+#include "hjx_device.h"
 
 namespace hjx {
 namespace {
 
-// ---------------------------------------------------------------- arithmetic
-
-template <typename T>
-struct Arith;
-
-template <>
-struct Arith<float> {
-    // one-ulp reciprocal: the WENO weights only need relative accuracy
-    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-    // floor of the WENO epsilon: 1e-99 is zero in binary32; (1e-18)^2 is normal
-    static constexpr float kEpsFloor = 1e-18f;
-};
-
-template <>
-struct Arith<double> {
-    // hardware reciprocal estimate refined by two Newton-Raphson steps
-    // (r <- r + r (1 - x r)), each of which roughly doubles the correct bits:
-    // a few ulp, against the ten-instruction IEEE division sequence.  The
-    // operands here are sums of squares plus eps >= 1e-99, far from the
-    // exponent range where the estimate needs pre-scaling.
-    static __device__ __forceinline__ double rcp(double x)
-    {
-        double r = __builtin_amdgcn_rcp(x);
-        double e = __builtin_fma(-x, r, 1.0);
-        r = __builtin_fma(r, e, r);
-        e = __builtin_fma(-x, r, 1.0);
-        return __builtin_fma(r, e, r);
-    }
-    static __device__ __forceinline__ double div(double a, double b) { return a * rcp(b); }
-    static constexpr double kEpsFloor = 1e-99;
-};
-
-template <typename T>
-__device__ __forceinline__ T sq(T x) { return x * x; }
-
-template <typename T>
-__device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
-
-template <typename T>
-__device__ __forceinline__ T vabs(T a) { return a < T(0) ? -a : a; }
-
-// ---------------------------------------------------------------- derivatives
-
-template <typename T>
-__device__ __forceinline__ T fmaT(T a, T b, T c) { return __builtin_fma(a, b, c); }
-template <>
-__device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// Load base[i] through a 32-bit byte offset from a uniform base pointer, so
-// the address is one scalar base plus one vector offset (arrays < 4 GiB; the
-// host only launches the direct variant on such arrays).
-template <typename T>
-__device__ __forceinline__ T ld32(const T *base, int i)
-{
-    const unsigned off = (unsigned)i * (unsigned)sizeof(T);
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
-}
-
-// Gather phi at offsets -3..3 along one axis of node idx (coordinate j of n,
-// stride s), filling ghosts: periodic wrap, else linear extrapolation from
-// the two end nodes.
-template <typename T>
-__device__ __forceinline__ void gather7(const T *__restrict__ phi, int idx, int j, int n, int s, bool per, T (&v)[7])
-{
-    if (j >= 3 && j < n - 3) {
-#pragma unroll
-        for (int k = 0; k < 7; ++k) v[k] = ld32(phi, idx + (k - 3) * s);
-        return;
-    }
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        int jj = j + k - 3;
-        if (per) {  // n >= 3 and |jj - j| <= 3, so one wrap lands in [0, n)
-            jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
-            v[k] = ld32(phi, idx + (jj - j) * s);
-        } else if (jj < 0) {
-            const T p0 = ld32(phi, idx - j * s), p1 = ld32(phi, idx + (1 - j) * s);
-            v[k] = fmaT(T(-jj), p0 - p1, p0);
-        } else if (jj >= n) {
-            const T p0 = ld32(phi, idx + (n - 1 - j) * s), p1 = ld32(phi, idx + (n - 2 - j) * s);
-            v[k] = fmaT(T(jj - n + 1), p0 - p1, p0);
-        } else {
-            v[k] = ld32(phi, idx + (k - 3) * s);
-        }
-    }
-}
-
-// WENO5 (Sec. IV-C) on one window of five one-sided differences u0..u4
-// (D+ phi at I-2 .. I+2, I being the interval between nodes I and I+1).
-// The left-biased value of node I+1 reads the window in order; the
-// right-biased value of node I is its mirror image and reads it backwards.
-// The smoothness indicators of the reversed window are those of the window
-// itself, so both directions share S_k, eps and q_k = 1/(S_k + eps)^2, with
-// the weights d = (0.1, 0.6, 0.3) on (q0, q1, q2) forwards and on
-// (q2, q1, q0) backwards.
-//
-// Contraction is off and every fused multiply-add is written out, so the
-// rounding of each value is fixed by the source: a value computed at any call
-// site, by any kernel variant or tile, has the same bits.
-template <typename T>
-__device__ __forceinline__ void weno5_q(T u0, T u1, T u2, T u3, T u4, T &q0, T &q1, T &q2)
-{
-#pragma clang fp contract(off)
-    const T k1312 = T(13.0 / 12.0), k14 = T(0.25);
-    const T A0 = fmaT(T(-2), u1, u0 + u2), B0 = fmaT(T(-4), u1, fmaT(T(3), u2, u0));
-    const T A1 = fmaT(T(-2), u2, u1 + u3), B1 = u1 - u3;
-    const T A2 = fmaT(T(-2), u3, u2 + u4), B2 = fmaT(T(-4), u3, fmaT(T(3), u2, u4));
-    const T s0 = fmaT(k1312 * A0, A0, k14 * B0 * B0);
-    const T s1 = fmaT(k1312 * A1, A1, k14 * B1 * B1);
-    const T s2 = fmaT(k1312 * A2, A2, k14 * B2 * B2);
-    const T m = vmax(vmax(vmax(u0 * u0, u1 * u1), vmax(u2 * u2, u3 * u3)), u4 * u4);
-    const T eps = fmaT(T(1e-6), m, Arith<T>::kEpsFloor);
-    const T r0 = Arith<T>::rcp(s0 + eps), r1 = Arith<T>::rcp(s1 + eps), r2 = Arith<T>::rcp(s2 + eps);
-    q0 = r0 * r0;
-    q1 = r1 * r1;
-    q2 = r2 * r2;
-}
-
-template <typename T>
-__device__ __forceinline__ T weno5_fwd(T u0, T u1, T u2, T u3, T u4, T q0, T q1, T q2)
-{
-#pragma clang fp contract(off)
-    const T c13 = T(1.0 / 3.0), c16 = T(1.0 / 6.0), c56 = T(5.0 / 6.0), c76 = T(7.0 / 6.0), c116 = T(11.0 / 6.0);
-    const T f0 = fmaT(c13, u0, fmaT(-c76, u1, c116 * u2));
-    const T f1 = fmaT(-c16, u1, fmaT(c56, u2, c13 * u3));
-    const T f2 = fmaT(c13, u2, fmaT(c56, u3, -c16 * u4));
-    const T a0 = T(0.1) * q0, a1 = T(0.6) * q1, a2 = T(0.3) * q2;
-    return Arith<T>::div(fmaT(a0, f0, fmaT(a1, f1, a2 * f2)), a0 + a1 + a2);
-}
-
-template <typename T>
-__device__ __forceinline__ T weno5_rev(T u0, T u1, T u2, T u3, T u4, T q0, T q1, T q2)
-{
-#pragma clang fp contract(off)
-    const T c13 = T(1.0 / 3.0), c16 = T(1.0 / 6.0), c56 = T(5.0 / 6.0), c76 = T(7.0 / 6.0), c116 = T(11.0 / 6.0);
-    const T g0 = fmaT(c13, u4, fmaT(-c76, u3, c116 * u2));
-    const T g1 = fmaT(-c16, u3, fmaT(c56, u2, c13 * u1));
-    const T g2 = fmaT(c13, u2, fmaT(c56, u1, -c16 * u0));
-    const T b0 = T(0.1) * q2, b1 = T(0.6) * q1, b2 = T(0.3) * q0;
-    return Arith<T>::div(fmaT(b0, g0, fmaT(b1, g1, b2 * g2)), b0 + b1 + b2);
-}
-
-template <typename T>
-__device__ __forceinline__ void weno5_pair(T u0, T u1, T u2, T u3, T u4, T &fwd, T &rev)
-{
-    T q0, q1, q2;
-    weno5_q(u0, u1, u2, u3, u4, q0, q1, q2);
-    fwd = weno5_fwd(u0, u1, u2, u3, u4, q0, q1, q2);
-    rev = weno5_rev(u0, u1, u2, u3, u4, q0, q1, q2);
-}
-
-// The interval I between nodes I and I+1 along one axis, from v[0..5] = phi
-// at I-2 .. I+3: pm = left-biased derivative of node I+1, pp = right-biased
-// derivative of node I.  Both start from the same divided difference
-// D^1_{I+1/2}; ENO grows the same stencil for both (Sec. IV-B) and only the
-// evaluation point differs; WENO5 uses the same window in both directions.
-template <typename T, int SCHEME>
-__device__ __forceinline__ void interval(const T *v, T inv_dx, T dx, T &pm, T &pp)
-{
-#pragma clang fp contract(off)
-    if constexpr (SCHEME == kSchemeFirst) {
-        pm = pp = (v[3] - v[2]) * inv_dx;
-    } else if constexpr (SCHEME == kSchemeWeno5) {
-        T u[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) u[k] = (v[k + 1] - v[k]) * inv_dx;
-        weno5_pair(u[0], u[1], u[2], u[3], u[4], pm, pp);
-    } else {
-        T d1[5];  // D^1 at (I-2+k)+1/2
-#pragma unroll
-        for (int k = 0; k < 5; ++k) d1[k] = (v[k + 1] - v[k]) * inv_dx;
-        const T h2 = T(0.5) * inv_dx;
-        T d2[5];  // D^2 at node I-2+k, k = 1..4
-#pragma unroll
-        for (int k = 1; k < 5; ++k) d2[k] = (d1[k] - d1[k - 1]) * h2;
-        // ENO2: the smaller |D^2| of D^2_I and D^2_{I+1}; ties go left
-        const bool left = vabs(d2[2]) <= vabs(d2[3]);
-        const T c = left ? d2[2] : d2[3];
-        // Q2'(x_i) = c (2(i-k) - 1) dx with k = I: +c dx at I+1, -c dx at I
-        pm = d1[2] + c * dx;
-        pp = d1[2] - c * dx;
-        if constexpr (SCHEME == kSchemeEno3) {
-            // k* = I-1 after a left choice, else I; candidates D^3 at k*+1/2
-            // and k*+3/2; Q3' multiplier 3m^2 - 6m + 2 with m = i - k*
-            const T h3 = inv_dx * T(1.0 / 3.0);
-            const T lo = left ? (d2[2] - d2[1]) * h3 : (d2[3] - d2[2]) * h3;
-            const T hi = left ? (d2[3] - d2[2]) * h3 : (d2[4] - d2[3]) * h3;
-            const T cs = vabs(lo) <= vabs(hi) ? lo : hi;
-            const T dx2 = dx * dx;
-            pm = pm + cs * (left ? T(2) : T(-1)) * dx2;   // m = 2 or 1 at node I+1
-            pp = pp + cs * (left ? T(-1) : T(2)) * dx2;   // m = 1 or 0 at node I
-        }
-    }
-}
-
-// Both derivative approximations at node j from v[0..6] = phi at j-3 .. j+3:
-// pm from the interval left of the node, pp from the interval right of it,
-// with exactly the arithmetic interval() uses for that half.
-template <typename T, int SCHEME>
-__device__ __forceinline__ void node_derivs(const T *v, T inv_dx, T dx, T &pm, T &pp)
-{
-    if constexpr (SCHEME == kSchemeWeno5) {
-#pragma clang fp contract(off)
-        T u[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) u[k] = (v[k + 1] - v[k]) * inv_dx;
-        T q0, q1, q2;
-        weno5_q(u[0], u[1], u[2], u[3], u[4], q0, q1, q2);
-        pm = weno5_fwd(u[0], u[1], u[2], u[3], u[4], q0, q1, q2);
-        weno5_q(u[1], u[2], u[3], u[4], u[5], q0, q1, q2);
-        pp = weno5_rev(u[1], u[2], u[3], u[4], u[5], q0, q1, q2);
-    } else {
-        T unused;
-        interval<T, SCHEME>(v, inv_dx, dx, pm, unused);
-        interval<T, SCHEME>(v + 1, inv_dx, dx, unused, pp);
-    }
-}
-
-// ---------------------------------------------------------------- Hamiltonians
-
-template <typename T, int D, int HAM>
-__device__ __forceinline__ T ham_value(const StageArgs<T> &a, const int *j, const T *p)
-{
-#pragma clang fp contract(off)
-    if constexpr (HAM == kHamNormal) {  // a |p|
-        T s = T(0);
-#pragma unroll
-        for (int d = 0; d < D; ++d) s = fmaT(p[d], p[d], s);
-        return a.hp[0] * sqrt(s);
-    } else if constexpr (HAM == kHamDubins3) {
-        // -[p1(-v_e + v_p cos th) + p2 v_p sin th + wbar_e |p1 y - p2 x - p3| - wbar_p |p3|]
-        const T x = a.tab.coord[0][j[0]], y = a.tab.coord[1][j[1]];
-        const T c = a.tab.cosv[2][j[2]], sn = a.tab.sinv[2][j[2]];
-        const T ve = a.hp[0], vp = a.hp[1], we = a.hp[2], wp = a.hp[3];
-        const T drift = fmaT(p[0], fmaT(vp, c, -ve), p[1] * (vp * sn));
-        const T arg = fmaT(p[0], y, -fmaT(p[1], x, p[2]));
-        return -fmaT(we, vabs(arg), fmaT(-wp, vabs(p[2]), drift));
-    } else {
-        // -v (p1 cos th + p2 sin th) + wbar |p3| + abar |p4|
-        const T c = a.tab.cosv[2][j[2]], sn = a.tab.sinv[2][j[2]];
-        const T v = a.tab.coord[3][j[3]];
-        return fmaT(-v, fmaT(p[0], c, p[1] * sn), fmaT(a.hp[0], vabs(p[2]), a.hp[1] * vabs(p[3])));
-    }
-}
-
-// LF Hamiltonian (Sec. IV-D) and the stage combination (Sec. V, Sec. VI):
-// L = -(H(x, pbar) - sum_d alpha_d (p+_d - p-_d)/2); the result is L itself
-// (rhs_only) or ca phi_n + cb (phi + dt L), then min with the target.
-template <typename T, int D, int HAM>
-__device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, const T *pm, const T *pp, T center,
-                                          int idx)
-{
-#pragma clang fp contract(off)
-    T pbar[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (pm[d] + pp[d]);
-    T hhat = ham_value<T, D, HAM>(a, j, pbar);
-#pragma unroll
-    for (int d = 0; d < D; ++d) hhat = fmaT(-a.alpha[d], T(0.5) * (pp[d] - pm[d]), hhat);
-    const T L = -hhat;
-    if (a.rhs_only) return L;
-    T res = a.cb * fmaT(a.dt, L, center);
-    if (a.ca != T(0)) res = fmaT(a.ca, ld32(a.phi_n, idx), res);
-    if (a.target) {
-        const T tg = ld32(a.target, idx);
-        res = tg < res ? tg : res;
-    }
-    return res;
-}
+using namespace dev;
 
 // ---------------------------------------------------------------- stage kernel
 //
@@ -308,12 +39,6 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
 // Each interval is evaluated by exactly the same arithmetic whichever thread
 // or tile evaluates it, so results do not depend on the launch shape.
 
-template <typename T>
-__device__ __forceinline__ int wrap_index(int j, int n)
-{
-    j %= n;
-    return j < 0 ? j + n : j;
-}
 
 template <typename T, int D, int SCHEME, int HAM>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)

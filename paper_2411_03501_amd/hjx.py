@@ -68,6 +68,12 @@ SIGNATURES = {
     "hjx_problem_get_tile": ([_P] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
     "hjx_tune": ([_P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hjx_solve": ([_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(Stats)], ctypes.c_int),
+    "hjx_tape_create": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)],
+                        ctypes.c_int),
+    "hjx_tape_destroy": ([_P], ctypes.c_int),
+    "hjx_solve_taped": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], ctypes.c_int),
+    "hjx_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    "hjx_loss_volume": ([_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P], ctypes.c_int),
 }
 
 
@@ -173,6 +179,34 @@ def hjx_solve(handle, phi0_ptr, target_ptr, out_ptr, t0, t1, stream=None, stats=
     return st
 
 
+def hjx_tape_create(handle, t0, t1, ckpt_every, stream=None):
+    t = ctypes.c_void_p()
+    _check(lib().hjx_tape_create(handle, float(t0), float(t1), int(ckpt_every), _stream(stream), ctypes.byref(t)))
+    return t
+
+
+def hjx_tape_destroy(tape):
+    _check(lib().hjx_tape_destroy(tape))
+
+
+def hjx_solve_taped(handle, tape, phi0_ptr, target_ptr, out_ptr, stream=None):
+    st = Stats()
+    _check(lib().hjx_solve_taped(handle, tape, phi0_ptr, target_ptr, out_ptr, _stream(stream), ctypes.byref(st)))
+    return st
+
+
+def hjx_adjoint(handle, tape, g_ptr, dphi0_ptr, dtarget_ptr, stream=None):
+    dp = (ctypes.c_double * 8)()
+    _check(lib().hjx_adjoint(handle, tape, g_ptr, dphi0_ptr, dtarget_ptr, dp, _stream(stream)))
+    return [dp[k] for k in range(8)]
+
+
+def hjx_loss_volume(handle, phi_ptr, eps, grad_ptr, stream=None):
+    v = ctypes.c_double()
+    _check(lib().hjx_loss_volume(handle, phi_ptr, float(eps), ctypes.byref(v), grad_ptr, _stream(stream)))
+    return v.value
+
+
 # ------------------------------------------------------------------ handle wrapper
 
 def descriptors(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3, cfl=0.75,
@@ -259,6 +293,15 @@ class Problem:
         hjx_step(self.handle, self._t(phi, "phi"), self._t(target, "target"), dt, stream)
         return phi
 
+    def tape(self, t1, t0=0.0, ckpt_every=8, stream=None):
+        return Tape(self, t0, t1, ckpt_every, stream)
+
+    def loss_volume(self, phi, eps, grad=True, stream=None):
+        """Smoothed volume of {phi <= 0} and (optionally) its gradient."""
+        g = torch.empty_like(phi) if grad else None
+        v = hjx_loss_volume(self.handle, self._t(phi, "phi"), eps, self._t(g, "grad"), stream)
+        return (v, g) if grad else v
+
     def solve(self, phi0, t1, t0=0.0, target=None, out=None, stream=None):
         """Returns (phi(t1), stats dict)."""
         if out is None:
@@ -266,3 +309,69 @@ class Problem:
         st = hjx_solve(self.handle, self._t(phi0, "phi0"), self._t(target, "target"), self._t(out, "phi_out"),
                        t0, t1, stream)
         return out, st.as_dict()
+
+
+class Tape:
+    """Checkpoints of one solve, for hjx_adjoint."""
+
+    def __init__(self, problem, t0, t1, ckpt_every=8, stream=None):
+        self.problem = problem
+        self.handle = None
+        self.handle = hjx_tape_create(problem.handle, t0, t1, ckpt_every, stream)
+        self.has_target = False
+
+    def close(self):
+        if self.handle is not None:
+            hjx_tape_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, phi0, target=None, out=None, stream=None):
+        P = self.problem
+        if out is None:
+            out = torch.empty_like(phi0)
+        st = hjx_solve_taped(P.handle, self.handle, P._t(phi0, "phi0"), P._t(target, "target"),
+                             P._t(out, "phi_out"), stream)
+        self.has_target = target is not None
+        return out, st.as_dict()
+
+    def adjoint(self, dL_dphiT, stream=None):
+        """Returns (dL/dphi0, dL/dtarget or None, dL/dparams list of 8)."""
+        P = self.problem
+        g0 = torch.empty_like(dL_dphiT)
+        gt = torch.empty_like(dL_dphiT) if self.has_target else None
+        dp = hjx_adjoint(P.handle, self.handle, P._t(dL_dphiT, "dL_dphiT"), P._t(g0, "dL_dphi0"),
+                         P._t(gt, "dL_dtarget"), stream)
+        return g0, gt, dp
+
+
+class HjxSolve(torch.autograd.Function):
+    """phi(t1) = solve(phi0) with min-with-target against phi0 itself (the
+    reachable-tube setting) or no target; backward through hjx_adjoint.
+    Usage: HjxSolve.apply(phi0, problem, t1, with_target, ckpt_every).
+    The gradient of the Hamiltonian parameters of the last backward call is
+    left in problem.param_grad."""
+
+    @staticmethod
+    def forward(ctx, phi0, problem, t1, with_target=True, ckpt_every=8):
+        tape = problem.tape(t1, 0.0, ckpt_every)
+        phi0c = phi0.detach().contiguous()
+        out, _ = tape.solve(phi0c, target=phi0c if with_target else None)
+        ctx.tape = tape
+        ctx.phi0 = phi0c  # the target must stay alive until backward
+        ctx.with_target = with_target
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        g0, gt, dp = ctx.tape.adjoint(g.contiguous())
+        ctx.tape.problem.param_grad = dp
+        if ctx.with_target:
+            g0 = g0 + gt
+        ctx.tape.close()
+        return g0, None, None, None, None

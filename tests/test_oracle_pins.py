@@ -552,3 +552,55 @@ def test_time_reversal_of_sign_convention():
     r = np.sqrt(X * X + Y * Y)
     m = (r > 0.3) & (np.abs(X) < 0.8) & (np.abs(Y) < 0.8)
     assert np.abs(L[m] + 1.0).max() < 1e-3
+
+
+# --------------------------------------------------------------------------
+# the complex-step build (directional derivatives for the gradient checks)
+
+def _loss(P, phi, eps):
+    vol = np.prod([O.grid(P, d)[0] for d in range(P.dim)])
+    return vol * np.sum(1.0 / (1.0 + np.exp(phi / eps)))
+
+
+@pytest.mark.parametrize("ham", ["dubins3_pe", "normal"])
+def test_complex_step_matches_real_solve_and_central_differences(ham):
+    if ham == "dubins3_pe":
+        w = inputs.DUBINS3D.with_(n=(13, 11, 9), t1=0.3)
+        params = np.array(w.params)
+        dparams = np.array([0.3, -0.2, 0.5, 0.7])
+    else:
+        w = inputs.NORMAL2D.with_(n=(21, 19), scheme="weno5", rk=3, t1=0.2)
+        params = np.array(w.params)
+        dparams = np.array([1.0])
+    P = O.make_problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, params, w.scheme, w.rk, w.cfl)
+    # a symmetric surface puts nodes exactly on kinks (ties of the WENO max,
+    # |pbar| = 0 at the centre), where one-sided and central differences part
+    # ways; a small smooth perturbation moves every node off them
+    phi0 = inputs.initial_surface(w) + 0.05 * inputs.smooth_field(w.n, 62)
+    eps = 1.5 * max(O.grid(P, 0)[0], O.grid(P, 1)[0])
+    tgt = w.with_target
+    loss, dloss, steps = O.cs_solve_loss(P, phi0, w.t1, dphi0=np.zeros_like(phi0), with_target=tgt, eps_h=eps)
+    ref, n, _ = O.solve(P, phi0, w.t1, target=phi0 if tgt else None)
+    assert n == steps
+    assert abs(loss - _loss(P, ref, eps)) <= 1e-12 * abs(loss)
+    assert dloss == 0.0
+    # directional derivative in phi0 and in the parameters against central differences
+    delta = inputs.smooth_field(w.n, 61)
+    for dphi0, dpar in ((delta, None), (None, dparams)):
+        _, cs, _ = O.cs_solve_loss(P, phi0, w.t1, dphi0=dphi0, dparams=dpar, with_target=tgt, eps_h=eps)
+        # the scheme is only piecewise smooth: a difference quotient whose
+        # step straddles a kink is off, so central differences must reach the
+        # complex-step value as the step shrinks, not at every step
+        errs = []
+        for hstep in (1e-5, 1e-6, 1e-7):
+            vals = []
+            for sgn in (1, -1):
+                pr = params + sgn * hstep * (dpar if dpar is not None else 0)
+                Q = O.make_problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, pr, w.scheme, w.rk, w.cfl)
+                f0 = phi0 + sgn * hstep * (dphi0 if dphi0 is not None else 0)
+                out, m, _ = O.solve(Q, f0, w.t1, target=f0 if tgt else None)
+                assert m == steps
+                vals.append(_loss(Q, out, eps))
+            fd = (vals[0] - vals[1]) / (2 * hstep)
+            errs.append(abs(cs - fd) / max(abs(fd), 1e-3))
+        assert min(errs) <= 1e-6, (cs, errs)
