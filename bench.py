@@ -151,6 +151,60 @@ def run_adjoint(w, reps=2):
             "central_diff": "FP64 solves, steps 1e-5 (relative for v_e), phi0 direction independent of theta"}
 
 
+def run_batch(reps=2):
+    """The uneven 256-member batch (2-D level sets moving in the normal
+    direction and 3-D pursuit-evasion games, 64..161 nodes per axis, 16..64
+    RK3 steps each, FP32): one batched solve (persistent stage launches
+    replayed from a hipGraph) against a loop of per-member hjx_solve calls
+    over the same members, inputs and horizons."""
+    import torch
+
+    from paper_2411_03501_amd import hjx, inputs
+
+    ws = inputs.batch256()
+    probs = [hjx.Problem.from_workload(w, "f32") for w in ws]
+    phi0 = [torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=torch.float32) for w in ws]
+    t1 = [(w.steps - 0.5) * P.dissipation()[1] for w, P in zip(ws, probs)]
+    target = [x if w.with_target else None for x, w in zip(phi0, ws)]
+    out = [torch.empty_like(x) for x in phi0]
+    updates = sum(w.points * w.steps for w in ws)
+    log(f"  batch256: {sum(w.points for w in ws) / 1e6:.1f} M nodes, {updates / 1e9:.2f} G updates per solve")
+
+    def singles():
+        for P, x, t, g, o in zip(probs, phi0, t1, target, out):
+            P.solve(x, t, target=g, out=o)
+
+    singles()   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        singles()
+    torch.cuda.synchronize()
+    single_s = (time.perf_counter() - t0) / reps
+
+    B = hjx.Batch(probs)
+    shape, tuned_ms = B.tune(phi0, t1, target=target, out=out, reps=1)
+    log(f"  tuned batch shape {shape}: {tuned_ms:.1f} ms per horizon")
+    B.solve(phi0, t1, target=target, out=out)   # warm-up
+    torch.cuda.synchronize()
+    graph_ms = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = B.solve(phi0, t1, target=target, out=out)
+        graph_ms.append(st[0]["elapsed_ms"])
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / reps
+    log(f"  per-member solves {single_s * 1e3:.1f} ms, batched {batch_s * 1e3:.1f} ms "
+        f"(graph {min(graph_ms):.1f} ms)")
+    B.close()
+    for P in probs:
+        P.close()
+    return {"members": len(ws), "nodes": sum(w.points for w in ws), "updates_per_solve": updates,
+            "batched_updates_per_s": updates / batch_s, "per_member_updates_per_s": updates / single_s,
+            "batched_ms": batch_s * 1e3, "per_member_ms": single_s * 1e3, "graph_replay_ms": min(graph_ms),
+            "speedup": single_s / batch_s, "shape": {"item_nodes": shape[0], "blocks": shape[1]}}
+
+
 def run_cpu_baseline(w, budget_s=15.0):
     """The oracle as it stands, on the host's cores, for a bounded number of
     RK steps of the same workload."""
@@ -238,6 +292,9 @@ def main():
             "stage_kernel_us": k4 * 1e6,
             "alu_frac": alg_ops_per_point(w4.scheme, w4.ham, w4.dim) * w4.points / k4 / 1e12 / PEAK_VALU_TOPS,
             "hbm_alg_frac": stage_bytes_per_point(w4.rk, w4.with_target, 4) * w4.points / k4 / 1e9 / PEAK_HBM_GBS}
+
+        log("batch256 f32: batched vs per-member")
+        extra["batch256"] = run_batch()
 
         log("adjoint: dubins3d_81 f32")
         extra["adjoint"] = run_adjoint(inputs.DUBINS3D_81)

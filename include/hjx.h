@@ -251,6 +251,54 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *tape, const void *dL_dphiT, voi
 hjx_status hjx_loss_volume(hjx_problem *p, const void *phi, double eps, double *loss, void *dL_dphi,
                            void *stream);
 
+/* ------------------------------------------------------------------ batch
+ * Many problems solved together (no counterpart in the paper: for every
+ * member the same solve as hjx_solve from t0 = 0, scheduled as one).  The
+ * members may differ in grid, sizes, Hamiltonian and parameters but share
+ * dtype, derivative scheme and RK order.  Each RK stage of each global step
+ * is one launch of persistent blocks over a work list of (member, run of
+ * item_nodes nodes) items; members are ordered by decreasing step count, so
+ * a step launches only over those still stepping, and every member keeps
+ * its own CFL step and clamped last step.  The launches of one set of
+ * horizons are captured once in a hipGraph and replayed while the step
+ * counts stay the same.  Results are bit-for-bit those of hjx_solve on each
+ * member.  The batch borrows each member's stage workspace: members must
+ * outlive the batch, appear once in it, and not be stepped otherwise while
+ * a batch solve is in flight.  Member arrays must be under 4 GiB. */
+typedef struct hjx_batch hjx_batch;
+
+/* Create a batch of n >= 1 problems (host array of handles, each used once).
+ * Runs the dissipation reduction of every member and fixes its CFL step
+ * (synchronises `stream`).  The launch shape defaults to the resident
+ * block count and 1024-node items. */
+hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *stream, hjx_batch **out);
+hjx_status hjx_batch_destroy(hjx_batch *b);
+
+/* Launch shape: item_nodes (a multiple of 256, at most 2^20) nodes per work
+ * item, `blocks` persistent blocks per launch (1..blocks_max, the count
+ * resident on the whole device).  Results do not depend on it. */
+hjx_status hjx_batch_set_shape(hjx_batch *b, int32_t item_nodes, int32_t blocks);
+hjx_status hjx_batch_get_shape(const hjx_batch *b, int32_t *item_nodes, int32_t *blocks, int32_t *blocks_max);
+
+/* Solve every member i from 0 to t1[i] >= 0 (host array of n doubles; at
+ * most 2^20 steps each).  phi0, phi_out: host arrays of n device pointers
+ * (phi_out[i] may be phi0[i]); target: NULL, or a host array of n device
+ * pointers each NULL or a target that is not phi_out[i].  stats: NULL or a
+ * host array of n records (elapsed_ms is the whole batch's).  Synchronises
+ * `stream`.  Returns HJX_ERR_NONFINITE without stepping if some phi0 holds
+ * NaN/Inf, and after the solve if some result does (the lowest such member
+ * is named by hjx_last_error). */
+hjx_status hjx_batch_solve(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
+                           const double *t1, void *stream, hjx_stats *stats);
+
+/* Autotuner of the batch launch shape: runs hjx_batch_solve with the given
+ * arguments, then times `reps` replays of the horizon per candidate shape
+ * (items of 256, 1024 and 4096 nodes by 1, 2 and 4 blocks per compute unit
+ * and blocks_max) and keeps the fastest.  phi_out is overwritten.
+ * best_ms (optional, host): the winner's mean replay time. */
+hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
+                          const double *t1, int32_t reps, void *stream, double *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

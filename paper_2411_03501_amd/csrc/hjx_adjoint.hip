@@ -169,18 +169,19 @@ hipError_t launch_seed(const AdjSeedArgs<T> &a, int scheme, int ham, hipStream_t
 
 // LDS of one block: phi at l0-5 .. l0+tl+4, the two seeds at l0-3 .. l0+tl+2
 // and the five difference adjoints of each interval l0-3 .. l0+tl+1.
-template <typename T>
-__device__ __forceinline__ int lds_at(bool lx, int pos, int col, int npos, int tw)
+template <bool LX>
+__device__ __forceinline__ int lds_at(int pos, int col, int npos, int tw)
 {
-    return lx ? col * npos + pos : pos * tw + col;
+    return LX ? col * npos + pos : pos * tw + col;
 }
 
-template <typename T, int SCHEME>
+// LX: the line axis is the fastest axis and runs along the lanes
+template <typename T, int SCHEME, bool LX>
 __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
 {
     extern __shared__ unsigned char smem_raw[];
     const int tl = a.tl, tw = a.tw;
-    const bool lx = a.d == a.g.dim - 1;  // the line runs along the lanes
+    constexpr bool lx = LX;
     const int ip = lx ? threadIdx.x : threadIdx.y;
     const int ic = lx ? threadIdx.y : threadIdx.x;
     const int NP = tl + 10, NS = tl + 6, NI = tl + 5;
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
     };
 
     // stage phi and the seeds of this axis
-    for (int p = ip; p < NP; p += tl) PH[lds_at<T>(lx, p, ic, NP, tw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
+    for (int p = ip; p < NP; p += tl) PH[lds_at<LX>(p, ic, NP, tw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
     for (int p = ip; p < NS; p += tl) {
         int g = l0 - 3 + p;
         T m = T(0), pl = T(0);
@@ -228,8 +229,8 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
                 pl = a.seed_p[base + g * sd];
             }
         }
-        SM[lds_at<T>(lx, p, ic, NS, tw)] = m;
-        SP[lds_at<T>(lx, p, ic, NS, tw)] = pl;
+        SM[lds_at<LX>(p, ic, NS, tw)] = m;
+        SP[lds_at<LX>(p, ic, NS, tw)] = pl;
     }
     __syncthreads();
 
@@ -252,13 +253,13 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
         if (c0 + cc < nc) {
             T v[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) v[k] = PH[lds_at<T>(lx, iv + k, cc, NP, tw)];
-            const T gm = SM[lds_at<T>(lx, iv + 1, cc, NS, tw)];  // left-biased seed of node I+1
-            const T gp = SP[lds_at<T>(lx, iv, cc, NS, tw)];      // right-biased seed of node I
+            for (int k = 0; k < 6; ++k) v[k] = PH[lds_at<LX>(iv + k, cc, NP, tw)];
+            const T gm = SM[lds_at<LX>(iv + 1, cc, NS, tw)];  // left-biased seed of node I+1
+            const T gp = SP[lds_at<LX>(iv, cc, NS, tw)];      // right-biased seed of node I
             interval_vjp<T, SCHEME>(v, a.inv_dx, a.dx, gm, gp, ub);
         }
 #pragma unroll
-        for (int r = 0; r < 5; ++r) UB[lds_at<T>(lx, iv * 5 + r, cc, NI * 5, tw)] = ub[r];
+        for (int r = 0; r < 5; ++r) UB[lds_at<LX>(iv * 5 + r, cc, NI * 5, tw)] = ub[r];
     }
     __syncthreads();
 
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
             const int iv = m + 2 - r - (l0 - 3);
-            if (iv >= 0 && iv < NI) s += UB[lds_at<T>(lx, iv * 5 + r, ic, NI * 5, tw)];
+            if (iv >= 0 && iv < NI) s += UB[lds_at<LX>(iv * 5 + r, ic, NI * 5, tw)];
         }
         return s;
     };
@@ -310,13 +311,21 @@ hipError_t launch_axis(const AdjAxisArgs<T> &a, int scheme, hipStream_t s)
     const dim3 grid(((nd + a.tl - 1) / a.tl) * ((nc + a.tw - 1) / a.tw), rest);
     const dim3 block(lx ? a.tl : a.tw, lx ? a.tw : a.tl);
     const size_t lds = sizeof(T) * (size_t)a.tw * ((a.tl + 10) + 2 * (a.tl + 6) + 5 * (a.tl + 5));
+#define HJX_AXIS_LAUNCH(S)                                                                \
+    do {                                                                                  \
+        if (lx)                                                                           \
+            hipLaunchKernelGGL((adj_axis_kernel<T, S, true>), grid, block, lds, s, a);    \
+        else                                                                              \
+            hipLaunchKernelGGL((adj_axis_kernel<T, S, false>), grid, block, lds, s, a);   \
+    } while (0)
     switch (scheme) {
-    case kSchemeFirst: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeFirst>), grid, block, lds, s, a); break;
-    case kSchemeEno2: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeEno2>), grid, block, lds, s, a); break;
-    case kSchemeEno3: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeEno3>), grid, block, lds, s, a); break;
-    case kSchemeWeno5: hipLaunchKernelGGL((adj_axis_kernel<T, kSchemeWeno5>), grid, block, lds, s, a); break;
+    case kSchemeFirst: HJX_AXIS_LAUNCH(kSchemeFirst); break;
+    case kSchemeEno2: HJX_AXIS_LAUNCH(kSchemeEno2); break;
+    case kSchemeEno3: HJX_AXIS_LAUNCH(kSchemeEno3); break;
+    case kSchemeWeno5: HJX_AXIS_LAUNCH(kSchemeWeno5); break;
     default: return hipErrorInvalidValue;
     }
+#undef HJX_AXIS_LAUNCH
     return hipGetLastError();
 }
 

@@ -1098,3 +1098,367 @@ hjx_status hjx_loss_volume(hjx_problem *p, const void *phi, double eps, double *
 }
 
 }  // extern "C"
+
+// ==================================================================== batch (host)
+
+struct hjx_batch {
+    int n = 0;
+    int device = 0;
+    int dtype = 0, deriv = 0, rk = 0;
+    size_t elem = 0, inst_bytes = 0;
+    std::vector<hjx_problem *> probs;
+    std::vector<double> alpha;        // n * kMaxDim
+    std::vector<double> dt;           // CFL step of each problem
+    void *dinst = nullptr;            // device descriptors (sorted order)
+    void *hinst = nullptr;            // pinned host copy
+    int *dflag = nullptr;             // device, per sorted instance
+    int *hflag = nullptr;             // pinned
+    int item_nodes = 1024, blocks = 0, blocks_max = 0;
+    // schedule behind the captured graph
+    std::vector<int64_t> steps;       // per problem
+    std::vector<double> dt_last;      // per problem
+    std::vector<int> order;           // sorted position -> problem
+    std::vector<int> item0;           // sorted position -> first item; n+1 entries
+    int64_t max_steps = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_ok = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int64_t kBatchMaxSteps = 1 << 20;
+
+void batch_drop_graph(hjx_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_ok = false;
+}
+
+void batch_release(hjx_batch *b)
+{
+    if (!b) return;
+    batch_drop_graph(b);
+    if (b->dinst) (void)hipFree(b->dinst);
+    if (b->hinst) (void)hipHostFree(b->hinst);
+    if (b->dflag) (void)hipFree(b->dflag);
+    if (b->hflag) (void)hipHostFree(b->hflag);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete b;
+}
+
+// one whole-batch or stage launch
+hipError_t batch_launch(const hjx_batch *b, int n_active, int s, int stage, hipStream_t st)
+{
+    const int items = b->item0[n_active];
+    if (b->dtype == HJX_F32) {
+        BatchArgs<float> a{static_cast<const BatchInst<float> *>(b->dinst), b->dflag, n_active, items, s, stage,
+                           b->rk, b->item_nodes};
+        return launch_batch_f32(a, b->deriv, b->blocks, st);
+    }
+    BatchArgs<double> a{static_cast<const BatchInst<double> *>(b->dinst), b->dflag, n_active, items, s, stage,
+                        b->rk, b->item_nodes};
+    return launch_batch_f64(a, b->deriv, b->blocks, st);
+}
+
+// the launches of one horizon: copy in, rk stages of every global step over
+// the instances still active, copy out (RK1)
+hipError_t batch_enqueue(const hjx_batch *b, hipStream_t st)
+{
+    hipError_t e = batch_launch(b, b->n, 0, kBatchCopyIn, st);
+    int active = b->n;
+    for (int64_t s = 0; s < b->max_steps && e == hipSuccess; ++s) {
+        while (active > 0 && b->steps[b->order[active - 1]] <= s) --active;
+        for (int k = 0; k < b->rk && e == hipSuccess; ++k) e = batch_launch(b, active, (int)s, k, st);
+    }
+    if (e == hipSuccess && b->rk == 1) e = batch_launch(b, b->n, 0, kBatchCopyOut, st);
+    return e;
+}
+
+hjx_status batch_build_graph(hjx_batch *b)
+{
+    batch_drop_graph(b);
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = batch_enqueue(b, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(HJX_ERR_DEVICE, "batch graph capture: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_ok = true;
+    return HJX_OK;
+}
+
+template <typename T>
+void batch_descriptors(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out)
+{
+    BatchInst<T> *I = static_cast<BatchInst<T> *>(b->hinst);
+    for (int k = 0; k < b->n; ++k) {
+        const int i = b->order[k];
+        const hjx_problem *p = b->probs[i];
+        BatchInst<T> x{};
+        x.st = stage_args<T>(p, &b->alpha[(size_t)i * kMaxDim]);
+        x.phi0 = static_cast<const T *>(phi0[i]);
+        x.target = target ? static_cast<const T *>(target[i]) : nullptr;
+        x.phi = static_cast<T *>(phi_out[i]);
+        x.ws0 = static_cast<T *>(p->ws[0]);
+        x.ws1 = static_cast<T *>(p->ws[1]);
+        x.dt = T(b->dt[i]);
+        x.dt_last = T(b->dt_last[i]);
+        x.steps = (int)b->steps[i];
+        x.ham = p->ham.kind;
+        x.total = (int)p->total;
+        x.item0 = b->item0[k];
+        I[k] = x;
+    }
+}
+
+// the schedule of every instance for horizons t1; (re)builds the order,
+// the work list and the graph when they change
+hjx_status batch_schedule(hjx_batch *b, const double *t1)
+{
+    std::vector<int64_t> steps(b->n);
+    std::vector<double> last(b->n);
+    int64_t mx = 0;
+    for (int i = 0; i < b->n; ++i) {
+        if (!std::isfinite(t1[i]) || !(t1[i] >= 0.0))
+            return fail(HJX_ERR_INVALID_ARG, "t1[%d] = %g is not finite and >= 0", i, t1[i]);
+        if (t1[i] > 0.0 && (double)kBatchMaxSteps * b->dt[i] < t1[i])
+            return fail(HJX_ERR_UNSUPPORTED, "instance %d needs more than %lld steps", i, (long long)kBatchMaxSteps);
+        schedule(0.0, t1[i], b->dt[i], &steps[i], &last[i]);
+        mx = std::max(mx, steps[i]);
+    }
+    b->dt_last = last;
+    if (b->graph_ok && steps == b->steps) return HJX_OK;
+    b->steps = steps;
+    b->max_steps = mx;
+    b->order.resize(b->n);
+    for (int i = 0; i < b->n; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return steps[x] > steps[y]; });
+    b->item0.assign(b->n + 1, 0);
+    int64_t acc = 0;
+    for (int k = 0; k < b->n; ++k) {
+        b->item0[k] = (int)acc;
+        acc += (b->probs[b->order[k]]->total + b->item_nodes - 1) / b->item_nodes;
+    }
+    if (acc > INT32_MAX) return fail(HJX_ERR_UNSUPPORTED, "batch work list too long");
+    b->item0[b->n] = (int)acc;
+    return batch_build_graph(b);
+}
+
+// flags of the last check -> first bad problem index or -1; synchronises
+hjx_status batch_check(hjx_batch *b, int mode, hipStream_t s, int *first_bad)
+{
+    HIP_TRY(hipMemsetAsync(b->dflag, 0, sizeof(int) * b->n, s));
+    HIP_TRY(batch_launch(b, b->n, 0, mode, s));
+    HIP_TRY(hipMemcpyAsync(b->hflag, b->dflag, sizeof(int) * b->n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *first_bad = -1;
+    for (int k = 0; k < b->n; ++k)
+        if (b->hflag[k] && (*first_bad < 0 || b->order[k] < *first_bad)) *first_bad = b->order[k];
+    return HJX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *stream, hjx_batch **out)
+{
+    if (!out) return fail(HJX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !problems) return fail(HJX_ERR_INVALID_ARG, "need n >= 1 problems");
+    for (int i = 0; i < n; ++i)
+        if (!problems[i]) return fail(HJX_ERR_INVALID_ARG, "problems[%d] is NULL", i);
+    const hjx_problem *p0 = problems[0];
+    {
+        std::vector<const hjx_problem *> seen(problems, problems + n);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return fail(HJX_ERR_INVALID_ARG, "a problem appears twice in the batch");
+    }
+    for (int i = 0; i < n; ++i) {
+        const hjx_problem *p = problems[i];
+        if (p->scheme.dtype != p0->scheme.dtype || p->scheme.deriv != p0->scheme.deriv ||
+            p->scheme.rk != p0->scheme.rk)
+            return fail(HJX_ERR_INVALID_ARG, "problems[%d]: every problem of a batch needs the same dtype, "
+                        "derivative scheme and RK order", i);
+        if (p->device != p0->device) return fail(HJX_ERR_INVALID_ARG, "problems[%d] is on another device", i);
+        if (!direct_ok(geometry(p), p->elem))
+            return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: arrays of 4 GiB or more", i);
+    }
+    hjx_batch *b = new (std::nothrow) hjx_batch;
+    if (!b) return fail(HJX_ERR_OOM, "host allocation failed");
+    b->n = n;
+    b->device = p0->device;
+    b->dtype = p0->scheme.dtype;
+    b->deriv = p0->scheme.deriv;
+    b->rk = p0->scheme.rk;
+    b->elem = p0->elem;
+    b->inst_bytes = b->dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
+    b->probs.assign(problems, problems + n);
+    b->alpha.assign((size_t)n * kMaxDim, 0.0);
+    b->dt.assign(n, 0.0);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+        hjx_status st = device_alpha(b->probs[i], s, &b->alpha[(size_t)i * kMaxDim]);
+        if (st != HJX_OK) {
+            batch_release(b);
+            return st;
+        }
+        b->dt[i] = cfl_dt(b->probs[i], &b->alpha[(size_t)i * kMaxDim]);
+    }
+    int cus = 0;
+    hipError_t e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device)) != hipSuccess ||
+        (e = hipMalloc(&b->dinst, b->inst_bytes * n)) != hipSuccess ||
+        (e = hipHostMalloc(&b->hinst, b->inst_bytes * n, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&b->dflag), sizeof(int) * n)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&b->hflag), sizeof(int) * n, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreate(&b->ev[0])) != hipSuccess || (e = hipEventCreate(&b->ev[1])) != hipSuccess) {
+        batch_release(b);
+        return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "batch allocation: %s",
+                    hipGetErrorString(e));
+    }
+    const int per_cu = batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv);
+    b->blocks_max = std::max(1, cus) * per_cu;
+    b->blocks = b->blocks_max;
+    *out = b;
+    return ok();
+}
+
+hjx_status hjx_batch_destroy(hjx_batch *b)
+{
+    batch_release(b);
+    return ok();
+}
+
+hjx_status hjx_batch_set_shape(hjx_batch *b, int32_t item_nodes, int32_t blocks)
+{
+    if (!b) return fail(HJX_ERR_INVALID_ARG, "NULL batch");
+    if (item_nodes < 256 || item_nodes > (1 << 20) || item_nodes % 256)
+        return fail(HJX_ERR_INVALID_ARG, "item_nodes %d: a multiple of 256 in [256, 2^20]", item_nodes);
+    if (blocks < 1 || blocks > b->blocks_max)
+        return fail(HJX_ERR_INVALID_ARG, "blocks %d: in [1, %d] (resident blocks)", blocks, b->blocks_max);
+    if (item_nodes != b->item_nodes || blocks != b->blocks) batch_drop_graph(b);
+    b->item_nodes = item_nodes;
+    b->blocks = blocks;
+    return ok();
+}
+
+hjx_status hjx_batch_get_shape(const hjx_batch *b, int32_t *item_nodes, int32_t *blocks, int32_t *blocks_max)
+{
+    if (!b) return fail(HJX_ERR_INVALID_ARG, "NULL batch");
+    if (item_nodes) *item_nodes = b->item_nodes;
+    if (blocks) *blocks = b->blocks;
+    if (blocks_max) *blocks_max = b->blocks_max;
+    return ok();
+}
+
+hjx_status hjx_batch_solve(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
+                           const double *t1, void *stream, hjx_stats *stats)
+{
+    if (!b || !phi0 || !phi_out || !t1) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    for (int i = 0; i < b->n; ++i) {
+        if (!phi0[i] || !phi_out[i]) return fail(HJX_ERR_INVALID_ARG, "phi0[%d] or phi_out[%d] is NULL", i, i);
+        if (target && target[i] && target[i] == phi_out[i])
+            return fail(HJX_ERR_INVALID_ARG, "target[%d] aliases phi_out[%d]", i, i);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hjx_status st = batch_schedule(b, t1);
+    if (st != HJX_OK) return st;
+    if (b->dtype == HJX_F32) batch_descriptors<float>(b, phi0, target, phi_out);
+    else batch_descriptors<double>(b, phi0, target, phi_out);
+    HIP_TRY(hipMemcpyAsync(b->dinst, b->hinst, b->inst_bytes * b->n, hipMemcpyHostToDevice, s));
+
+    int bad = -1;
+    if ((st = batch_check(b, kBatchCheckIn, s, &bad)) != HJX_OK) return st;
+    if (bad >= 0) return fail(HJX_ERR_NONFINITE, "phi0[%d] holds NaN or Inf", bad);
+
+    HIP_TRY(hipEventRecord(b->ev[0], s));
+    HIP_TRY(hipGraphLaunch(b->exec, s));
+    HIP_TRY(hipEventRecord(b->ev[1], s));
+
+    if ((st = batch_check(b, kBatchCheckOut, s, &bad)) != HJX_OK) return st;
+    if (stats) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+        for (int i = 0; i < b->n; ++i) {
+            const hjx_problem *p = b->probs[i];
+            hjx_stats &x = stats[i];
+            x.steps = b->steps[i];
+            x.dt = b->dt[i];
+            x.dt_last = b->steps[i] ? b->dt_last[i] : 0.0;
+            x.t_final = t1[i];
+            for (int d = 0; d < kMaxDim; ++d) x.alpha[d] = b->alpha[(size_t)i * kMaxDim + d];
+            x.elapsed_ms = ms;  // the whole batch
+            const double f = (double)p->total * (double)p->elem;
+            double per_step = b->rk == 1 ? 2.0 : (b->rk == 2 ? 5.0 : 8.0);
+            if (target && target[i]) per_step += 1.0;
+            x.alg_bytes = per_step * f * (double)b->steps[i];
+        }
+    }
+    if (bad >= 0) return fail(HJX_ERR_NONFINITE, "the solution of instance %d holds NaN or Inf", bad);
+    return ok();
+}
+
+hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
+                          const double *t1, int32_t reps, void *stream, double *best_ms)
+{
+    if (!b) return fail(HJX_ERR_INVALID_ARG, "NULL batch");
+    if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cus = std::max(1, b->blocks_max / std::max(1, batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv)));
+    std::vector<std::pair<int, int>> cand;
+    for (int items : {256, 1024, 4096}) {
+        for (int per_cu : {1, 2, 4}) {
+            const int blocks = per_cu * cus;
+            if (blocks < b->blocks_max) cand.push_back({items, blocks});
+        }
+        cand.push_back({items, b->blocks_max});
+    }
+    if (cand.empty()) cand.push_back({b->item_nodes, b->blocks_max});
+    const bool verbose = std::getenv("HJX_TUNE_VERBOSE") != nullptr;
+    double best = INFINITY;
+    std::pair<int, int> win = cand[0];
+    for (const auto &c : cand) {
+        hjx_status st = hjx_batch_set_shape(b, c.first, c.second);
+        if (st != HJX_OK) return st;
+        if ((st = hjx_batch_solve(b, phi0, target, phi_out, t1, stream, nullptr)) != HJX_OK) return st;  // capture
+        double total = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            HIP_TRY(hipEventRecord(b->ev[0], s));
+            HIP_TRY(hipGraphLaunch(b->exec, s));
+            HIP_TRY(hipEventRecord(b->ev[1], s));
+            HIP_TRY(hipEventSynchronize(b->ev[1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            total += ms;
+        }
+        const double mean = total / reps;
+        if (verbose) std::fprintf(stderr, "hjx_batch_tune items=%d blocks=%d: %.3f ms\n", c.first, c.second, mean);
+        if (mean < best) {
+            best = mean;
+            win = c;
+        }
+    }
+    hjx_status st = hjx_batch_set_shape(b, win.first, win.second);
+    if (st != HJX_OK) return st;
+    if (best_ms) *best_ms = best;
+    return ok();
+}
+
+}  // extern "C"

@@ -452,5 +452,25 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
     return res;
 }
 
+// One node of the direct variant: gather every axis through the caches,
+// both derivative halves at the node, LF Hamiltonian, stage combination.
+template <typename T, int D, int SCHEME, int HAM>
+__device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
+{
+    int idx = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) idx += j[d] * a.g.stride[d];
+    T pm[D], pp[D], center = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        T v[7];
+        gather7(a.phi_in, idx, j[d], a.g.n[d], a.g.stride[d], (a.g.periodic >> d) & 1u, v);
+        center = v[3];
+        node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
+    }
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
+        stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+}
+
 }  // namespace dev
 }  // namespace hjx

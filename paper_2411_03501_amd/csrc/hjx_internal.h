@@ -115,6 +115,46 @@ struct AdjAxisArgs {
     int tl, tw;
 };
 
+// ---------------------------------------------------------------- batch
+// One instance of a batched solve.  Its solution lives in phi (the caller's
+// output array); ws0 and ws1 are its stage buffers (ws1 for RK3 only).
+template <typename T>
+struct BatchInst {
+    StageArgs<T> st;   // geometry, tables, alpha, parameters (stage pointers set in the kernel)
+    const T *phi0;     // initial data, copied into phi first
+    const T *target;   // nullable
+    T *phi, *ws0, *ws1;
+    T dt, dt_last;     // CFL step; the last (clamped) step
+    int steps;         // RK steps of this instance
+    int ham;
+    int total;         // nodes
+    int item0;         // first work item of this instance
+};
+
+// Batch launch modes (BatchArgs::stage): RK stages are 0..rk-1; the others
+// are whole-batch passes.
+enum : int {
+    kBatchCopyIn = -1,     // phi = phi0
+    kBatchCopyOut = -2,    // RK1 with an odd step count: phi = ws0
+    kBatchCheckIn = -3,    // flags[k] = 1 if phi0 of instance k holds NaN/Inf
+    kBatchCheckOut = -4    // the same for phi
+};
+
+// One launch: `items` work items (item_nodes consecutive nodes of one
+// instance each) of the first n_active instances (instances sorted by
+// decreasing step count), for stage `stage` of global step s.
+template <typename T>
+struct BatchArgs {
+    const BatchInst<T> *inst;
+    int *flags;
+    int n_active, items, s, stage, rk, item_nodes;
+};
+
+hipError_t launch_batch_f32(const BatchArgs<float> &a, int scheme, int blocks, hipStream_t s);
+hipError_t launch_batch_f64(const BatchArgs<double> &a, int scheme, int blocks, hipStream_t s);
+// resident blocks of the batch kernel on one CU (occupancy)
+int batch_blocks_per_cu(int dtype_f64, int scheme);
+
 hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, int scheme, int ham, hipStream_t s);
 hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham, hipStream_t s);
 hipError_t launch_adj_axis_f32(const AdjAxisArgs<float> &a, int scheme, hipStream_t s);

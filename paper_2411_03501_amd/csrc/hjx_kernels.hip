@@ -257,25 +257,17 @@ __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
         j[D - 2] = jm;
         j[D - 1] = jl;
     }
+    if constexpr (D <= 2) {  // one plane: no loop over the slow axes
+        direct_node<T, D, SCHEME, HAM>(a, j);
+        return;
+    }
     for (int sy = blockIdx.y; sy < a.g.slow; sy += gridDim.y) {
         if constexpr (D == 3) j[0] = sy;
         if constexpr (D == 4) {
             j[0] = sy / a.g.n[1];
             j[1] = sy - j[0] * a.g.n[1];
         }
-        int idx = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) idx += j[d] * a.g.stride[d];
-        T pm[D], pp[D], center = T(0);
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            T v[7];
-            gather7(a.phi_in, idx, j[d], a.g.n[d], a.g.stride[d], (a.g.periodic >> d) & 1u, v);
-            center = v[3];
-            node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
-        }
-        *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
-            stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+        direct_node<T, D, SCHEME, HAM>(a, j);
     }
 }
 

@@ -74,6 +74,17 @@ SIGNATURES = {
     "hjx_solve_taped": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], ctypes.c_int),
     "hjx_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "hjx_loss_volume": ([_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P], ctypes.c_int),
+    "hjx_batch_create": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), _P, ctypes.POINTER(ctypes.c_void_p)],
+                         ctypes.c_int),
+    "hjx_batch_destroy": ([_P], ctypes.c_int),
+    "hjx_batch_set_shape": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "hjx_batch_get_shape": ([_P] + [ctypes.POINTER(ctypes.c_int32)] * 3, ctypes.c_int),
+    "hjx_batch_solve": ([_P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double), _P,
+                         ctypes.POINTER(Stats)], ctypes.c_int),
+    "hjx_batch_tune": ([_P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P,
+                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
 }
 
 
@@ -205,6 +216,54 @@ def hjx_loss_volume(handle, phi_ptr, eps, grad_ptr, stream=None):
     v = ctypes.c_double()
     _check(lib().hjx_loss_volume(handle, phi_ptr, float(eps), ctypes.byref(v), grad_ptr, _stream(stream)))
     return v.value
+
+
+def _ptrs(ptrs):
+    """A host array of device pointers (entries may be None)."""
+    if ptrs is None:
+        return None
+    arr = (ctypes.c_void_p * len(ptrs))()
+    for i, p in enumerate(ptrs):
+        arr[i] = None if p is None else (p.value if isinstance(p, ctypes.c_void_p) else int(p))
+    return arr
+
+
+def hjx_batch_create(handles, stream=None):
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    b = ctypes.c_void_p()
+    _check(lib().hjx_batch_create(len(handles), arr, _stream(stream), ctypes.byref(b)))
+    return b
+
+
+def hjx_batch_destroy(batch):
+    _check(lib().hjx_batch_destroy(batch))
+
+
+def hjx_batch_set_shape(batch, item_nodes, blocks):
+    _check(lib().hjx_batch_set_shape(batch, int(item_nodes), int(blocks)))
+
+
+def hjx_batch_get_shape(batch):
+    v = [ctypes.c_int32() for _ in range(3)]
+    _check(lib().hjx_batch_get_shape(batch, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def hjx_batch_solve(batch, phi0_ptrs, target_ptrs, out_ptrs, t1, stream=None, stats=True):
+    n = len(phi0_ptrs)
+    st = (Stats * n)() if stats else None
+    _check(lib().hjx_batch_solve(batch, _ptrs(phi0_ptrs), _ptrs(target_ptrs), _ptrs(out_ptrs),
+                                 (ctypes.c_double * n)(*[float(v) for v in t1]), _stream(stream), st))
+    return st
+
+
+def hjx_batch_tune(batch, phi0_ptrs, target_ptrs, out_ptrs, t1, reps=2, stream=None):
+    n = len(phi0_ptrs)
+    ms = ctypes.c_double()
+    _check(lib().hjx_batch_tune(batch, _ptrs(phi0_ptrs), _ptrs(target_ptrs), _ptrs(out_ptrs),
+                                (ctypes.c_double * n)(*[float(v) for v in t1]), int(reps), _stream(stream),
+                                ctypes.byref(ms)))
+    return ms.value
 
 
 # ------------------------------------------------------------------ handle wrapper
@@ -348,6 +407,60 @@ class Tape:
         dp = hjx_adjoint(P.handle, self.handle, P._t(dL_dphiT, "dL_dphiT"), P._t(g0, "dL_dphi0"),
                          P._t(gt, "dL_dtarget"), stream)
         return g0, gt, dp
+
+
+class Batch:
+    """Many problems solved together (hjx_batch_*).  The batch borrows each
+    member's workspace; keep the members alive while it exists."""
+
+    def __init__(self, problems, stream=None):
+        self.problems = list(problems)
+        self.handle = None
+        self.handle = hjx_batch_create([p.handle for p in self.problems], stream)
+
+    def close(self):
+        if self.handle is not None:
+            hjx_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        """(item_nodes, blocks, blocks_max)."""
+        return hjx_batch_get_shape(self.handle)
+
+    @shape.setter
+    def shape(self, v):
+        hjx_batch_set_shape(self.handle, *v[:2])
+
+    def _args(self, phi0, target, out):
+        n = len(self.problems)
+        if len(phi0) != n or (target is not None and len(target) != n) or (out is not None and len(out) != n):
+            raise ValueError(f"need {n} arrays per argument")
+        if out is None:
+            out = [torch.empty_like(x) for x in phi0]
+        p0 = [P._t(x, f"phi0[{i}]") for i, (P, x) in enumerate(zip(self.problems, phi0))]
+        tg = None if target is None else [P._t(x, f"target[{i}]") for i, (P, x) in
+                                          enumerate(zip(self.problems, target))]
+        po = [P._t(x, f"phi_out[{i}]") for i, (P, x) in enumerate(zip(self.problems, out))]
+        return p0, tg, po, out
+
+    def solve(self, phi0, t1, target=None, out=None, stream=None):
+        """Returns (list of phi(t1[i]), list of stats dicts)."""
+        p0, tg, po, out = self._args(phi0, target, out)
+        st = hjx_batch_solve(self.handle, p0, tg, po, t1, stream)
+        return out, [s.as_dict() for s in st]
+
+    def tune(self, phi0, t1, target=None, out=None, reps=2, stream=None):
+        """Pick the fastest launch shape; returns (shape, mean replay ms)."""
+        p0, tg, po, out = self._args(phi0, target, out)
+        ms = hjx_batch_tune(self.handle, p0, tg, po, t1, reps, stream)
+        return self.shape, ms
 
 
 class HjxSolve(torch.autograd.Function):

@@ -101,3 +101,19 @@ def test_null_arguments():
     d = ctypes.c_double()
     assert L.hjx_dissipation(None, a, ctypes.byref(d), None) == hjx.HJX_ERR_INVALID_ARG
     assert L.hjx_problem_destroy(None) == hjx.HJX_OK
+
+
+def test_batch_rejects_bad_arguments_before_the_device():
+    L = hjx.lib()
+    out = ctypes.c_void_p()
+    assert L.hjx_batch_create(0, None, None, ctypes.byref(out)) == hjx.HJX_ERR_INVALID_ARG
+    assert "n >= 1" in hjx.hjx_last_error()
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.hjx_batch_create(2, arr, None, ctypes.byref(out)) == hjx.HJX_ERR_INVALID_ARG
+    assert "problems[0]" in hjx.hjx_last_error()
+    assert L.hjx_batch_create(1, arr, None, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_batch_set_shape(None, 256, 1) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_batch_get_shape(None, None, None, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_batch_solve(None, None, None, None, None, None, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_batch_tune(None, None, None, None, None, 1, None, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_batch_destroy(None) == hjx.HJX_OK

@@ -1,0 +1,194 @@
+"""Batched solves (hjx_batch_* through the C ABI): every member must come out
+bit for bit as its own hjx_solve, whatever the launch shape, for every RK
+order (forward Euler with odd and even step counts), with members of zero
+steps, with and without targets, across graph replays and re-captures, and
+on the full uneven 256-member workload.  One small FP64 member is also
+checked against the oracle directly."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_03501_amd import inputs
+from helpers import assert_close, gpu_problem, oracle_problem, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_03501_amd import hjx  # noqa: E402
+
+TDT = {"f32": torch.float32, "f64": torch.float64}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def members(scheme="weno5", rk=3):
+    """Uneven small members: 1-D to 4-D, every Hamiltonian, ragged sizes."""
+    N2, D3, C4 = inputs.NORMAL2D, inputs.DUBINS3D, inputs.CAR4D
+    return [
+        N2.with_(n=(37, 29), scheme=scheme, rk=rk),
+        D3.with_(n=(19, 23, 17), scheme=scheme, rk=rk),
+        N2.with_(n=(64, 65), params=(2.5,), scheme=scheme, rk=rk, radius=0.3),
+        D3.with_(n=(31, 9, 12), params=(3.0, 4.0, 0.7, 1.3), scheme=scheme, rk=rk, radius=3.0),
+        C4.with_(n=(9, 11, 8, 7), scheme=scheme, rk=rk),
+        N2.with_(n=(3, 300), scheme=scheme, rk=rk),
+        inputs.Workload("line1d", (-1.0,), (1.0,), (77,), (), "normal", (0.8,), scheme, rk, 0.75, 0.0, False,
+                        0.4, "sphere", "f64", 0),
+    ]
+
+
+def setup(ws, dtype, steps, with_target=True):
+    probs = [gpu_problem(w, dtype) for w in ws]
+    phi0 = [to_dev(inputs.initial_surface(w) + 0.05 * inputs.smooth_field(w.n, 7 + i), TDT[dtype])
+            for i, w in enumerate(ws)]
+    t1 = []
+    for P, k in zip(probs, steps):
+        dt = P.dissipation()[1]
+        t1.append(0.0 if k == 0 else (k - 0.5) * dt)
+    target = [x if (with_target and w.with_target) else None for x, w in zip(phi0, ws)]
+    return probs, phi0, t1, target
+
+
+def singles(probs, phi0, t1, target):
+    out = []
+    for P, x, t, g in zip(probs, phi0, t1, target):
+        y, st = P.solve(x, t, target=g)
+        out.append((y, st))
+    return out
+
+
+def check_equal(got, ref, stats, ref_stats, what):
+    for i, (a, b) in enumerate(zip(got, ref)):
+        assert torch.equal(a, b), f"{what}: member {i} differs (max {float((a - b).abs().max()):.3e})"
+        assert stats[i]["steps"] == ref_stats[i]["steps"], (what, i)
+        assert stats[i]["dt"] == ref_stats[i]["dt"], (what, i)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("scheme,rk", [("weno5", 3), ("eno3", 2), ("first", 1), ("eno2", 1)])
+def test_batch_equals_single_solves(dtype, scheme, rk):
+    ws = members(scheme, rk)
+    steps = [5, 4, 0, 7, 3, 6, 1]   # odd and even counts, a member with none
+    say(f"batch {dtype} {scheme} rk{rk}")
+    probs, phi0, t1, target = setup(ws, dtype, steps)
+    B = hjx.Batch(probs)
+    got, st = B.solve(phi0, t1, target=target)
+    ref = singles(probs, phi0, t1, target)
+    check_equal(got, [r[0] for r in ref], st, [r[1] for r in ref], f"{dtype} {scheme} rk{rk}")
+    assert [s["steps"] for s in st] == steps
+    assert torch.equal(got[2], phi0[2])   # zero steps: phi0 itself
+    B.close()
+
+
+def test_launch_shape_and_replay_do_not_change_results():
+    ws = members()
+    steps = [6, 2, 9, 4, 3, 5, 7]
+    probs, phi0, t1, target = setup(ws, "f32", steps)
+    B = hjx.Batch(probs)
+    ref, _ = B.solve(phi0, t1, target=target)
+    ref = [x.clone() for x in ref]
+    _, _, bmax = B.shape
+    for items, blocks in [(256, 1), (256, 7), (1024, bmax), (4096, 3), (2048, min(bmax, 300))]:
+        say(f"shape items={items} blocks={blocks}")
+        B.shape = (items, blocks)
+        for rep in range(2):     # the second call replays the captured graph
+            got, _ = B.solve(phi0, t1, target=target)
+            for i in range(len(ws)):
+                assert torch.equal(got[i], ref[i]), (items, blocks, rep, i)
+    # new horizons: the graph is captured again, and matches single solves
+    t1b = [t * 0.5 for t in t1]
+    got, st = B.solve(phi0, t1b, target=target)
+    r = singles(probs, phi0, t1b, target)
+    check_equal(got, [x[0] for x in r], st, [x[1] for x in r], "recapture")
+    B.close()
+
+
+def test_batch_in_place_and_target_variants():
+    ws = members()
+    steps = [4, 3, 5, 2, 3, 4, 2]
+    probs, phi0, t1, _ = setup(ws, "f64", steps)
+    # targets on some members only: phi0 itself, or another array
+    target = [phi0[0], None, phi0[2] - 0.1, None, phi0[4], None, None]
+    ref = singles(probs, phi0, t1, target)
+    B = hjx.Batch(probs)
+    got, st = B.solve(phi0, t1, target=target)
+    check_equal(got, [x[0] for x in ref], st, [x[1] for x in ref], "targets")
+    # in place: phi_out is phi0 (the targets are the untouched originals)
+    work = [x.clone() for x in phi0]
+    got, st = B.solve(work, t1, target=target, out=work)
+    assert all(g is w for g, w in zip(got, work))
+    check_equal(work, [x[0] for x in ref], st, [x[1] for x in ref], "in place")
+    B.close()
+
+
+def test_batch_member_matches_the_oracle():
+    w = inputs.DUBINS3D.with_(n=(21, 19, 17))
+    ws = [w, inputs.NORMAL2D.with_(n=(41, 43), scheme="weno5", rk=3)]
+    probs, phi0, t1, target = setup(ws, "f64", [6, 9])
+    B = hjx.Batch(probs)
+    got, st = B.solve(phi0, t1, target=target)
+    for i, wi in enumerate(ws):
+        Po = oracle_problem(wi)
+        tg = to_host(target[i]) if target[i] is not None else None
+        ref, n_steps, dt0 = O.solve(Po, to_host(phi0[i]), t1[i], target=tg)
+        assert n_steps == st[i]["steps"]
+        assert_close(to_host(got[i]), ref, "f64", wi.periodic, f"batch member {i}")
+    B.close()
+
+
+def test_batch_errors():
+    ws = members()[:3]
+    probs, phi0, t1, target = setup(ws, "f32", [2, 2, 2])
+    with pytest.raises(hjx.HjxError, match="twice"):
+        hjx.Batch([probs[0], probs[1], probs[0]])
+    P64 = gpu_problem(ws[0], "f64")
+    with pytest.raises(hjx.HjxError, match="same dtype"):
+        hjx.Batch([probs[0], P64])
+    B = hjx.Batch(probs)
+    with pytest.raises(hjx.HjxError, match="item_nodes"):
+        B.shape = (300, 4)
+    with pytest.raises(hjx.HjxError, match="blocks"):
+        B.shape = (256, B.shape[2] + 1)
+    with pytest.raises(hjx.HjxError, match="t1"):
+        B.solve(phi0, [0.1, -1.0, 0.1])
+    with pytest.raises(hjx.HjxError, match="aliases"):
+        B.solve(phi0, t1, target=[None, phi0[1], None], out=phi0)
+    bad = [x.clone() for x in phi0]
+    bad[1].view(-1)[17] = float("nan")
+    with pytest.raises(hjx.HjxError, match=r"phi0\[1\]"):
+        B.solve(bad, t1)
+    # still usable afterwards
+    got, _ = B.solve(phi0, t1, target=target)
+    ref = singles(probs, phi0, t1, target)
+    for a, (b, _) in zip(got, ref):
+        assert torch.equal(a, b)
+    B.close()
+
+
+def test_batch256_full_size_equals_single_solves():
+    """The uneven 256-member workload at full size, in the launch shape the
+    batched benchmark uses after tuning: every member bitwise equal to its
+    own solve."""
+    ws = inputs.batch256()
+    probs = [gpu_problem(w, "f32") for w in ws]
+    phi0 = [to_dev(inputs.initial_surface(w), torch.float32) for w in ws]
+    t1 = [(w.steps - 0.5) * P.dissipation()[1] for w, P in zip(ws, probs)]
+    target = [x if w.with_target else None for x, w in zip(phi0, ws)]
+    say(f"batch256: {sum(P.numel for P in probs) / 1e6:.1f} M nodes")
+    B = hjx.Batch(probs)
+    shape, ms = B.tune(phi0, t1, target=target, reps=1)
+    say(f"tuned shape {shape}: {ms:.1f} ms")
+    got, st = B.solve(phi0, t1, target=target)
+    assert [s["steps"] for s in st] == [w.steps for w in ws]
+    for i, (P, x, t, g) in enumerate(zip(probs, phi0, t1, target)):
+        y, s1 = P.solve(x, t, target=g)
+        assert s1["steps"] == ws[i].steps
+        assert torch.equal(got[i], y), f"member {i} {ws[i].name}"
+    B.close()
