@@ -47,7 +47,53 @@ def stage_bytes_per_point(rk, with_target, elem):
     return reads_writes * elem / rk
 
 
-def run_gpu(w, dtype, steps, warmup):
+def describe(w, rk_steps):
+    """The workload in words: problem, grid, scheme, horizon."""
+    what = {"normal": f"{w.dim}-D motion in the normal direction",
+            "dubins3_pe": "3-D pursuit-evasion game of two Dubins cars",
+            "dubins4": "4-D Dubins car with a speed state"}[w.ham]
+    scheme = {"first": "first-order upwind", "eno2": "ENO2", "eno3": "ENO3", "weno5": "WENO5"}[w.scheme]
+    rk = {1: "forward Euler", 2: "TVD-RK2", 3: "TVD-RK3"}[w.rk]
+    tube = ", min-with-target (BRT)" if w.with_target else ""
+    return (f"{w.name}: {what}, {'x'.join(map(str, w.n))} nodes, {scheme}+LF+{rk}{tube}, horizon {w.t1} "
+            f"({rk_steps} RK steps per solve)")
+
+
+# the sources that define the stage kernels (their per-node arithmetic and launch)
+KERNEL_SOURCES = ["paper_2411_03501_amd/csrc/hjx_device.h", "paper_2411_03501_amd/csrc/hjx_kernels.hip"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(w, dtype, tile):
+    """HBM bytes per stage launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or None
+    when there is none for this workload and tile or the kernel sources have
+    changed since the counters were taken."""
+    import re
+    name = f"traffic_{w.name}_{dtype}.md"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    src = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
+    tl = re.search(r"tile: \(([\d, ]+)\)", text)
+    val = re.search(r"HBM bytes per launch: ([0-9.e+]+)", text)
+    if not (src and tl and val) or src.group(1) != kernel_sources_sha256():
+        return None
+    if tuple(int(v) for v in tl.group(1).split(",")) != tuple(tile):
+        return None
+    return float(val.group(1))
+
+
+def run_gpu(w, dtype, steps, warmup, tile=None):
     import torch
 
     from paper_2411_03501_amd import hjx, inputs
@@ -57,8 +103,13 @@ def run_gpu(w, dtype, steps, warmup):
     phi0 = torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=tdt)
     target = phi0 if w.with_target else None
     out = torch.empty_like(phi0)
-    tile, us = P.tune(phi0, reps=3)   # launch-shape autotuner (outside the timed region)
-    log(f"  tuned tile {tile}: {us:.2f} us per stage launch")
+    if tile is None:
+        tile, us = P.tune(phi0, reps=3)   # launch-shape autotuner (outside the timed region)
+        log(f"  tuned tile {tile}: {us:.2f} us per stage launch")
+    else:
+        P.tile = tile
+        tile = P.tile
+        log(f"  fixed tile {tile}")
     for i in range(warmup):
         P.solve(phi0, w.t1, target=target, out=out)
         log(f"  warmup {i + 1}/{warmup} done")
@@ -164,7 +215,7 @@ def run_batch(reps=2):
     ws = inputs.batch256()
     probs = [hjx.Problem.from_workload(w, "f32") for w in ws]
     phi0 = [torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=torch.float32) for w in ws]
-    t1 = [(w.steps - 0.5) * P.dissipation()[1] for w, P in zip(ws, probs)]
+    t1 = [w.steps * P.dissipation()[1] for w, P in zip(ws, probs)]
     target = [x if w.with_target else None for x, w in zip(phi0, ws)]
     out = [torch.empty_like(x) for x in phi0]
     updates = sum(w.points * w.steps for w in ws)
@@ -205,6 +256,23 @@ def run_batch(reps=2):
             "speedup": single_s / batch_s, "shape": {"item_nodes": shape[0], "blocks": shape[1]}}
 
 
+def run_copy(nbytes=1 << 30, reps=4):
+    """A plain device-to-device copy of nbytes (torch's copy kernel): HBM
+    counters of this kernel give the scale between counter readings and
+    bytes moved."""
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "reps": reps, "gbs": 2 * nbytes / dt / 1e9}
+
+
 def run_cpu_baseline(w, budget_s=15.0):
     """The oracle as it stands, on the host's cores, for a bounded number of
     RK steps of the same workload."""
@@ -242,6 +310,12 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--tile", default=None,
+                    help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
+                         "(counter runs: the tuner's timings are distorted under counter collection)")
+    ap.add_argument("--only", choices=["batch256", "adjoint", "copy"],
+                    help="run one secondary measurement alone and print its JSON (for profiling); "
+                         "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -251,9 +325,20 @@ def main():
 
     from paper_2411_03501_amd import inputs
 
+    if args.only:
+        if args.only == "batch256":
+            res = run_batch()
+        elif args.only == "adjoint":
+            res = run_adjoint(inputs.DUBINS3D_81)
+        else:
+            res = run_copy()
+        print(json.dumps({"only": args.only, **res}), flush=True)
+        return
+
     w = inputs.WORKLOADS[args.workload]
     log(f"bench {w.name} {args.dtype}: {w.points} nodes, K={args.steps} W={args.warmup}")
-    elapsed, st, loop_ms = run_gpu(w, args.dtype, args.steps, args.warmup)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    elapsed, st, loop_ms = run_gpu(w, args.dtype, args.steps, args.warmup, tile)
     rk_steps = st["steps"]
     elem = 4 if args.dtype == "f32" else 8
     updates = w.points * rk_steps * args.steps
@@ -265,14 +350,15 @@ def main():
     achieved_tops = ops / kern_s / 1e12
     bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
     achieved_gbs = bytes_launch / kern_s / 1e9
+    traffic = measured_traffic(w, args.dtype, st["tile"])
     if w.scheme == "weno5":
         roof = {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
+                "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
                 "kernel": "stage_kernel", "kernel_us": kern_s * 1e6, "tile": st["tile"],
                 "hbm_alg_gbs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS}
     else:
         roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": None,
+                "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic,
                 "kernel": "stage_kernel", "kernel_us": kern_s * 1e6}
 
     extra = {}
@@ -318,9 +404,7 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: 3-D pursuit-evasion BRT, {'x'.join(map(str, w.n))} nodes, "
-                               f"{w.scheme.upper()}+LF+TVD-RK{w.rk}, min-with-target, horizon {w.t1} "
-                               f"({rk_steps} RK steps per solve)",
+        "config": {"workload": describe(w, rk_steps),
                    "nodes": w.points, "rk_steps_per_solve": rk_steps, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -224,7 +224,7 @@ typedef struct hjx_tape hjx_tape;
 /* Create a tape for a solve of p from t0 to t1 (t1 >= t0) with a checkpoint
  * every ckpt_every >= 1 steps.  Runs the dissipation reduction (synchronises
  * `stream`) and allocates the checkpoints and the replay workspace: about
- * (steps/ckpt_every + 3 ckpt_every + 12) arrays of the problem's size.
+ * (steps/ckpt_every + 3 ckpt_every + 4 + 3 dim) arrays of the problem's size.
  * Arrays must be under 4 GiB each (else HJX_ERR_UNSUPPORTED). */
 hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream,
                            hjx_tape **out);

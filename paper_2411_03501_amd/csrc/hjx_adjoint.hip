@@ -19,6 +19,8 @@
 //                    end nodes they were extrapolated from.
 #include "hjx_device.h"
 
+#include <algorithm>
+
 namespace hjx {
 namespace {
 
@@ -33,6 +35,40 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
+// Reduce-scatter over the 64 lanes of a wave: each lane brings V values
+// (V a power of two, at most 64); at every butterfly step a lane keeps half
+// of its values and adds its partner's copy of that half, so value i ends
+// summed over all lanes in the lanes whose bits 5, 4, ... spell i (lane
+// i << (6 - log2 V) among them).  About V + log2(64/V) exchanges instead of
+// 6 V for V separate sums.  Returns the value this lane holds.
+template <int V>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[V], int lane)
+{
+    static_assert(V >= 1 && V <= 64 && (V & (V - 1)) == 0, "V must be a power of two");
+    int off = 32;
+#pragma unroll
+    for (int half = V / 2; half >= 1; half >>= 1, off >>= 1) {
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = upper ? v[i] : v[i + half];
+            const double keep = upper ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    double x = v[0];
+    for (; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <int HAM>
+constexpr int ham_params()
+{
+    return HAM == kHamDubins3 ? 4 : (HAM == kHamDubins4 ? 2 : 1);
+}
+
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+
 // ---------------------------------------------------------------- seeds
 
 template <typename T, int D, int SCHEME, int HAM>
@@ -41,7 +77,10 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
     const StageArgs<T> &st = a.st;
     const int q = blockIdx.x * kSeedThreads + threadIdx.x;
     const bool live = q < st.g.plane;
-    double part[kAccCount] = {};
+    // per-node contributions: [0] dL/dh, [1..D] dL/dalpha_d, [D+1..D+NP] dL/dtheta
+    constexpr int NP = ham_params<HAM>();
+    constexpr int V = pow2_at_least(1 + D + NP);
+    double part[V] = {};
 
     int j[kMaxDim] = {0, 0, 0, 0};
     if (live) {
@@ -97,11 +136,11 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
             // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
             a.seed_m[d][idx] = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
             a.seed_p[d][idx] = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
-            part[kAccAlpha + d] = (double)(w * T(0.5) * (pp[d] - pm[d]));
+            part[1 + d] = (double)(w * T(0.5) * (pp[d] - pm[d]));
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) part[kAccTheta + m] = (double)(w * dmH[m]);
-        part[a.h_slot] = (double)(a.cb * lo) * (double)L;
+        for (int m = 0; m < NP; ++m) part[1 + D + m] = (double)(w * dmH[m]);
+        part[0] = (double)(a.cb * lo) * (double)L;
 
         const T cin = a.cb * lo;
         a.lam_in[idx] = a.in_mode ? a.lam_in[idx] + cin : cin;
@@ -111,20 +150,20 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
         }
     }
 
-    // block sums, accumulated into this block's slot (a fixed order: deterministic)
-    __shared__ double red[kSeedThreads / 64][kAccCount];
+    // block sums, accumulated into this block's slots (a fixed order: deterministic)
+    __shared__ double red[kSeedThreads / 64][V];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < kAccCount; ++k) {
-        const double s = wave_sum(part[k]);
-        if (lane == 0) red[wave][k] = s;
-    }
+    constexpr int kShift = 6 - (V == 1 ? 0 : V == 2 ? 1 : V == 4 ? 2 : V == 8 ? 3 : V == 16 ? 4 : 5);
+    const double mine = wave_reduce_scatter<V>(part, lane);
+    if ((lane & ((1 << kShift) - 1)) == 0) red[wave][lane >> kShift] = mine;
     __syncthreads();
-    if (threadIdx.x < kAccCount) {
+    if (threadIdx.x < 1 + D + NP) {
+        const int k = threadIdx.x;
         double s = 0.0;
-        for (int w = 0; w < kSeedThreads / 64; ++w) s += red[w][threadIdx.x];
+        for (int w = 0; w < kSeedThreads / 64; ++w) s += red[w][k];
+        const int slot = k == 0 ? a.h_slot : (k <= D ? kAccAlpha + (k - 1) : kAccTheta + (k - 1 - D));
         const int b = blockIdx.y * gridDim.x + blockIdx.x;
-        a.acc[b * kAccCount + threadIdx.x] += s;
+        a.acc[b * kAccCount + slot] += s;
     }
 }
 
@@ -175,15 +214,18 @@ __device__ __forceinline__ int lds_at(int pos, int col, int npos, int tw)
     return LX ? col * npos + pos : pos * tw + col;
 }
 
-// LX: the line axis is the fastest axis and runs along the lanes
+// One line tile of one axis.  LX: the line axis is the fastest axis and
+// runs along the lanes (thread t: position t % tl, column t / tl);
+// otherwise the columns run along the lanes (column t % tw, position t / tw).
+// Threads t >= tl * tw only take part in the barriers.
 template <typename T, int SCHEME, bool LX>
-__global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
+__device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int by, int tid, unsigned char *smem_raw)
 {
-    extern __shared__ unsigned char smem_raw[];
     const int tl = a.tl, tw = a.tw;
     constexpr bool lx = LX;
-    const int ip = lx ? threadIdx.x : threadIdx.y;
-    const int ic = lx ? threadIdx.y : threadIdx.x;
+    const bool active = tid < tl * tw;
+    const int ip = active ? (lx ? tid % tl : tid / tw) : tl;
+    const int ic = active ? (lx ? tid / tl : tid % tw) : 0;
     const int NP = tl + 10, NS = tl + 6, NI = tl + 5;
     T *PH = reinterpret_cast<T *>(smem_raw);   // NP x tw
     T *SM = PH + NP * tw;                      // NS x tw
@@ -194,12 +236,12 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
     const bool per = (a.g.periodic >> d) & 1u;
     const int nc = a.c >= 0 ? a.g.n[a.c] : 1, sc = a.c >= 0 ? a.g.stride[a.c] : 0;
     const int tiles_d = (nd + tl - 1) / tl;
-    const int l0 = (blockIdx.x % tiles_d) * tl, c0 = (blockIdx.x / tiles_d) * tw;
+    const int l0 = (bx % tiles_d) * tl, c0 = (bx / tiles_d) * tw;
     const int col = c0 + ic;
-    const bool col_ok = col < nc;
+    const bool col_ok = active && col < nc;
     int base = col_ok ? col * sc : 0;
     {
-        int r = blockIdx.y;
+        int r = by;
         for (int k = 1; k >= 0; --k)
             if (a.rest[k] >= 0) {
                 const int n = a.g.n[a.rest[k]];
@@ -218,8 +260,8 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
     };
 
     // stage phi and the seeds of this axis
-    for (int p = ip; p < NP; p += tl) PH[lds_at<LX>(p, ic, NP, tw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
-    for (int p = ip; p < NS; p += tl) {
+    for (int p = active ? ip : NP; p < NP; p += tl) PH[lds_at<LX>(p, ic, NP, tw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
+    for (int p = active ? ip : NS; p < NS; p += tl) {
         int g = l0 - 3 + p;
         T m = T(0), pl = T(0);
         if (col_ok) {
@@ -238,9 +280,9 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
     // column) pairs are spread evenly over the block's threads, consecutive
     // lanes taking consecutive intervals of a line (lx) or consecutive
     // columns (otherwise), as the LDS layout is laid out
-    const int nthr = tl * tw, tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nthr = tl * tw;
     const float inv_ni = 1.0f / (float)NI;
-    for (int e = tid; e < NI * tw; e += nthr) {
+    for (int e = active ? tid : NI * tw; e < NI * tw; e += nthr) {
         int iv, cc;
         if (lx) {
             cc = (int)(((float)e + 0.5f) * inv_ni);
@@ -294,38 +336,69 @@ __global__ __launch_bounds__(256) void adj_axis_kernel(AdjAxisArgs<T> a)
                 }
             }
         }
-        a.lam[base + g * sd] += acc;
+        if (a.out) a.out[base + g * sd] = acc;
+        else a.lam[base + g * sd] += acc;
+    }
+}
+
+// The transposes of every axis in one launch: block b belongs to the axis k
+// with start[k] <= b < start[k+1] and is tile (bx, by) of that axis.  With
+// several axes each writes its own contribution array (out), so the blocks of
+// different axes never touch the same memory and overlap freely.
+template <typename T, int SCHEME>
+__global__ __launch_bounds__(256) void adj_axes_kernel(AdjAxesArgs<T> a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int b = (int)blockIdx.x;
+    int k = 0;
+    while (k + 1 < a.nax && b >= a.start[k + 1]) ++k;
+    const int lb = b - a.start[k];
+    const int bx = lb % a.gx[k], by = lb / a.gx[k];
+    const AdjAxisArgs<T> &A = a.ax[k];
+    if (A.d == A.g.dim - 1) axis_tile<T, SCHEME, true>(A, bx, by, (int)threadIdx.x, smem_raw);
+    else axis_tile<T, SCHEME, false>(A, bx, by, (int)threadIdx.x, smem_raw);
+}
+
+// lam += c[0] (+ c[1]) (+ c[2]) (+ c[3]), added in that order
+template <typename T>
+__global__ __launch_bounds__(256) void combine_kernel(T *lam, AdjCombineArgs<T> c, int n)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        T v = lam[i];
+        for (int k = 0; k < c.n; ++k) v += c.c[k][i];
+        lam[i] = v;
     }
 }
 
 template <typename T>
-hipError_t launch_axis(const AdjAxisArgs<T> &a, int scheme, hipStream_t s)
+hipError_t launch_axes(const AdjAxesArgs<T> &in, int scheme, hipStream_t s)
 {
-    const int nd = a.g.n[a.d], nc = a.c >= 0 ? a.g.n[a.c] : 1;
-    if (a.tl < 2 || a.tw < 1 || a.tl * a.tw > 256) return hipErrorInvalidConfiguration;
-    const bool lx = a.d == a.g.dim - 1;
-    int rest = 1;
-    for (int k = 0; k < 2; ++k)
-        if (a.rest[k] >= 0) rest *= a.g.n[a.rest[k]];
-    if (rest > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid(((nd + a.tl - 1) / a.tl) * ((nc + a.tw - 1) / a.tw), rest);
-    const dim3 block(lx ? a.tl : a.tw, lx ? a.tw : a.tl);
-    const size_t lds = sizeof(T) * (size_t)a.tw * ((a.tl + 10) + 2 * (a.tl + 6) + 5 * (a.tl + 5));
-#define HJX_AXIS_LAUNCH(S)                                                                \
-    do {                                                                                  \
-        if (lx)                                                                           \
-            hipLaunchKernelGGL((adj_axis_kernel<T, S, true>), grid, block, lds, s, a);    \
-        else                                                                              \
-            hipLaunchKernelGGL((adj_axis_kernel<T, S, false>), grid, block, lds, s, a);   \
-    } while (0)
+    AdjAxesArgs<T> a = in;
+    if (a.nax < 1 || a.nax > kMaxDim) return hipErrorInvalidValue;
+    size_t lds = 0;
+    long total = 0;
+    for (int k = 0; k < a.nax; ++k) {
+        const AdjAxisArgs<T> &x = a.ax[k];
+        const int nd = x.g.n[x.d], nc = x.c >= 0 ? x.g.n[x.c] : 1;
+        if (x.tl < 2 || x.tw < 1 || x.tl * x.tw > 256) return hipErrorInvalidConfiguration;
+        int rest = 1;
+        for (int r = 0; r < 2; ++r)
+            if (x.rest[r] >= 0) rest *= x.g.n[x.rest[r]];
+        a.gx[k] = ((nd + x.tl - 1) / x.tl) * ((nc + x.tw - 1) / x.tw);
+        a.start[k] = (int)total;
+        total += (long)a.gx[k] * rest;
+        lds = std::max(lds, sizeof(T) * (size_t)x.tw * ((x.tl + 10) + 2 * (x.tl + 6) + 5 * (x.tl + 5)));
+    }
+    if (total > 0x7fffffffL) return hipErrorInvalidConfiguration;
+    a.start[a.nax] = (int)total;
+    const dim3 grid((unsigned)total);
     switch (scheme) {
-    case kSchemeFirst: HJX_AXIS_LAUNCH(kSchemeFirst); break;
-    case kSchemeEno2: HJX_AXIS_LAUNCH(kSchemeEno2); break;
-    case kSchemeEno3: HJX_AXIS_LAUNCH(kSchemeEno3); break;
-    case kSchemeWeno5: HJX_AXIS_LAUNCH(kSchemeWeno5); break;
+    case kSchemeFirst: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeFirst>), grid, dim3(256), lds, s, a); break;
+    case kSchemeEno2: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeEno2>), grid, dim3(256), lds, s, a); break;
+    case kSchemeEno3: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeEno3>), grid, dim3(256), lds, s, a); break;
+    case kSchemeWeno5: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeWeno5>), grid, dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
-#undef HJX_AXIS_LAUNCH
     return hipGetLastError();
 }
 
@@ -413,13 +486,23 @@ hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham
 {
     return launch_seed<double>(a, scheme, ham, s);
 }
-hipError_t launch_adj_axis_f32(const AdjAxisArgs<float> &a, int scheme, hipStream_t s)
+hipError_t launch_adj_axes_f32(const AdjAxesArgs<float> &a, int scheme, hipStream_t s)
 {
-    return launch_axis<float>(a, scheme, s);
+    return launch_axes<float>(a, scheme, s);
 }
-hipError_t launch_adj_axis_f64(const AdjAxisArgs<double> &a, int scheme, hipStream_t s)
+hipError_t launch_adj_axes_f64(const AdjAxesArgs<double> &a, int scheme, hipStream_t s)
 {
-    return launch_axis<double>(a, scheme, s);
+    return launch_axes<double>(a, scheme, s);
+}
+hipError_t launch_combine_f32(float *lam, const AdjCombineArgs<float> &c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(combine_kernel<float>, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, lam, c, n);
+    return hipGetLastError();
+}
+hipError_t launch_combine_f64(double *lam, const AdjCombineArgs<double> &c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(combine_kernel<double>, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, lam, c, n);
+    return hipGetLastError();
 }
 hipError_t launch_acc_reduce(const double *acc, int blocks, double *out, hipStream_t s)
 {

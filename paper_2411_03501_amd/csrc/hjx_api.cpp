@@ -649,6 +649,7 @@ struct hjx_tape {
     std::vector<unsigned char *> mask; // replay: where the target was the smaller
     void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
     void *seed_m[kMaxDim] = {}, *seed_p[kMaxDim] = {};
+    void *contrib[kMaxDim] = {};       // per-axis transpose contributions (dim >= 2)
     double *acc = nullptr;             // per seed-kernel block
     int acc_blocks = 0;
     double *acc_out = nullptr;         // device, kAccCount
@@ -674,6 +675,7 @@ void tape_release(hjx_tape *t)
     for (int d = 0; d < kMaxDim; ++d) {
         f(t->seed_m[d]);
         f(t->seed_p[d]);
+        f(t->contrib[d]);
     }
     f(t->acc);
     f(t->acc_out);
@@ -792,6 +794,7 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     for (int d = 0; d < p->grid.dim; ++d) {
         grab(&t->seed_m[d], field);
         grab(&t->seed_p[d], field);
+        if (p->grid.dim >= 2) grab(&t->contrib[d], field);
     }
     t->acc_blocks = adj_seed_blocks(geometry(p));
     grab(reinterpret_cast<void **>(&t->acc), sizeof(double) * kAccCount * (size_t)t->acc_blocks);
@@ -918,13 +921,21 @@ hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, co
     else
         e = launch_adj_seed_f64(a, p->scheme.deriv, p->ham.kind, s);
     if (e != hipSuccess) return e;
+    // the transposes of all axes in one launch; with several axes each
+    // writes its own contribution, added to lam_in afterwards in axis order
     const GridGeom g = geometry(p);
+    AdjAxesArgs<T> xs{};
+    xs.nax = g.dim;
+    AdjCombineArgs<T> cmb{};
+    cmb.n = g.dim >= 2 ? g.dim : 0;
     for (int d = 0; d < g.dim; ++d) {
-        AdjAxisArgs<T> x{};
+        AdjAxisArgs<T> &x = xs.ax[d];
         x.phi = static_cast<const T *>(in);
         x.seed_m = static_cast<const T *>(t->seed_m[d]);
         x.seed_p = static_cast<const T *>(t->seed_p[d]);
         x.lam = static_cast<T *>(lam_in);
+        x.out = g.dim >= 2 ? static_cast<T *>(t->contrib[d]) : nullptr;
+        cmb.c[d] = x.out;
         x.g = g;
         x.d = d;
         // cross axis: the fastest axis (coalesced rows), or the second-fastest
@@ -947,13 +958,15 @@ hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, co
             x.tw = std::max(1, std::min(256 / x.tl, nc));
         else
             x.tw = std::min(nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)), 256 / x.tl);
-        if constexpr (std::is_same<T, float>::value)
-            e = launch_adj_axis_f32(x, p->scheme.deriv, s);
-        else
-            e = launch_adj_axis_f64(x, p->scheme.deriv, s);
-        if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    if constexpr (std::is_same<T, float>::value) {
+        if ((e = launch_adj_axes_f32(xs, p->scheme.deriv, s)) != hipSuccess) return e;
+        if (cmb.n) e = launch_combine_f32(static_cast<float *>(lam_in), cmb, (int)p->total, s);
+    } else {
+        if ((e = launch_adj_axes_f64(xs, p->scheme.deriv, s)) != hipSuccess) return e;
+        if (cmb.n) e = launch_combine_f64(static_cast<double *>(lam_in), cmb, (int)p->total, s);
+    }
+    return e;
 }
 
 hipError_t reverse_stage(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,

@@ -113,6 +113,24 @@ struct AdjAxisArgs {
     int rest[2];     // remaining axes, or -1
     T inv_dx, dx;
     int tl, tw;
+    T *out;          // nullable: write the contribution here instead of adding it to lam
+};
+
+// The transposes of several axes in one launch (start and gx are filled in
+// by the launcher).
+template <typename T>
+struct AdjAxesArgs {
+    AdjAxisArgs<T> ax[kMaxDim];
+    int nax;
+    int start[kMaxDim + 1];
+    int gx[kMaxDim];
+};
+
+// lam += c[0] + ... + c[n-1], in that order
+template <typename T>
+struct AdjCombineArgs {
+    const T *c[kMaxDim];
+    int n;
 };
 
 // ---------------------------------------------------------------- batch
@@ -157,8 +175,10 @@ int batch_blocks_per_cu(int dtype_f64, int scheme);
 
 hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, int scheme, int ham, hipStream_t s);
 hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham, hipStream_t s);
-hipError_t launch_adj_axis_f32(const AdjAxisArgs<float> &a, int scheme, hipStream_t s);
-hipError_t launch_adj_axis_f64(const AdjAxisArgs<double> &a, int scheme, hipStream_t s);
+hipError_t launch_adj_axes_f32(const AdjAxesArgs<float> &a, int scheme, hipStream_t s);
+hipError_t launch_adj_axes_f64(const AdjAxesArgs<double> &a, int scheme, hipStream_t s);
+hipError_t launch_combine_f32(float *lam, const AdjCombineArgs<float> &c, int n, hipStream_t s);
+hipError_t launch_combine_f64(double *lam, const AdjCombineArgs<double> &c, int n, hipStream_t s);
 int adj_seed_blocks(const GridGeom &g);
 // out[k] = sum over blocks of acc[block * kAccCount + k]
 hipError_t launch_acc_reduce(const double *acc, int blocks, double *out, hipStream_t s);

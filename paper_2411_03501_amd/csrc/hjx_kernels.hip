@@ -238,7 +238,15 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 template <typename T, int D, int SCHEME, int HAM>
 __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
 {
-    const int q = blockIdx.x * 256 + threadIdx.x;
+    // XCD-aware order: the hardware deals consecutive blocks round-robin to
+    // the 8 XCDs, each with its own L2.  Renumber the blocks so that each
+    // XCD takes a contiguous run of them: the rows a block's stencils reach
+    // along the second-fastest axis then mostly sit in the same L2.
+    const int G = (int)(gridDim.x * gridDim.y);
+    int lb = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if ((G & 7) == 0) lb = (lb & 7) * (G >> 3) + (lb >> 3);
+    const int bx = lb % (int)gridDim.x, by = lb / (int)gridDim.x;
+    const int q = bx * 256 + threadIdx.x;
     if (q >= a.g.plane) return;
     int j[kMaxDim] = {0, 0, 0, 0};
     if constexpr (D == 1) {
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
         direct_node<T, D, SCHEME, HAM>(a, j);
         return;
     }
-    for (int sy = blockIdx.y; sy < a.g.slow; sy += gridDim.y) {
+    for (int sy = by; sy < a.g.slow; sy += gridDim.y) {
         if constexpr (D == 3) j[0] = sy;
         if constexpr (D == 4) {
             j[0] = sy / a.g.n[1];

@@ -179,7 +179,7 @@ def test_batch256_full_size_equals_single_solves():
     ws = inputs.batch256()
     probs = [gpu_problem(w, "f32") for w in ws]
     phi0 = [to_dev(inputs.initial_surface(w), torch.float32) for w in ws]
-    t1 = [(w.steps - 0.5) * P.dissipation()[1] for w, P in zip(ws, probs)]
+    t1 = [w.steps * P.dissipation()[1] for w, P in zip(ws, probs)]
     target = [x if w.with_target else None for x, w in zip(phi0, ws)]
     say(f"batch256: {sum(P.numel for P in probs) / 1e6:.1f} M nodes")
     B = hjx.Batch(probs)
