@@ -351,15 +351,16 @@ def main():
     bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
     achieved_gbs = bytes_launch / kern_s / 1e9
     traffic = measured_traffic(w, args.dtype, st["tile"])
+    kernel_name = "stage_direct_kernel" if st["tile"][0] == 1 else "stage_kernel (plane-march)"
     if w.scheme == "weno5":
         roof = {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
                 "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
-                "kernel": "stage_kernel", "kernel_us": kern_s * 1e6, "tile": st["tile"],
+                "kernel": kernel_name, "kernel_us": kern_s * 1e6, "tile": st["tile"],
                 "hbm_alg_gbs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS}
     else:
         roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic,
-                "kernel": "stage_kernel", "kernel_us": kern_s * 1e6}
+                "kernel": kernel_name, "kernel_us": kern_s * 1e6}
 
     extra = {}
     if not args.no_extra:

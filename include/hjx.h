@@ -230,6 +230,19 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
                            hjx_tape **out);
 hjx_status hjx_tape_destroy(hjx_tape *tape);
 
+/* What the replay keeps for the reverse sweep.  HJX_TAPE_STORE_DERIVS keeps
+ * the derivative approximations p-_d, p+_d of every stage of a segment
+ * (ckpt_every * rk * 2 dim more arrays of the problem's size), so the
+ * reverse sweep reads them instead of evaluating the stencils again;
+ * HJX_TAPE_RECOMPUTE keeps none.  hjx_tape_create picks STORE_DERIVS when
+ * that memory is at most a quarter of the device's free memory.  Both modes
+ * give the same bits.  set_mode allocates or frees the store (HJX_ERR_OOM if
+ * it does not fit). */
+#define HJX_TAPE_RECOMPUTE 0
+#define HJX_TAPE_STORE_DERIVS 1
+hjx_status hjx_tape_set_mode(hjx_tape *tape, int32_t mode);
+hjx_status hjx_tape_get_mode(const hjx_tape *tape, int32_t *mode);
+
 /* hjx_solve on the tape's schedule, recording the checkpoints.  The target
  * (NULL for none; may be phi0, not phi_out) must stay unchanged until
  * hjx_adjoint has run. */

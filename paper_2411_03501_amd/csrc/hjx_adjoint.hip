@@ -71,7 +71,7 @@ constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 
 
 // ---------------------------------------------------------------- seeds
 
-template <typename T, int D, int SCHEME, int HAM>
+template <typename T, int D, int SCHEME, int HAM, bool STORED>
 __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a)
 {
     const StageArgs<T> &st = a.st;
@@ -111,16 +111,25 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
         for (int d = 0; d < D; ++d) idx += j[d] * st.g.stride[d];
 
         T lo = ld32(a.lam_out, idx);
-        if (a.mask && a.mask[idx]) {  // the target was kept: its adjoint takes lam_out
-            if (a.lam_target) a.lam_target[idx] += lo;
+        for (int k = 0; k < a.n_add; ++k) lo += ld32(a.lam_add[k], idx);
+        if (a.mask && ld32(a.mask, idx)) {  // the target was kept: its adjoint takes lam_out
+            if (a.lam_target) at32(a.lam_target, idx) += lo;
             lo = T(0);
         }
         T pm[D], pp[D];
+        if constexpr (STORED) {  // the replay kept them
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            T v[7];
-            gather7(st.phi_in, idx, j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
-            node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], pm[d], pp[d]);
+            for (int d = 0; d < D; ++d) {
+                pm[d] = ld32(a.dp_in + (size_t)(2 * d) * (size_t)a.dp_stride, idx);
+                pp[d] = ld32(a.dp_in + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx);
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                T v[7];
+                gather7(st.phi_in, idx, j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
+                node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], pm[d], pp[d]);
+            }
         }
         T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
 #pragma unroll
@@ -134,8 +143,8 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
-            a.seed_m[d][idx] = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
-            a.seed_p[d][idx] = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
+            at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
+            at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
             part[1 + d] = (double)(w * T(0.5) * (pp[d] - pm[d]));
         }
 #pragma unroll
@@ -143,10 +152,10 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
         part[0] = (double)(a.cb * lo) * (double)L;
 
         const T cin = a.cb * lo;
-        a.lam_in[idx] = a.in_mode ? a.lam_in[idx] + cin : cin;
+        at32(a.lam_in, idx) = a.in_mode ? ld32(a.lam_in, idx) + cin : cin;
         if (a.n_mode) {
             const T cn = a.ca * lo;
-            a.lam_n[idx] = a.n_mode == 2 ? a.lam_n[idx] + cn : cn;
+            at32(a.lam_n, idx) = a.n_mode == 2 ? ld32(a.lam_n, idx) + cn : cn;
         }
     }
 
@@ -171,7 +180,10 @@ template <typename T, int D, int SCHEME, int HAM>
 hipError_t launch_seed_one(const AdjSeedArgs<T> &a, hipStream_t s)
 {
     dim3 grid((a.st.g.plane + kSeedThreads - 1) / kSeedThreads, a.st.g.slow);
-    hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM>), grid, dim3(kSeedThreads), 0, s, a);
+    if (a.dp_in)
+        hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, false>), grid, dim3(kSeedThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -251,11 +263,11 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     }
 
     auto phi_at = [&](int gpos) -> T {  // with ghosts along d
-        if (gpos >= 0 && gpos < nd) return a.phi[base + gpos * sd];
-        if (per) return a.phi[base + wrap_index<T>(gpos, nd) * sd];
+        if (gpos >= 0 && gpos < nd) return ld32(a.phi, base + gpos * sd);
+        if (per) return ld32(a.phi, base + wrap_index<T>(gpos, nd) * sd);
         const int e = gpos < 0 ? 0 : nd - 1, e2 = gpos < 0 ? 1 : nd - 2;
         const T c = T(gpos < 0 ? -gpos : gpos - (nd - 1));
-        const T p0 = a.phi[base + e * sd], p1 = a.phi[base + e2 * sd];
+        const T p0 = ld32(a.phi, base + e * sd), p1 = ld32(a.phi, base + e2 * sd);
         return fmaT(c, p0 - p1, p0);
     };
 
@@ -267,8 +279,8 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
         if (col_ok) {
             if (g < 0 || g >= nd) g = per ? wrap_index<T>(g, nd) : -1;  // ghosts carry no seed
             if (g >= 0) {
-                m = a.seed_m[base + g * sd];
-                pl = a.seed_p[base + g * sd];
+                m = ld32(a.seed_m, base + g * sd);
+                pl = ld32(a.seed_p, base + g * sd);
             }
         }
         SM[lds_at<LX>(p, ic, NS, tw)] = m;
@@ -336,8 +348,8 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
                 }
             }
         }
-        if (a.out) a.out[base + g * sd] = acc;
-        else a.lam[base + g * sd] += acc;
+        if (a.out) at32(a.out, base + g * sd) = acc;
+        else at32(a.lam, base + g * sd) += acc;
     }
 }
 
@@ -364,9 +376,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void combine_kernel(T *lam, AdjCombineArgs<T> c, int n)
 {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        T v = lam[i];
-        for (int k = 0; k < c.n; ++k) v += c.c[k][i];
-        lam[i] = v;
+        T v = ld32(lam, i);
+        for (int k = 0; k < c.n; ++k) v += ld32(c.c[k], i);
+        at32(lam, i) = v;
     }
 }
 

@@ -650,6 +650,8 @@ struct hjx_tape {
     void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
     void *seed_m[kMaxDim] = {}, *seed_p[kMaxDim] = {};
     void *contrib[kMaxDim] = {};       // per-axis transpose contributions (dim >= 2)
+    bool pending = false;              // contrib holds sums not yet added to the last lam_in
+    std::vector<void *> dp;            // replay: p-, p+ of every stage of a segment (empty: recompute)
     double *acc = nullptr;             // per seed-kernel block
     int acc_blocks = 0;
     double *acc_out = nullptr;         // device, kAccCount
@@ -671,6 +673,7 @@ void tape_release(hjx_tape *t)
     for (void *x : t->x1) f(x);
     for (void *x : t->xh) f(x);
     for (unsigned char *x : t->mask) f(x);
+    for (void *x : t->dp) f(x);
     for (void *x : t->lam) f(x);
     for (int d = 0; d < kMaxDim; ++d) {
         f(t->seed_m[d]);
@@ -681,6 +684,32 @@ void tape_release(hjx_tape *t)
     f(t->acc_out);
     if (t->hacc) (void)hipHostFree(t->hacc);
     delete t;
+}
+
+// bytes of the replay's derivative store: p-, p+ per axis for every stage
+// of a segment
+size_t tape_dp_bytes(const hjx_problem *p, const hjx_tape *t)
+{
+    const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
+    return (size_t)K * (size_t)p->scheme.rk * 2 * (size_t)p->grid.dim * (size_t)p->total * p->elem;
+}
+
+hjx_status tape_alloc_dp(const hjx_problem *p, hjx_tape *t)
+{
+    const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
+    const size_t block = 2 * (size_t)p->grid.dim * (size_t)p->total * p->elem;
+    t->dp.assign((size_t)K * p->scheme.rk, nullptr);
+    for (auto &x : t->dp) {
+        const hipError_t e = hipMalloc(&x, block);
+        if (e != hipSuccess) {
+            for (void *y : t->dp)
+                if (y) (void)hipFree(y);
+            t->dp.clear();
+            return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "derivative store: %s",
+                        hipGetErrorString(e));
+        }
+    }
+    return HJX_OK;
 }
 
 // the steps of a solve from t0 to t1 with CFL step dt (the loop of hjx_solve)
@@ -806,7 +835,40 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
         return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "tape allocation: %s",
                     hipGetErrorString(e));
     }
+    // keep the replay's derivatives when they take at most a quarter of the
+    // free device memory
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && tape_dp_bytes(p, t) <= free_b / 4) {
+        st = tape_alloc_dp(p, t);
+        if (st != HJX_OK) {
+            tape_release(t);
+            return st;
+        }
+    }
     *out = t;
+    return ok();
+}
+
+hjx_status hjx_tape_set_mode(hjx_tape *tape, int32_t mode)
+{
+    if (!tape) return fail(HJX_ERR_INVALID_ARG, "NULL tape");
+    if (mode != HJX_TAPE_RECOMPUTE && mode != HJX_TAPE_STORE_DERIVS)
+        return fail(HJX_ERR_INVALID_ARG, "mode %d: HJX_TAPE_RECOMPUTE or HJX_TAPE_STORE_DERIVS", mode);
+    if (mode == HJX_TAPE_RECOMPUTE) {
+        for (void *x : tape->dp)
+            if (x) (void)hipFree(x);
+        tape->dp.clear();
+        return ok();
+    }
+    if (!tape->dp.empty()) return ok();
+    const hjx_status st = tape_alloc_dp(tape->p, tape);
+    return st == HJX_OK ? ok() : st;
+}
+
+hjx_status hjx_tape_get_mode(const hjx_tape *tape, int32_t *mode)
+{
+    if (!tape || !mode) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    *mode = tape->dp.empty() ? HJX_TAPE_RECOMPUTE : HJX_TAPE_STORE_DERIVS;
     return ok();
 }
 
@@ -865,10 +927,12 @@ namespace {
 // one forward stage for the replay, writing the min-with-target mask
 hipError_t replay_stage(const hjx_problem *p, const double *alpha, const void *in, const void *phin,
                         const void *target, void *out, double h, double ca, double cb, unsigned char *mask,
-                        hipStream_t s)
+                        void *dp_out, hipStream_t s)
 {
     if (p->scheme.dtype == HJX_F32) {
         StageArgs<float> a = stage_args<float>(p, alpha);
+        a.dp_out = static_cast<float *>(dp_out);
+        a.dp_stride = (int)p->total;
         a.phi_in = static_cast<const float *>(in);
         a.phi_n = static_cast<const float *>(phin);
         a.target = static_cast<const float *>(target);
@@ -880,6 +944,8 @@ hipError_t replay_stage(const hjx_problem *p, const double *alpha, const void *i
         return launch_stage_f32(a, p->scheme.deriv, p->ham.kind, s);
     }
     StageArgs<double> a = stage_args<double>(p, alpha);
+    a.dp_out = static_cast<double *>(dp_out);
+    a.dp_stride = (int)p->total;
     a.phi_in = static_cast<const double *>(in);
     a.phi_n = static_cast<const double *>(phin);
     a.target = static_cast<const double *>(target);
@@ -894,9 +960,15 @@ hipError_t replay_stage(const hjx_problem *p, const double *alpha, const void *i
 template <typename T>
 hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,
                            const unsigned char *mask, void *lam_target, void *lam_in, int in_mode, void *lam_n,
-                           int n_mode, double ca, double cb, double h, int h_slot, hipStream_t s)
+                           int n_mode, double ca, double cb, double h, int h_slot, const void *dp, hipStream_t s)
 {
     AdjSeedArgs<T> a{};
+    a.dp_in = static_cast<const T *>(dp);
+    a.dp_stride = (int)p->total;
+    // lam_out is the lam_in of the stage reversed just before, whose per-axis
+    // contributions are still pending
+    if (t->pending)
+        for (int d = 0; d < p->grid.dim; ++d) a.lam_add[a.n_add++] = static_cast<const T *>(t->contrib[d]);
     a.st = stage_args<T>(p, t->alpha);
     a.st.phi_in = static_cast<const T *>(in);
     a.lam_out = static_cast<const T *>(lam_out);
@@ -959,25 +1031,40 @@ hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, co
         else
             x.tw = std::min(nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)), 256 / x.tl);
     }
-    if constexpr (std::is_same<T, float>::value) {
-        if ((e = launch_adj_axes_f32(xs, p->scheme.deriv, s)) != hipSuccess) return e;
-        if (cmb.n) e = launch_combine_f32(static_cast<float *>(lam_in), cmb, (int)p->total, s);
-    } else {
-        if ((e = launch_adj_axes_f64(xs, p->scheme.deriv, s)) != hipSuccess) return e;
-        if (cmb.n) e = launch_combine_f64(static_cast<double *>(lam_in), cmb, (int)p->total, s);
-    }
+    if constexpr (std::is_same<T, float>::value)
+        e = launch_adj_axes_f32(xs, p->scheme.deriv, s);
+    else
+        e = launch_adj_axes_f64(xs, p->scheme.deriv, s);
+    // with several axes the contributions stay in contrib: the next seed
+    // kernel (or the final combine) adds them to lam_in as it reads it
+    t->pending = cmb.n > 0;
     return e;
+}
+
+// lam += the pending per-axis contributions
+hipError_t flush_contrib(const hjx_problem *p, hjx_tape *t, void *lam, hipStream_t s)
+{
+    if (!t->pending) return hipSuccess;
+    t->pending = false;
+    if (p->scheme.dtype == HJX_F32) {
+        AdjCombineArgs<float> c{};
+        for (int d = 0; d < p->grid.dim; ++d) c.c[c.n++] = static_cast<const float *>(t->contrib[d]);
+        return launch_combine_f32(static_cast<float *>(lam), c, (int)p->total, s);
+    }
+    AdjCombineArgs<double> c{};
+    for (int d = 0; d < p->grid.dim; ++d) c.c[c.n++] = static_cast<const double *>(t->contrib[d]);
+    return launch_combine_f64(static_cast<double *>(lam), c, (int)p->total, s);
 }
 
 hipError_t reverse_stage(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,
                          const unsigned char *mask, void *lam_target, void *lam_in, int in_mode, void *lam_n,
-                         int n_mode, double ca, double cb, double h, int h_slot, hipStream_t s)
+                         int n_mode, double ca, double cb, double h, int h_slot, const void *dp, hipStream_t s)
 {
     if (p->scheme.dtype == HJX_F32)
         return reverse_stage_t<float>(p, t, in, lam_out, mask, lam_target, lam_in, in_mode, lam_n, n_mode, ca, cb,
-                                      h, h_slot, s);
+                                      h, h_slot, dp, s);
     return reverse_stage_t<double>(p, t, in, lam_out, mask, lam_target, lam_in, in_mode, lam_n, n_mode, ca, cb, h,
-                                   h_slot, s);
+                                   h_slot, dp, s);
 }
 
 hipError_t zero(const hjx_problem *p, void *x, hipStream_t s)
@@ -1004,6 +1091,7 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
     static const double kCb[3][3] = {{1, 0, 0}, {1, 0.5, 0}, {1, 0.25, 2.0 / 3.0}};
 
     void *lbar = t->lam[0], *lnew = t->lam[1];
+    t->pending = false;
     HIP_TRY(launch_copy(p, dL_dphiT, lbar, s));
     if (dL_dtarget) HIP_TRY(zero(p, dL_dtarget, s));
     HIP_TRY(launch_zero_f64acc(t->acc, kAccCount * t->acc_blocks, s));
@@ -1012,19 +1100,23 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
         const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
         const int len = (int)(s1 - s0);
         auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : t->phin[i]; };
+        auto dp = [&](int i, int k) -> void * { return t->dp.empty() ? nullptr : t->dp[(size_t)i * rk + k]; };
         // replay the segment, keeping every stage input and the masks
         for (int i = 0; i < len; ++i) {
             const double h = s0 + i == t->steps - 1 ? t->dt_last : t->dt;
             if (rk == 1) {
-                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, t->mask[i], s));
+                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, t->mask[i],
+                                     dp(i, 0), s));
             } else if (rk == 2) {
-                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, s));
-                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, t->mask[i], s));
+                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, dp(i, 0), s));
+                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, t->mask[i],
+                                     dp(i, 1), s));
             } else {
-                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, s));
-                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), nullptr, t->xh[i], h, 0.75, 0.25, nullptr, s));
+                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, dp(i, 0), s));
+                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), nullptr, t->xh[i], h, 0.75, 0.25, nullptr,
+                                     dp(i, 1), s));
                 HIP_TRY(replay_stage(p, t->alpha, t->xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0,
-                                     t->mask[i], s));
+                                     t->mask[i], dp(i, 2), s));
             }
         }
         // reverse steps
@@ -1056,12 +1148,13 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
                     n_written = true;
                 }
                 HIP_TRY(reverse_stage(p, t, inputs[k], lout, mk, ltgt, lin, in_mode, lnew, n_mode, ca, cb, h, slot,
-                                      s));
+                                      dp(i, k), s));
                 lout = lin;
             }
             std::swap(lbar, lnew);
         }
     }
+    HIP_TRY(flush_contrib(p, t, lbar, s));
     HIP_TRY(launch_copy(p, lbar, dL_dphi0, s));
 
     HIP_TRY(launch_acc_reduce(t->acc, t->acc_blocks, t->acc_out, s));

@@ -26,6 +26,7 @@ __device__ __forceinline__ StageArgs<T> batch_stage(const BatchInst<T> &I, int s
     a.dt = s == I.steps - 1 ? I.dt_last : I.dt;
     a.rhs_only = 0;
     a.mask = nullptr;
+    a.dp_out = nullptr;
     a.phi_n = nullptr;
     a.ca = T(0);
     a.cb = T(1);

@@ -7,6 +7,13 @@
 
 #include "hjx_internal.h"
 
+// No implicit contraction in any kernel that includes this header: every
+// fused multiply-add is written out (fmaT), so the rounding of each value is
+// fixed by the source and is the same in every kernel, variant, tile and
+// template instantiation that computes it.  (The functions below also carry
+// the pragma locally, which states the same thing where it matters most.)
+#pragma clang fp contract(off)
+
 namespace hjx {
 namespace dev {
 
@@ -75,6 +82,14 @@ __device__ __forceinline__ T ld32(const T *base, int i)
 {
     const unsigned off = (unsigned)i * (unsigned)sizeof(T);
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// The same addressing for an element that is written.
+template <typename T>
+__device__ __forceinline__ T &at32(T *base, int i)
+{
+    const unsigned off = (unsigned)i * (unsigned)sizeof(T);
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
 }
 
 // Gather phi at offsets -3..3 along one axis of node idx (coordinate j of n,
@@ -454,7 +469,8 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
 
 // One node of the direct variant: gather every axis through the caches,
 // both derivative halves at the node, LF Hamiltonian, stage combination.
-template <typename T, int D, int SCHEME, int HAM>
+// KEEP: also write p-, p+ to a.dp_out (the replay of the adjoint).
+template <typename T, int D, int SCHEME, int HAM, bool KEEP = false>
 __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
 {
     int idx = 0;
@@ -467,6 +483,13 @@ __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
         gather7(a.phi_in, idx, j[d], a.g.n[d], a.g.stride[d], (a.g.periodic >> d) & 1u, v);
         center = v[3];
         node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
+    }
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
+            at32(a.dp_out + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx) = pp[d];
+        }
     }
     *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
         stage_result<T, D, HAM>(a, j, pm, pp, center, idx);

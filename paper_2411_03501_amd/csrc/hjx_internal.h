@@ -62,6 +62,8 @@ struct StageArgs {
     int rhs_only;
     Tile tile;
     unsigned char *mask;  // nullable: 1 where the target was the smaller (replay for the adjoint)
+    T *dp_out;            // nullable: p-_d at dp_out + 2d dp_stride, p+_d at dp_out + (2d+1) dp_stride
+    int dp_stride;
 };
 
 // ---------------------------------------------------------------- adjoint
@@ -99,6 +101,10 @@ struct AdjSeedArgs {
     T ca, cb, h;
     double *acc;
     int h_slot;
+    const T *dp_in;            // nullable: p-, p+ stored by the replay (layout of StageArgs::dp_out)
+    int dp_stride;
+    const T *lam_add[kMaxDim]; // lam_out is lam_out + lam_add[0] + ... (added in that order)
+    int n_add;
 };
 
 // lam += transposed derivative intervals along axis d, from the seeds of

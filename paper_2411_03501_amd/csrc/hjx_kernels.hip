@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 // caches (fastest axis along the lanes), both halves evaluated at the node.
 // Best for grids of a few million nodes, where the plane-march tiling cannot
 // keep enough waves in flight.
-template <typename T, int D, int SCHEME, int HAM>
+template <typename T, int D, int SCHEME, int HAM, bool KEEP>
 __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
 {
     // XCD-aware order: the hardware deals consecutive blocks round-robin to
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
         j[D - 1] = jl;
     }
     if constexpr (D <= 2) {  // one plane: no loop over the slow axes
-        direct_node<T, D, SCHEME, HAM>(a, j);
+        direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
         return;
     }
     for (int sy = by; sy < a.g.slow; sy += gridDim.y) {
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
             j[0] = sy / a.g.n[1];
             j[1] = sy - j[0] * a.g.n[1];
         }
-        direct_node<T, D, SCHEME, HAM>(a, j);
+        direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
     }
 }
 
@@ -291,9 +291,10 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
     if (t.variant == kVariantPlaneMarch &&
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
-    if (t.variant == kVariantDirect) {
+    if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
         dim3 grid((a.g.plane + 255) / 256, a.g.slow < 65535 ? a.g.slow : 65535);
-        hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM>), grid, dim3(256), 0, s, a);
+        if (a.dp_out) hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
         return hipGetLastError();
     }
     const size_t lds = stage_lds_bytes(t, sizeof(T));

@@ -71,6 +71,8 @@ SIGNATURES = {
     "hjx_tape_create": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)],
                         ctypes.c_int),
     "hjx_tape_destroy": ([_P], ctypes.c_int),
+    "hjx_tape_set_mode": ([_P, ctypes.c_int32], ctypes.c_int),
+    "hjx_tape_get_mode": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "hjx_solve_taped": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(Stats)], ctypes.c_int),
     "hjx_adjoint": ([_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "hjx_loss_volume": ([_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _P, _P], ctypes.c_int),
@@ -198,6 +200,19 @@ def hjx_tape_create(handle, t0, t1, ckpt_every, stream=None):
 
 def hjx_tape_destroy(tape):
     _check(lib().hjx_tape_destroy(tape))
+
+
+TAPE_RECOMPUTE, TAPE_STORE_DERIVS = 0, 1
+
+
+def hjx_tape_set_mode(tape, mode):
+    _check(lib().hjx_tape_set_mode(tape, int(mode)))
+
+
+def hjx_tape_get_mode(tape):
+    m = ctypes.c_int32()
+    _check(lib().hjx_tape_get_mode(tape, ctypes.byref(m)))
+    return m.value
 
 
 def hjx_solve_taped(handle, tape, phi0_ptr, target_ptr, out_ptr, stream=None):
@@ -389,6 +404,15 @@ class Tape:
             self.close()
         except Exception:
             pass
+
+    @property
+    def mode(self):
+        """TAPE_STORE_DERIVS (the replay keeps p-, p+) or TAPE_RECOMPUTE."""
+        return hjx_tape_get_mode(self.handle)
+
+    @mode.setter
+    def mode(self, m):
+        hjx_tape_set_mode(self.handle, m)
 
     def solve(self, phi0, target=None, out=None, stream=None):
         P = self.problem

@@ -51,9 +51,12 @@ def _setup(w):
     return phi0, Po, eps
 
 
-def _gpu_grads(w, dtype, phi0, eps, ckpt=3, dL_dphiT=None):
+def _gpu_grads(w, dtype, phi0, eps, ckpt=3, dL_dphiT=None, mode=None):
     P = gpu_problem(w, dtype)
     tape = P.tape(w.t1, ckpt_every=ckpt)
+    if mode is not None:
+        tape.mode = mode
+        assert tape.mode == mode
     d0 = to_dev(phi0, TDT[dtype])
     out, st = tape.solve(d0, target=d0 if w.with_target else None)
     if dL_dphiT is None:
@@ -125,6 +128,21 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert np.array_equal(g, ref[0]) and dp == ref[1], ckpt
 
 
+@pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "dubins3_eno3_rk2", "dubins3_eno2_rk1", "car4_weno5_rk3",
+                                  "normal2d_weno5_rk3", "dubins3_multitile"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_stored_and_recomputed_derivatives_give_the_same_bits(case, dtype):
+    """The replay's derivative store is a cache: the reverse sweep that reads
+    it and the one that evaluates the stencils again agree to the bit."""
+    w = CASES[case]
+    phi0, Po, eps = _setup(w)
+    a = _gpu_grads(w, dtype, phi0, eps, mode=hjx.TAPE_STORE_DERIVS)
+    b = _gpu_grads(w, dtype, phi0, eps, mode=hjx.TAPE_RECOMPUTE)
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1]), (case, dtype, np.abs(a[1] - b[1]).max())
+    assert a[2] == b[2]
+
+
 def test_autograd_function():
     w = CASES["dubins3_weno5_rk3"]
     phi0, Po, eps = _setup(w)
@@ -152,3 +170,6 @@ def test_adjoint_argument_rules():
                         P._t(torch.empty_like(d), "gt"))
     with pytest.raises(hjx.HjxError):
         P.tape(w.t1, ckpt_every=0)
+    with pytest.raises(hjx.HjxError, match="mode"):
+        tape.mode = 7
+    assert tape.mode in (hjx.TAPE_RECOMPUTE, hjx.TAPE_STORE_DERIVS)
