@@ -224,7 +224,8 @@ typedef struct hjx_tape hjx_tape;
 /* Create a tape for a solve of p from t0 to t1 (t1 >= t0) with a checkpoint
  * every ckpt_every >= 1 steps.  Runs the dissipation reduction (synchronises
  * `stream`) and allocates the checkpoints and the replay workspace: about
- * (steps/ckpt_every + 3 ckpt_every + 4 + 3 dim) arrays of the problem's size.
+ * (steps/ckpt_every + 6 ckpt_every + 4 + 3 dim) arrays of the problem's size, plus
+ * the derivative store of hjx_tape_set_mode.
  * Arrays must be under 4 GiB each (else HJX_ERR_UNSUPPORTED). */
 hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream,
                            hjx_tape **out);
@@ -232,7 +233,7 @@ hjx_status hjx_tape_destroy(hjx_tape *tape);
 
 /* What the replay keeps for the reverse sweep.  HJX_TAPE_STORE_DERIVS keeps
  * the derivative approximations p-_d, p+_d of every stage of a segment
- * (ckpt_every * rk * 2 dim more arrays of the problem's size), so the
+ * (2 ckpt_every * rk * 2 dim more arrays of the problem's size), so the
  * reverse sweep reads them instead of evaluating the stencils again;
  * HJX_TAPE_RECOMPUTE keeps none.  hjx_tape_create picks STORE_DERIVS when
  * that memory is at most a quarter of the device's free memory.  Both modes
@@ -253,8 +254,10 @@ hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, con
  * gradient of the loss with respect to phi(t1).  dL_dphi0: device array
  * (output).  dL_dtarget: device array (output) or NULL; must be NULL when
  * the solve had no target.  dL_dparams: host array of 8 doubles (output, the
- * entries past the kind's parameter count are 0) or NULL.  Synchronises
- * `stream`. */
+ * entries past the kind's parameter count are 0) or NULL.  The segment
+ * replays run on the tape's own stream (default priority), each overlapping
+ * the reverse sweep of the segment after it; they wait for the work enqueued
+ * on `stream` before the call, and `stream` is synchronised at the end. */
 hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *tape, const void *dL_dphiT, void *dL_dphi0, void *dL_dtarget,
                        double *dL_dparams, void *stream);
 

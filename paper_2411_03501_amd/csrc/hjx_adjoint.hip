@@ -17,7 +17,7 @@
 //                    intervals whose stencils contain it; contributions to
 //                    extrapolated ghost cells are folded back onto the two
 //                    end nodes they were extrapolated from.
-#include "hjx_device.h"
+#include "hjx_adjoint_device.h"
 
 #include <algorithm>
 
@@ -27,6 +27,7 @@ namespace {
 using namespace dev;
 
 constexpr int kSeedThreads = 256;
+constexpr int kAxisThreads = 256;  // block of the per-axis transpose
 
 __device__ __forceinline__ double wave_sum(double x)
 {
@@ -289,12 +290,12 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     __syncthreads();
 
     // transpose every interval I = l0-3+iv once: the NI x tw (interval,
-    // column) pairs are spread evenly over the block's threads, consecutive
+    // column) pairs are spread over all the block's threads (the host sizes
+    // tiles so that there are at most as many pairs as threads), consecutive
     // lanes taking consecutive intervals of a line (lx) or consecutive
     // columns (otherwise), as the LDS layout is laid out
-    const int nthr = tl * tw;
     const float inv_ni = 1.0f / (float)NI;
-    for (int e = active ? tid : NI * tw; e < NI * tw; e += nthr) {
+    for (int e = tid; e < NI * tw; e += kAxisThreads) {  // every thread of the block takes part
         int iv, cc;
         if (lx) {
             cc = (int)(((float)e + 0.5f) * inv_ni);
@@ -358,7 +359,7 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
 // several axes each writes its own contribution array (out), so the blocks of
 // different axes never touch the same memory and overlap freely.
 template <typename T, int SCHEME>
-__global__ __launch_bounds__(256) void adj_axes_kernel(AdjAxesArgs<T> a)
+__global__ __launch_bounds__(kAxisThreads) void adj_axes_kernel(AdjAxesArgs<T> a)
 {
     extern __shared__ unsigned char smem_raw[];
     const int b = (int)blockIdx.x;
@@ -392,7 +393,7 @@ hipError_t launch_axes(const AdjAxesArgs<T> &in, int scheme, hipStream_t s)
     for (int k = 0; k < a.nax; ++k) {
         const AdjAxisArgs<T> &x = a.ax[k];
         const int nd = x.g.n[x.d], nc = x.c >= 0 ? x.g.n[x.c] : 1;
-        if (x.tl < 2 || x.tw < 1 || x.tl * x.tw > 256) return hipErrorInvalidConfiguration;
+        if (x.tl < 2 || x.tw < 1 || (x.tl + 5) * x.tw > kAxisThreads) return hipErrorInvalidConfiguration;
         int rest = 1;
         for (int r = 0; r < 2; ++r)
             if (x.rest[r] >= 0) rest *= x.g.n[x.rest[r]];
@@ -405,10 +406,10 @@ hipError_t launch_axes(const AdjAxesArgs<T> &in, int scheme, hipStream_t s)
     a.start[a.nax] = (int)total;
     const dim3 grid((unsigned)total);
     switch (scheme) {
-    case kSchemeFirst: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeFirst>), grid, dim3(256), lds, s, a); break;
-    case kSchemeEno2: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeEno2>), grid, dim3(256), lds, s, a); break;
-    case kSchemeEno3: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeEno3>), grid, dim3(256), lds, s, a); break;
-    case kSchemeWeno5: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeWeno5>), grid, dim3(256), lds, s, a); break;
+    case kSchemeFirst: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeFirst>), grid, dim3(kAxisThreads), lds, s, a); break;
+    case kSchemeEno2: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeEno2>), grid, dim3(kAxisThreads), lds, s, a); break;
+    case kSchemeEno3: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeEno3>), grid, dim3(kAxisThreads), lds, s, a); break;
+    case kSchemeWeno5: hipLaunchKernelGGL((adj_axes_kernel<T, kSchemeWeno5>), grid, dim3(kAxisThreads), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -645,13 +645,19 @@ struct hjx_tape {
     int64_t steps = 0;
     int K = 1, nseg = 0;
     std::vector<void *> ckpt;          // phi at the start of every segment
-    std::vector<void *> phin, x1, xh;  // replay: stage inputs of each step of a segment
-    std::vector<unsigned char *> mask; // replay: where the target was the smaller
+    // replay workspace, two sets: the replay of one segment (on rstream)
+    // runs while the reverse sweep of the next reads the other set
+    struct ReplaySet {
+        std::vector<void *> phin, x1, xh;  // stage inputs of each step of a segment
+        std::vector<unsigned char *> mask; // where the target was the smaller
+        std::vector<void *> dp;            // p-, p+ of every stage (empty: recompute)
+    } rs[2];
+    hipStream_t rstream = nullptr;
+    hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
     void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
     void *seed_m[kMaxDim] = {}, *seed_p[kMaxDim] = {};
     void *contrib[kMaxDim] = {};       // per-axis transpose contributions (dim >= 2)
     bool pending = false;              // contrib holds sums not yet added to the last lam_in
-    std::vector<void *> dp;            // replay: p-, p+ of every stage of a segment (empty: recompute)
     double *acc = nullptr;             // per seed-kernel block
     int acc_blocks = 0;
     double *acc_out = nullptr;         // device, kAccCount
@@ -669,11 +675,16 @@ void tape_release(hjx_tape *t)
         if (x) (void)hipFree(x);
     };
     for (void *x : t->ckpt) f(x);
-    for (void *x : t->phin) f(x);
-    for (void *x : t->x1) f(x);
-    for (void *x : t->xh) f(x);
-    for (unsigned char *x : t->mask) f(x);
-    for (void *x : t->dp) f(x);
+    for (auto &r : t->rs) {
+        for (void *x : r.phin) f(x);
+        for (void *x : r.x1) f(x);
+        for (void *x : r.xh) f(x);
+        for (unsigned char *x : r.mask) f(x);
+        for (void *x : r.dp) f(x);
+    }
+    for (hipEvent_t e : {t->ev_start, t->ev_rep[0], t->ev_rep[1], t->ev_rev[0], t->ev_rev[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (t->rstream) (void)hipStreamDestroy(t->rstream);
     for (void *x : t->lam) f(x);
     for (int d = 0; d < kMaxDim; ++d) {
         f(t->seed_m[d]);
@@ -687,26 +698,35 @@ void tape_release(hjx_tape *t)
 }
 
 // bytes of the replay's derivative store: p-, p+ per axis for every stage
-// of a segment
+// of a segment, in both replay sets
 size_t tape_dp_bytes(const hjx_problem *p, const hjx_tape *t)
 {
     const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
-    return (size_t)K * (size_t)p->scheme.rk * 2 * (size_t)p->grid.dim * (size_t)p->total * p->elem;
+    return 2 * (size_t)K * (size_t)p->scheme.rk * 2 * (size_t)p->grid.dim * (size_t)p->total * p->elem;
+}
+
+void tape_free_dp(hjx_tape *t)
+{
+    for (auto &r : t->rs) {
+        for (void *x : r.dp)
+            if (x) (void)hipFree(x);
+        r.dp.clear();
+    }
 }
 
 hjx_status tape_alloc_dp(const hjx_problem *p, hjx_tape *t)
 {
     const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
     const size_t block = 2 * (size_t)p->grid.dim * (size_t)p->total * p->elem;
-    t->dp.assign((size_t)K * p->scheme.rk, nullptr);
-    for (auto &x : t->dp) {
-        const hipError_t e = hipMalloc(&x, block);
-        if (e != hipSuccess) {
-            for (void *y : t->dp)
-                if (y) (void)hipFree(y);
-            t->dp.clear();
-            return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "derivative store: %s",
-                        hipGetErrorString(e));
+    for (auto &r : t->rs) {
+        r.dp.assign((size_t)K * p->scheme.rk, nullptr);
+        for (auto &x : r.dp) {
+            const hipError_t e = hipMalloc(&x, block);
+            if (e != hipSuccess) {
+                tape_free_dp(t);
+                return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "derivative store: %s",
+                            hipGetErrorString(e));
+            }
         }
     }
     return HJX_OK;
@@ -807,18 +827,23 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     };
     t->ckpt.assign(t->nseg, nullptr);
     for (auto &x : t->ckpt) grab(&x, field);
-    t->phin.assign(K + 1, nullptr);
-    for (int i = 1; i <= K; ++i) grab(&t->phin[i], field);  // phin[0] is the checkpoint itself
-    if (p->scheme.rk >= 2) {
-        t->x1.assign(K, nullptr);
-        for (auto &x : t->x1) grab(&x, field);
+    for (auto &r : t->rs) {
+        r.phin.assign(K + 1, nullptr);
+        for (int i = 1; i <= K; ++i) grab(&r.phin[i], field);  // phin[0] is the checkpoint itself
+        if (p->scheme.rk >= 2) {
+            r.x1.assign(K, nullptr);
+            for (auto &x : r.x1) grab(&x, field);
+        }
+        if (p->scheme.rk >= 3) {
+            r.xh.assign(K, nullptr);
+            for (auto &x : r.xh) grab(&x, field);
+        }
+        r.mask.assign(K, nullptr);
+        for (auto &x : r.mask) grab(reinterpret_cast<void **>(&x), (size_t)p->total);
     }
-    if (p->scheme.rk >= 3) {
-        t->xh.assign(K, nullptr);
-        for (auto &x : t->xh) grab(&x, field);
-    }
-    t->mask.assign(K, nullptr);
-    for (auto &x : t->mask) grab(reinterpret_cast<void **>(&x), (size_t)p->total);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&t->rstream, hipStreamNonBlocking);
+    for (hipEvent_t *ev : {&t->ev_start, &t->ev_rep[0], &t->ev_rep[1], &t->ev_rev[0], &t->ev_rev[1]})
+        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     for (auto &x : t->lam) grab(&x, field);
     for (int d = 0; d < p->grid.dim; ++d) {
         grab(&t->seed_m[d], field);
@@ -855,12 +880,10 @@ hjx_status hjx_tape_set_mode(hjx_tape *tape, int32_t mode)
     if (mode != HJX_TAPE_RECOMPUTE && mode != HJX_TAPE_STORE_DERIVS)
         return fail(HJX_ERR_INVALID_ARG, "mode %d: HJX_TAPE_RECOMPUTE or HJX_TAPE_STORE_DERIVS", mode);
     if (mode == HJX_TAPE_RECOMPUTE) {
-        for (void *x : tape->dp)
-            if (x) (void)hipFree(x);
-        tape->dp.clear();
+        tape_free_dp(tape);
         return ok();
     }
-    if (!tape->dp.empty()) return ok();
+    if (!tape->rs[0].dp.empty()) return ok();
     const hjx_status st = tape_alloc_dp(tape->p, tape);
     return st == HJX_OK ? ok() : st;
 }
@@ -868,7 +891,7 @@ hjx_status hjx_tape_set_mode(hjx_tape *tape, int32_t mode)
 hjx_status hjx_tape_get_mode(const hjx_tape *tape, int32_t *mode)
 {
     if (!tape || !mode) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
-    *mode = tape->dp.empty() ? HJX_TAPE_RECOMPUTE : HJX_TAPE_STORE_DERIVS;
+    *mode = tape->rs[0].dp.empty() ? HJX_TAPE_RECOMPUTE : HJX_TAPE_STORE_DERIVS;
     return ok();
 }
 
@@ -1021,15 +1044,18 @@ hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, co
         x.dx = T(p->dx[d]);
         const int nd = g.n[d], nc = x.c >= 0 ? g.n[x.c] : 1;
         // line tiles split each axis into equal pieces of at most 64 (fastest
-        // axis, along the lanes) or 32 nodes (other axes, 8 columns of the
-        // fastest axis per block): each piece recomputes 5 intervals beyond it
+        // axis, along the lanes) or 32 nodes (other axes, up to 8 columns of
+        // the fastest axis per block): each piece transposes its tl + 5
+        // intervals, and tw lines are taken so that those (tl + 5) tw
+        // intervals fit the block's 256 threads, one each
         const int cap = d == g.dim - 1 ? 64 : 32;
         const int pieces = (nd + cap - 1) / cap;
         x.tl = std::max(2, (nd + pieces - 1) / pieces);
+        const int fit = std::max(1, 256 / (x.tl + 5));
         if (d == g.dim - 1)
-            x.tw = std::max(1, std::min(256 / x.tl, nc));
+            x.tw = std::max(1, std::min(fit, nc));
         else
-            x.tw = std::min(nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)), 256 / x.tl);
+            x.tw = std::min(nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)), fit);
     }
     if constexpr (std::is_same<T, float>::value)
         e = launch_adj_axes_f32(xs, p->scheme.deriv, s);
@@ -1096,41 +1122,69 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
     if (dL_dtarget) HIP_TRY(zero(p, dL_dtarget, s));
     HIP_TRY(launch_zero_f64acc(t->acc, kAccCount * t->acc_blocks, s));
 
-    for (int seg = t->nseg - 1; seg >= 0; --seg) {
+    // The replay of segment seg - 1 only reads its checkpoint, so it runs on
+    // the tape's own stream, into the other replay set, while the reverse
+    // sweep of segment seg runs on `stream`.  Events order the two: a replay
+    // into a set waits until the reverse sweep that read that set is done;
+    // a reverse sweep waits for the replay of its segment.
+    hipStream_t r = t->rstream;
+    auto replay = [&](int seg) -> hipError_t {
         const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
         const int len = (int)(s1 - s0);
-        auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : t->phin[i]; };
-        auto dp = [&](int i, int k) -> void * { return t->dp.empty() ? nullptr : t->dp[(size_t)i * rk + k]; };
-        // replay the segment, keeping every stage input and the masks
-        for (int i = 0; i < len; ++i) {
+        hjx_tape::ReplaySet &R = t->rs[seg & 1];
+        auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : R.phin[i]; };
+        auto dp = [&](int i, int k) -> void * { return R.dp.empty() ? nullptr : R.dp[(size_t)i * rk + k]; };
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < len && e == hipSuccess; ++i) {
             const double h = s0 + i == t->steps - 1 ? t->dt_last : t->dt;
             if (rk == 1) {
-                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, t->mask[i],
-                                     dp(i, 0), s));
+                e = replay_stage(p, t->alpha, phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, R.mask[i], dp(i, 0),
+                                 r);
             } else if (rk == 2) {
-                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, dp(i, 0), s));
-                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, t->mask[i],
-                                     dp(i, 1), s));
+                e = replay_stage(p, t->alpha, phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0), r);
+                if (e == hipSuccess)
+                    e = replay_stage(p, t->alpha, R.x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, R.mask[i],
+                                     dp(i, 1), r);
             } else {
-                HIP_TRY(replay_stage(p, t->alpha, phin(i), nullptr, nullptr, t->x1[i], h, 0, 1, nullptr, dp(i, 0), s));
-                HIP_TRY(replay_stage(p, t->alpha, t->x1[i], phin(i), nullptr, t->xh[i], h, 0.75, 0.25, nullptr,
-                                     dp(i, 1), s));
-                HIP_TRY(replay_stage(p, t->alpha, t->xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0,
-                                     t->mask[i], dp(i, 2), s));
+                e = replay_stage(p, t->alpha, phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0), r);
+                if (e == hipSuccess)
+                    e = replay_stage(p, t->alpha, R.x1[i], phin(i), nullptr, R.xh[i], h, 0.75, 0.25, nullptr, dp(i, 1),
+                                     r);
+                if (e == hipSuccess)
+                    e = replay_stage(p, t->alpha, R.xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0,
+                                     R.mask[i], dp(i, 2), r);
             }
         }
+        if (e == hipSuccess) e = hipEventRecord(t->ev_rep[seg & 1], r);
+        return e;
+    };
+    HIP_TRY(hipEventRecord(t->ev_start, s));
+    HIP_TRY(hipStreamWaitEvent(r, t->ev_start, 0));
+    if (t->nseg > 0) HIP_TRY(replay(t->nseg - 1));
+    for (int seg = t->nseg - 1; seg >= 0; --seg) {
+        const int b = seg & 1;
+        if (seg > 0) {
+            if (seg + 1 < t->nseg) HIP_TRY(hipStreamWaitEvent(r, t->ev_rev[b ^ 1], 0));
+            HIP_TRY(replay(seg - 1));
+        }
+        HIP_TRY(hipStreamWaitEvent(s, t->ev_rep[b], 0));
+        const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
+        const int len = (int)(s1 - s0);
+        hjx_tape::ReplaySet &R = t->rs[b];
+        auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : R.phin[i]; };
+        auto dp = [&](int i, int k) -> void * { return R.dp.empty() ? nullptr : R.dp[(size_t)i * rk + k]; };
         // reverse steps
         for (int i = len - 1; i >= 0; --i) {
             const int64_t n = s0 + i;
             const double h = n == t->steps - 1 ? t->dt_last : t->dt;
             const int slot = n == t->steps - 1 ? kAccDhLast : kAccDhMain;
-            const void *inputs[3] = {phin(i), rk >= 2 ? t->x1[i] : nullptr, rk >= 3 ? t->xh[i] : nullptr};
+            const void *inputs[3] = {phin(i), rk >= 2 ? R.x1[i] : nullptr, rk >= 3 ? R.xh[i] : nullptr};
             bool n_written = false;
             const void *lout = lbar;
             void *stage_lam[2] = {t->lam[2], t->lam[3]};
             for (int k = rk - 1; k >= 0; --k) {
                 const bool last = k == rk - 1;
-                const unsigned char *mk = last && t->target ? t->mask[i] : nullptr;
+                const unsigned char *mk = last && t->target ? R.mask[i] : nullptr;
                 void *ltgt = last && t->target ? dL_dtarget : nullptr;
                 const double ca = kCa[rk - 1][k], cb = kCb[rk - 1][k];
                 void *lin;
@@ -1153,6 +1207,7 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
             }
             std::swap(lbar, lnew);
         }
+        HIP_TRY(hipEventRecord(t->ev_rev[b], s));
     }
     HIP_TRY(flush_contrib(p, t, lbar, s));
     HIP_TRY(launch_copy(p, lbar, dL_dphi0, s));
