@@ -271,3 +271,42 @@ def test_autotuner_picks_a_valid_tile_and_keeps_results():
     assert us > 0 and tile[1] * tile[2] <= 256
     after, _ = P.solve(d, 0.3, target=d)
     assert torch.equal(before, after)
+
+
+def _reflect_y_theta(a, theta_axis):
+    """phi(x, -y, -theta): y is axis 1 (symmetric grid), theta periodic with
+    nodes k 2 pi / n, so -theta is node (n - k) mod n."""
+    b = np.flip(a, axis=1)
+    n = a.shape[theta_axis]
+    idx = (n - np.arange(n)) % n
+    return np.take(b, idx, axis=theta_axis)
+
+
+@pytest.mark.parametrize("wname,dtype", [("dubins3d", "f64"), ("dubins3d", "f32"), ("car4d", "f32")])
+def test_full_size_full_horizon_properties(wname, dtype):
+    """The whole horizon at the full workload size, in the launch shape the
+    benchmark times (autotuned): the step count of the CFL schedule, the
+    reflection symmetry (x, y, theta) -> (x, -y, -theta) of both games, the
+    tube property phi(T) <= phi0, and FP32 within the FP32 rule of the FP64
+    solve (itself matched to the oracle at reduced sizes)."""
+    w = inputs.WORKLOADS[wname]
+    say(f"full horizon {wname} {dtype} n={w.n} t1={w.t1}")
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+    n_ref = int(math.ceil(w.t1 / O.cfl_dt(Po) - 1e-12))
+    P = gpu_problem(w, dtype)
+    d0 = to_dev(phi0, TDT[dtype])
+    P.tune(d0, reps=2)
+    out, st = P.solve(d0, w.t1, target=d0 if w.with_target else None)
+    assert st["steps"] == n_ref
+    got = to_host(out)
+    sym = np.abs(got - _reflect_y_theta(got, 2)).max()
+    tol = 1e-10 if dtype == "f64" else 1e-5 * (got.max() - got.min())
+    assert sym <= tol, f"reflection asymmetry {sym:.3e}"
+    if w.with_target:  # min with the target after every step: never above it
+        assert (got <= to_host(d0)).all()
+    if dtype == "f32" and wname == "dubins3d":
+        P64 = gpu_problem(w, "f64")
+        ref, _ = P64.solve(to_dev(phi0, torch.float64), w.t1, target=to_dev(phi0, torch.float64))
+        assert_close(got, to_host(ref), "f32", w.periodic, what=f"full horizon {wname} f32 vs f64")
+    say(f"  steps {st['steps']} asymmetry {sym:.3e} tile {P.tile}")
