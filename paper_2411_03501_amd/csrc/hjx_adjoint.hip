@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 T v[7];
-                gather7(st.phi_in, idx, j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
+                if (d == D - 1) gather7_row(st.phi_in, idx, j[d], st.g.n[d], (st.g.periodic >> d) & 1u, v);
+                else gather7(st.phi_in, idx, j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
                 node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], pm[d], pp[d]);
             }
         }
