@@ -5,18 +5,22 @@
 // and p-_d, p+_d are the upwind derivative approximations (LevelSetPy,
 // arXiv 2411.03501: Sec. IV-A..IV-D, Sec. V, Sec. VI).  Its reverse takes
 // two kinds of kernel:
-//   adj_seed_kernel  one thread per node: evaluates p-, p+ and H at phi_in,
-//                    turns lam_out into the seeds w dL/dp-_d, w dL/dp+_d
+//   adj_seed_kernel  one thread per node: reads p-, p+ kept by the replay (or
+//                    evaluates them again) and H at phi_in, turns lam_out
+//                    (plus the per-axis sums still pending from the stage
+//                    reversed before) into the seeds w dL/dp-_d, w dL/dp+_d
 //                    (w = cb h lam_out), writes the pass-through parts of the
 //                    adjoint and accumulates dL/dh, dL/dalpha and dL/dtheta
 //                    per block;
-//   adj_axis_kernel  one launch per axis: every derivative interval along
-//                    the axis is recomputed once in an LDS line tile, its
+//   adj_axes_kernel  one launch for all axes, line tiles of each axis in LDS:
+//                    every derivative interval is recomputed once, its
 //                    transpose applied to the seeds of its two nodes, and
 //                    each node gathers the contributions of the six
 //                    intervals whose stencils contain it; contributions to
 //                    extrapolated ghost cells are folded back onto the two
-//                    end nodes they were extrapolated from.
+//                    end nodes they were extrapolated from.  Each axis writes
+//                    its own sum (added by the next seed kernel, or by
+//                    combine_kernel at the end).
 #include "hjx_adjoint_device.h"
 
 #include <algorithm>
