@@ -130,8 +130,9 @@ def run_gpu(w, dtype, steps, warmup, tile=None):
 def run_adjoint(w, reps=2):
     """Gradient workload: forward solve (plain) vs backward (segment replay +
     reverse sweep, checkpoint every 8 steps) of the smoothed-volume loss,
-    and a central-difference check of dL/dv_e and of dL/dphi0 along a smooth
-    direction on the same GPU."""
+    and central differences (FP64 solves on the same GPU) of dL/dtheta for
+    every Hamiltonian parameter and of dL/dphi0 along three smooth
+    directions."""
     import numpy as np
     import torch
 
@@ -181,25 +182,38 @@ def run_adjoint(w, reps=2):
         Q.close()
         return v
 
-    h = 1e-5 * w.params[0]
-    pp = list(w.params)
-    pm = list(w.params)
-    pp[0] += h
-    pm[0] -= h
-    fd_ve = (loss_at(pp, phi64) - loss_at(pm, phi64)) / (2 * h)
-    d2 = inputs.smooth_field(w.n[:2], 5)
-    delta = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(d2[:, :, None], w.n))).to("cuda")
-    hd = 1e-5
-    fd_phi = (loss_at(w.params, phi64 + hd * delta) - loss_at(w.params, phi64 - hd * delta)) / (2 * hd)
-    adj_phi = float((grad_phi0 * delta).sum())
+    # every Hamiltonian parameter (relative steps) and three smooth
+    # directions of phi0 that do not vary with theta
+    fd_params, rel_params = [], []
+    for m in range(len(w.params)):
+        h = 1e-5 * w.params[m]
+        pp = list(w.params)
+        pm = list(w.params)
+        pp[m] += h
+        pm[m] -= h
+        fd = (loss_at(pp, phi64) - loss_at(pm, phi64)) / (2 * h)
+        fd_params.append(fd)
+        rel_params.append(abs(dp[m] - fd) / max(abs(fd), 1e-12))
+    fd_dirs, adj_dirs, rel_dirs = [], [], []
+    for seed in (5, 6, 7):
+        d2 = inputs.smooth_field(w.n[:2], seed)
+        delta = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(d2[:, :, None], w.n))).to("cuda")
+        hd = 1e-5
+        fd = (loss_at(w.params, phi64 + hd * delta) - loss_at(w.params, phi64 - hd * delta)) / (2 * hd)
+        adj = float((grad_phi0 * delta).sum())
+        fd_dirs.append(fd)
+        adj_dirs.append(adj)
+        rel_dirs.append(abs(adj - fd) / abs(fd))
     tape.close()
     P.close()
+    log(f"  central differences: params rel err {max(rel_params):.1e}, phi0 directions rel err {max(rel_dirs):.1e}")
     return {"workload": f"{w.name}: {'x'.join(map(str, w.n))} FP32, horizon {w.t1}, checkpoint every 8 steps",
             "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "adjoint_over_forward": bwd / fwd,
-            "loss": loss, "dL_dve_adjoint": dp[0], "dL_dve_central_diff": fd_ve,
-            "dL_dphi0_dir_adjoint": adj_phi, "dL_dphi0_dir_central_diff": fd_phi,
-            "rel_err_ve": abs(dp[0] - fd_ve) / abs(fd_ve), "rel_err_phi0": abs(adj_phi - fd_phi) / abs(fd_phi),
-            "central_diff": "FP64 solves, steps 1e-5 (relative for v_e), phi0 direction independent of theta"}
+            "loss": loss, "dL_dparams_adjoint": list(dp[:len(w.params)]), "dL_dparams_central_diff": fd_params,
+            "dL_dphi0_dirs_adjoint": adj_dirs, "dL_dphi0_dirs_central_diff": fd_dirs,
+            "max_rel_err_params": max(rel_params), "max_rel_err_phi0_dirs": max(rel_dirs),
+            "central_diff": "FP64 solves, steps 1e-5 (relative for the parameters), phi0 directions independent "
+                            "of theta; parameters (v_e, v_p, wbar_e, wbar_p)"}
 
 
 def run_batch(reps=2):
@@ -254,6 +268,50 @@ def run_batch(reps=2):
             "batched_updates_per_s": updates / batch_s, "per_member_updates_per_s": updates / single_s,
             "batched_ms": batch_s * 1e3, "per_member_ms": single_s * 1e3, "graph_replay_ms": min(graph_ms),
             "speedup": single_s / batch_s, "shape": {"item_nodes": shape[0], "blocks": shape[1]}}
+
+
+def run_small(reps=20):
+    """The launch-bound workload: normal2d (101^2, FP64, first-order upwind +
+    forward Euler, 40 steps).  Per solve: hjx_solve (host-driven launches,
+    plus its alpha and non-finite checks) against the same solve as a batch
+    of one member (the horizon captured once in a hipGraph and replayed)."""
+    import torch
+
+    from paper_2411_03501_amd import hjx, inputs
+
+    w = inputs.NORMAL2D
+    P = hjx.Problem.from_workload(w, "f64")
+    phi0 = torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=torch.float64)
+    out = torch.empty_like(phi0)
+    _, st = P.solve(phi0, w.t1, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.solve(phi0, w.t1, out=out)
+    torch.cuda.synchronize()
+    single = (time.perf_counter() - t0) / reps
+    B = hjx.Batch([P])
+    shape, _ = B.tune([phi0], [w.t1], out=[out], reps=3)
+    B.solve([phi0], [w.t1], out=[out])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph_ms = []
+    for _ in range(reps):
+        _, bst = B.solve([phi0], [w.t1], out=[out])
+        graph_ms.append(bst[0]["elapsed_ms"])
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t0) / reps
+    B.close()
+    P.close()
+    n = st["steps"]
+    upd = w.points * n
+    log(f"  normal2d: {n} steps, hjx_solve {single * 1e6:.0f} us, batch of one {batched * 1e6:.0f} us "
+        f"(graph {min(graph_ms) * 1e3:.0f} us, shape {shape})")
+    return {"workload": f"normal2d: 101x101 FP64, first-order + forward Euler, {n} steps",
+            "steps": n, "solve_us": single * 1e6, "graph_solve_us": batched * 1e6,
+            "graph_replay_us": min(graph_ms) * 1e3, "us_per_step_graph": min(graph_ms) * 1e3 / n,
+            "updates_per_s": upd / single, "graph_updates_per_s": upd / batched,
+            "graph_shape": {"item_nodes": shape[0], "blocks": shape[1]}}
 
 
 def run_copy(nbytes=1 << 30, reps=4):
@@ -313,7 +371,7 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
-    ap.add_argument("--only", choices=["batch256", "adjoint", "copy"],
+    ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -330,6 +388,8 @@ def main():
             res = run_batch()
         elif args.only == "adjoint":
             res = run_adjoint(inputs.DUBINS3D_81)
+        elif args.only == "normal2d":
+            res = run_small()
         else:
             res = run_copy()
         print(json.dumps({"only": args.only, **res}), flush=True)
@@ -379,6 +439,9 @@ def main():
             "stage_kernel_us": k4 * 1e6,
             "alu_frac": alg_ops_per_point(w4.scheme, w4.ham, w4.dim) * w4.points / k4 / 1e12 / PEAK_VALU_TOPS,
             "hbm_alg_frac": stage_bytes_per_point(w4.rk, w4.with_target, 4) * w4.points / k4 / 1e9 / PEAK_HBM_GBS}
+
+        log("normal2d f64: launch-bound solve, host-driven vs graph replay")
+        extra["normal2d_f64"] = run_small()
 
         log("batch256 f32: batched vs per-member")
         extra["batch256"] = run_batch()
