@@ -31,6 +31,11 @@
  * Threads: a problem handle may be used by one thread at a time; distinct
  *   handles are independent.
  * Limits: 1 <= dim <= 4; 3 <= n[d]; total nodes < 2^31.
+ * Environment: HJX_MAX_WORKSPACE (bytes), read at every create call, caps
+ *   the device workspace one hjx_problem_create, hjx_tape_create or
+ *   hjx_batch_create may allocate (HJX_ERR_OOM beyond it; a tape then keeps
+ *   no derivative store if that would pass the cap); HJX_TUNE_VERBOSE makes
+ *   the autotuners print each candidate's time to stderr.
  */
 #ifndef HJX_H
 #define HJX_H

@@ -49,6 +49,20 @@ hjx_status ok()
                         #call, hipGetErrorString(e_), __func__);                              \
     } while (0)
 
+// Optional cap on the device workspace one create call may allocate
+// (environment variable HJX_MAX_WORKSPACE, bytes; read at every call), for
+// exercising the out-of-memory paths without exhausting the device.
+bool over_workspace_cap(size_t bytes, size_t *cap_out)
+{
+    const char *v = std::getenv("HJX_MAX_WORKSPACE");
+    if (!v || !*v) return false;
+    char *end = nullptr;
+    const unsigned long long cap = std::strtoull(v, &end, 10);
+    if (end == v) return false;
+    *cap_out = (size_t)cap;
+    return bytes > (size_t)cap;
+}
+
 int n_params(int kind)
 {
     switch (kind) {
@@ -397,6 +411,12 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
 
     const size_t field = (size_t)p->total * p->elem;
     const int partials = alpha_blocks((int)p->total);
+    size_t cap = 0;
+    const size_t need = bytes + 2 * field + sizeof(double) * kMaxDim * (1 + (size_t)partials) + sizeof(int);
+    if (over_workspace_cap(need, &cap)) {
+        release(p);
+        return fail(HJX_ERR_OOM, "problem workspace of %zu bytes exceeds HJX_MAX_WORKSPACE=%zu", need, cap);
+    }
     if ((e = hipMalloc(&p->tables, bytes)) != hipSuccess ||
         (e = hipMemcpy(p->tables, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMalloc(&p->ws[0], field)) != hipSuccess || (e = hipMalloc(&p->ws[1], field)) != hipSuccess ||
@@ -658,6 +678,7 @@ struct hjx_tape {
     void *seed_m[kMaxDim] = {}, *seed_p[kMaxDim] = {};
     void *contrib[kMaxDim] = {};       // per-axis transpose contributions (dim >= 2)
     bool pending = false;              // contrib holds sums not yet added to the last lam_in
+    size_t base_bytes = 0;             // device workspace without the derivative store
     double *acc = nullptr;             // per seed-kernel block
     int acc_blocks = 0;
     double *acc_out = nullptr;         // device, kAccCount
@@ -821,6 +842,19 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     t->nseg = (int)((t->steps + t->K - 1) / t->K);
     const size_t field = (size_t)p->total * p->elem;
     const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
+    {
+        const int rk = p->scheme.rk;
+        const size_t sets = 2 * ((size_t)K * (1 + (rk >= 2) + (rk >= 3)) * field + (size_t)K * (size_t)p->total);
+        const size_t need = (size_t)t->nseg * field + sets + 4 * field +
+                            (size_t)p->grid.dim * (p->grid.dim >= 2 ? 3 : 2) * field +
+                            sizeof(double) * kAccCount * ((size_t)adj_seed_blocks(geometry(p)) + 1);
+        size_t cap = 0;
+        if (over_workspace_cap(need, &cap)) {
+            tape_release(t);
+            return fail(HJX_ERR_OOM, "tape workspace of %zu bytes exceeds HJX_MAX_WORKSPACE=%zu", need, cap);
+        }
+        t->base_bytes = need;
+    }
     hipError_t e = hipSuccess;
     auto grab = [&](void **x, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(x, bytes);
@@ -862,8 +896,9 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     }
     // keep the replay's derivatives when they take at most a quarter of the
     // free device memory
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && tape_dp_bytes(p, t) <= free_b / 4) {
+    size_t free_b = 0, total_b = 0, cap = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && tape_dp_bytes(p, t) <= free_b / 4 &&
+        !over_workspace_cap(t->base_bytes + tape_dp_bytes(p, t), &cap)) {
         st = tape_alloc_dp(p, t);
         if (st != HJX_OK) {
             tape_release(t);
@@ -884,6 +919,9 @@ hjx_status hjx_tape_set_mode(hjx_tape *tape, int32_t mode)
         return ok();
     }
     if (!tape->rs[0].dp.empty()) return ok();
+    size_t cap = 0;
+    if (over_workspace_cap(tape->base_bytes + tape_dp_bytes(tape->p, tape), &cap))
+        return fail(HJX_ERR_OOM, "the derivative store would exceed HJX_MAX_WORKSPACE=%zu", cap);
     const hjx_status st = tape_alloc_dp(tape->p, tape);
     return st == HJX_OK ? ok() : st;
 }
@@ -1458,6 +1496,13 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
         if (p->device != p0->device) return fail(HJX_ERR_INVALID_ARG, "problems[%d] is on another device", i);
         if (!direct_ok(geometry(p), p->elem))
             return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: arrays of 4 GiB or more", i);
+    }
+    {
+        const size_t need = (p0->scheme.dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>)) *
+                                (size_t)n + sizeof(int) * (size_t)n;
+        size_t cap = 0;
+        if (over_workspace_cap(need, &cap))
+            return fail(HJX_ERR_OOM, "batch workspace of %zu bytes exceeds HJX_MAX_WORKSPACE=%zu", need, cap);
     }
     hjx_batch *b = new (std::nothrow) hjx_batch;
     if (!b) return fail(HJX_ERR_OOM, "host allocation failed");

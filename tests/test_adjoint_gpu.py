@@ -173,3 +173,31 @@ def test_adjoint_argument_rules():
     with pytest.raises(hjx.HjxError, match="mode"):
         tape.mode = 7
     assert tape.mode in (hjx.TAPE_RECOMPUTE, hjx.TAPE_STORE_DERIVS)
+
+
+def test_tape_workspace_cap(monkeypatch):
+    """The tape honours HJX_MAX_WORKSPACE: too small a cap fails with
+    HJX_ERR_OOM; a cap that fits the tape but not the derivative store gives
+    a tape in recompute mode, whose gradients are the same bits."""
+    w = CASES["dubins3_weno5_rk3"]
+    phi0, Po, eps = _setup(w)
+    P = gpu_problem(w, "f64")
+    monkeypatch.setenv("HJX_MAX_WORKSPACE", "1000")
+    with pytest.raises(hjx.HjxError) as e:
+        P.tape(w.t1, ckpt_every=3)
+    assert e.value.status == hjx.HJX_ERR_OOM
+    field = P.numel * 8
+    # the tape without its store takes well under 60 arrays here; the store
+    # (2 sets x 3 steps x 3 stages x 6 arrays) would not fit beside it
+    monkeypatch.setenv("HJX_MAX_WORKSPACE", str(60 * field))
+    tape = P.tape(w.t1, ckpt_every=3)
+    assert tape.mode == hjx.TAPE_RECOMPUTE
+    with pytest.raises(hjx.HjxError) as e:
+        tape.mode = hjx.TAPE_STORE_DERIVS
+    assert e.value.status == hjx.HJX_ERR_OOM
+    tape.close()
+    monkeypatch.delenv("HJX_MAX_WORKSPACE")
+    a = _gpu_grads(w, "f64", phi0, eps, mode=hjx.TAPE_RECOMPUTE)
+    b = _gpu_grads(w, "f64", phi0, eps)
+    assert np.array_equal(a[1], b[1]) and a[2] == b[2]
+    P.close()

@@ -330,3 +330,66 @@ def test_full_size_full_horizon_properties(wname, dtype):
         assert flips == 0
         assert err <= 1e-2 * rng
     say(f"  steps {st['steps']} asymmetry {sym:.3e} tile {P.tile}")
+
+
+def test_self_convergence_under_refinement():
+    """The reachable set converges as the grid is refined: dubins3d on nested
+    grids 51x51x50, 101x101x100 and 201x201x200 (every node of a coarse grid
+    is a node of the finer ones, theta included), FP64, whole horizon; the
+    difference to the next finer grid on the common nodes shrinks at each
+    refinement, in max-norm away from the kinks and in the mean."""
+    sols = []
+    for k, n in enumerate([(51, 51, 50), (101, 101, 100), (201, 201, 200)]):
+        w = inputs.DUBINS3D.with_(n=n)
+        say(f"refinement {n}")
+        P = gpu_problem(w, "f64")
+        d0 = to_dev(inputs.initial_surface(w), torch.float64)
+        out, st = P.solve(d0, w.t1, target=d0)
+        sols.append(to_host(out))
+        P.close()
+    c0 = sols[0]
+    c1 = sols[1][::2, ::2, ::2]
+    c2 = sols[2][::4, ::4, ::4]
+    e1 = np.abs(c1 - c0)
+    e2 = np.abs(c2 - c1)
+    say(f"  mean |diff| {e1.mean():.3e} -> {e2.mean():.3e}, max {e1.max():.3e} -> {e2.max():.3e}")
+    assert e2.mean() < 0.7 * e1.mean()
+    assert np.quantile(e2, 0.99) < np.quantile(e1, 0.99)
+
+
+def test_resume_from_the_middle_of_the_horizon():
+    """Checkpoint and resume: solving [0, T/2] and then [T/2, T] from the
+    saved state equals the oracle run with the same split (the split changes
+    the clamped steps, so the unsplit run is not the reference)."""
+    w = inputs.DUBINS3D.with_(n=(25, 23, 21), t1=0.9)
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+    mid = 0.5 * w.t1
+    ref_a, na, _ = O.solve(Po, phi0, mid, target=phi0)
+    ref_b, nb, _ = O.solve(Po, ref_a, w.t1, t0=mid, target=phi0)
+    P = gpu_problem(w, "f64")
+    d0 = to_dev(phi0, torch.float64)
+    a, sa = P.solve(d0, mid, target=d0)
+    b, sb = P.solve(a, w.t1, t0=mid, target=d0)
+    assert (sa["steps"], sb["steps"]) == (na, nb)
+    assert_close(to_host(a), ref_a, "f64", w.periodic, what="first half")
+    assert_close(to_host(b), ref_b, "f64", w.periodic, what="resumed")
+
+
+def test_workspace_cap_forces_out_of_memory(monkeypatch):
+    """HJX_MAX_WORKSPACE caps what one create call may allocate: beyond it
+    the call fails with HJX_ERR_OOM and allocates nothing; without it the
+    same call succeeds."""
+    w = CASES["dubins3"]
+    monkeypatch.setenv("HJX_MAX_WORKSPACE", "1000")
+    with pytest.raises(hjx.HjxError) as e:
+        gpu_problem(w, "f64")
+    assert e.value.status == hjx.HJX_ERR_OOM and "HJX_MAX_WORKSPACE" in str(e.value)
+    monkeypatch.delenv("HJX_MAX_WORKSPACE")
+    P = gpu_problem(w, "f64")
+    monkeypatch.setenv("HJX_MAX_WORKSPACE", "10")
+    with pytest.raises(hjx.HjxError) as e:
+        hjx.Batch([P])
+    assert e.value.status == hjx.HJX_ERR_OOM
+    monkeypatch.delenv("HJX_MAX_WORKSPACE")
+    P.close()
