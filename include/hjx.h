@@ -35,7 +35,9 @@
  *   the device workspace one hjx_problem_create, hjx_tape_create or
  *   hjx_batch_create may allocate (HJX_ERR_OOM beyond it; a tape then keeps
  *   no derivative store if that would pass the cap); HJX_TUNE_VERBOSE makes
- *   the autotuners print each candidate's time to stderr.
+ *   the autotuners print each candidate's time to stderr; HJX_TRACE (not
+ *   "0") puts a roctx range around every call and every reverse-sweep
+ *   segment (rocprofv3 --marker-trace shows them).
  */
 #ifndef HJX_H
 #define HJX_H

@@ -18,6 +18,8 @@
 
 #include "hjx_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 using namespace hjx;
 
 namespace {
@@ -62,6 +64,37 @@ bool over_workspace_cap(size_t bytes, size_t *cap_out)
     *cap_out = (size_t)cap;
     return bytes > (size_t)cap;
 }
+
+// roctx ranges around the library's calls (and the segments of a reverse
+// sweep) when the environment variable HJX_TRACE is set to anything but 0;
+// rocprofv3 --marker-trace shows them beside the kernels.
+bool trace_on()
+{
+    const char *v = std::getenv("HJX_TRACE");
+    return v && *v && !(v[0] == '0' && v[1] == 0);
+}
+
+struct TraceRange {
+    bool on;
+    explicit TraceRange(const char *name) : on(trace_on())
+    {
+        if (on) roctxRangePushA(name);
+    }
+    TraceRange(const char *fmt, long a) : on(trace_on())
+    {
+        if (on) {
+            char buf[96];
+            std::snprintf(buf, sizeof buf, fmt, a);
+            roctxRangePushA(buf);
+        }
+    }
+    ~TraceRange()
+    {
+        if (on) roctxRangePop();
+    }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 int n_params(int kind)
 {
@@ -473,6 +506,7 @@ hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t 
 
 hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream, double *best_us)
 {
+    TraceRange trace_("hjx_tune");
     if (!p || !phi) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps %d < 1", reps);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -551,6 +585,7 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream,
 
 hjx_status hjx_dissipation(hjx_problem *p, double *alpha_out, double *dt_out, void *stream)
 {
+    TraceRange trace_("hjx_dissipation");
     if (!p || !alpha_out || !dt_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     double alpha[kMaxDim];
     hjx_status st = device_alpha(p, static_cast<hipStream_t>(stream), alpha);
@@ -562,6 +597,7 @@ hjx_status hjx_dissipation(hjx_problem *p, double *alpha_out, double *dt_out, vo
 
 hjx_status hjx_rhs(hjx_problem *p, const void *phi, void *L_out, void *stream)
 {
+    TraceRange trace_("hjx_rhs");
     if (!p || !phi || !L_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (phi == L_out) return fail(HJX_ERR_INVALID_ARG, "phi and L_out alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -574,6 +610,7 @@ hjx_status hjx_rhs(hjx_problem *p, const void *phi, void *L_out, void *stream)
 
 hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, void *stream)
 {
+    TraceRange trace_("hjx_step");
     if (!p || !phi) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (target == phi) return fail(HJX_ERR_INVALID_ARG, "target aliases phi");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HJX_ERR_INVALID_ARG, "dt %g is not a positive finite step", dt);
@@ -588,6 +625,7 @@ hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, vo
 hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void *phi_out, double t0, double t1,
                      void *stream, hjx_stats *stats)
 {
+    TraceRange trace_("hjx_solve");
     if (!p || !phi0 || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (target && target == phi_out) return fail(HJX_ERR_INVALID_ARG, "target aliases phi_out");
     if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0))
@@ -942,6 +980,7 @@ hjx_status hjx_tape_destroy(hjx_tape *tape)
 hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, const void *target, void *phi_out,
                            void *stream, hjx_stats *stats)
 {
+    TraceRange trace_("hjx_solve_taped");
     if (!p || !tape || !phi0 || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (tape->p != p) return fail(HJX_ERR_INVALID_ARG, "the tape belongs to another problem");
     if (target && target == phi_out) return fail(HJX_ERR_INVALID_ARG, "target aliases phi_out");
@@ -1144,6 +1183,7 @@ extern "C" {
 hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *dL_dphi0, void *dL_dtarget,
                        double *dL_dparams, void *stream)
 {
+    TraceRange trace_("hjx_adjoint");
     if (!p || !t || !dL_dphiT || !dL_dphi0) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (t->p != p) return fail(HJX_ERR_INVALID_ARG, "the tape belongs to another problem");
     if (!t->solved) return fail(HJX_ERR_INVALID_ARG, "the tape holds no solve (call hjx_solve_taped first)");
@@ -1206,6 +1246,7 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
             HIP_TRY(replay(seg - 1));
         }
         HIP_TRY(hipStreamWaitEvent(s, t->ev_rep[b], 0));
+        TraceRange trace_seg("hjx_adjoint reverse segment %ld", (long)seg);
         const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
         const int len = (int)(s1 - s0);
         hjx_tape::ReplaySet &R = t->rs[b];
@@ -1577,6 +1618,7 @@ hjx_status hjx_batch_get_shape(const hjx_batch *b, int32_t *item_nodes, int32_t 
 hjx_status hjx_batch_solve(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
                            const double *t1, void *stream, hjx_stats *stats)
 {
+    TraceRange trace_("hjx_batch_solve");
     if (!b || !phi0 || !phi_out || !t1) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     for (int i = 0; i < b->n; ++i) {
         if (!phi0[i] || !phi_out[i]) return fail(HJX_ERR_INVALID_ARG, "phi0[%d] or phi_out[%d] is NULL", i, i);
@@ -1624,6 +1666,7 @@ hjx_status hjx_batch_solve(hjx_batch *b, const void *const *phi0, const void *co
 hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
                           const double *t1, int32_t reps, void *stream, double *best_ms)
 {
+    TraceRange trace_("hjx_batch_tune");
     if (!b) return fail(HJX_ERR_INVALID_ARG, "NULL batch");
     if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(stream);

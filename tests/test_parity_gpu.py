@@ -393,3 +393,23 @@ def test_workspace_cap_forces_out_of_memory(monkeypatch):
     assert e.value.status == hjx.HJX_ERR_OOM
     monkeypatch.delenv("HJX_MAX_WORKSPACE")
     P.close()
+
+
+def test_trace_ranges_do_not_change_results(monkeypatch):
+    """HJX_TRACE turns on roctx ranges around the calls; results are the
+    same bits with and without."""
+    w = CASES["dubins3"]
+    phi0 = inputs.initial_surface(w)
+    P = gpu_problem(w, "f64")
+    d0 = to_dev(phi0, torch.float64)
+    ref, _ = P.solve(d0, 0.2, target=d0)
+    monkeypatch.setenv("HJX_TRACE", "1")
+    got, _ = P.solve(d0, 0.2, target=d0)
+    tape = P.tape(0.2, ckpt_every=2)
+    out, _ = tape.solve(d0, target=d0)
+    g0, _, _ = tape.adjoint(torch.ones_like(out))
+    monkeypatch.delenv("HJX_TRACE")
+    assert torch.equal(ref, got) and torch.equal(ref, out)
+    assert bool(torch.isfinite(g0).all())
+    tape.close()
+    P.close()
