@@ -226,10 +226,12 @@ hipError_t launch_seed(const AdjSeedArgs<T> &a, int scheme, int ham, hipStream_t
 
 // LDS of one block: phi at l0-5 .. l0+tl+4, the two seeds at l0-3 .. l0+tl+2
 // and the five difference adjoints of each interval l0-3 .. l0+tl+1.
+// (position, column) -> LDS index: columns of npos positions when the line
+// runs along the lanes (LX), else positions of tw = 2^lw columns
 template <bool LX>
-__device__ __forceinline__ int lds_at(int pos, int col, int npos, int tw)
+__device__ __forceinline__ int lds_at(int pos, int col, int npos, int lw)
 {
-    return LX ? col * npos + pos : pos * tw + col;
+    return LX ? col * npos + pos : (pos << lw) + col;
 }
 
 // One line tile of one axis.  LX: the line axis is the fastest axis and
@@ -241,9 +243,12 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
 {
     const int tl = a.tl, tw = a.tw;
     constexpr bool lx = LX;
+    // off the line axis tw is a power of two (the launcher checks): shifts
+    // and masks instead of integer division and multiplication
+    const int lw = lx ? 0 : __builtin_ctz((unsigned)tw);
     const bool active = tid < tl * tw;
-    const int ip = active ? (lx ? tid % tl : tid / tw) : tl;
-    const int ic = active ? (lx ? tid / tl : tid % tw) : 0;
+    const int ip = active ? (lx ? tid % tl : tid >> lw) : tl;
+    const int ic = active ? (lx ? tid / tl : tid & (tw - 1)) : 0;
     const int NP = tl + 10, NS = tl + 6, NI = tl + 5;
     T *PH = reinterpret_cast<T *>(smem_raw);   // NP x tw
     T *SM = PH + NP * tw;                      // NS x tw
@@ -278,7 +283,7 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     };
 
     // stage phi and the seeds of this axis
-    for (int p = active ? ip : NP; p < NP; p += tl) PH[lds_at<LX>(p, ic, NP, tw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
+    for (int p = active ? ip : NP; p < NP; p += tl) PH[lds_at<LX>(p, ic, NP, lw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
     for (int p = active ? ip : NS; p < NS; p += tl) {
         int g = l0 - 3 + p;
         T m = T(0), pl = T(0);
@@ -289,8 +294,8 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
                 pl = ld32(a.seed_p, base + g * sd);
             }
         }
-        SM[lds_at<LX>(p, ic, NS, tw)] = m;
-        SP[lds_at<LX>(p, ic, NS, tw)] = pl;
+        SM[lds_at<LX>(p, ic, NS, lw)] = m;
+        SP[lds_at<LX>(p, ic, NS, lw)] = pl;
     }
     __syncthreads();
 
@@ -306,20 +311,20 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
             cc = (int)(((float)e + 0.5f) * inv_ni);
             iv = e - cc * NI;
         } else {
-            cc = e % tw;
-            iv = e / tw;
+            cc = e & (tw - 1);
+            iv = e >> lw;
         }
         T ub[5] = {T(0), T(0), T(0), T(0), T(0)};
         if (c0 + cc < nc) {
             T v[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) v[k] = PH[lds_at<LX>(iv + k, cc, NP, tw)];
-            const T gm = SM[lds_at<LX>(iv + 1, cc, NS, tw)];  // left-biased seed of node I+1
-            const T gp = SP[lds_at<LX>(iv, cc, NS, tw)];      // right-biased seed of node I
+            for (int k = 0; k < 6; ++k) v[k] = PH[lds_at<LX>(iv + k, cc, NP, lw)];
+            const T gm = SM[lds_at<LX>(iv + 1, cc, NS, lw)];  // left-biased seed of node I+1
+            const T gp = SP[lds_at<LX>(iv, cc, NS, lw)];      // right-biased seed of node I
             interval_vjp<T, SCHEME>(v, a.inv_dx, a.dx, gm, gp, ub);
         }
 #pragma unroll
-        for (int r = 0; r < 5; ++r) UB[lds_at<LX>(iv * 5 + r, cc, NI * 5, tw)] = ub[r];
+        for (int r = 0; r < 5; ++r) UB[lds_at<LX>(iv * 5 + r, cc, NI * 5, lw)] = ub[r];
     }
     __syncthreads();
 
@@ -330,7 +335,7 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
             const int iv = m + 2 - r - (l0 - 3);
-            if (iv >= 0 && iv < NI) s += UB[lds_at<LX>(iv * 5 + r, ic, NI * 5, tw)];
+            if (iv >= 0 && iv < NI) s += UB[lds_at<LX>(iv * 5 + r, ic, NI * 5, lw)];
         }
         return s;
     };
@@ -399,6 +404,7 @@ hipError_t launch_axes(const AdjAxesArgs<T> &in, int scheme, hipStream_t s)
         const AdjAxisArgs<T> &x = a.ax[k];
         const int nd = x.g.n[x.d], nc = x.c >= 0 ? x.g.n[x.c] : 1;
         if (x.tl < 2 || x.tw < 1 || (x.tl + 5) * x.tw > kAxisThreads) return hipErrorInvalidConfiguration;
+        if (x.d != x.g.dim - 1 && (x.tw & (x.tw - 1))) return hipErrorInvalidConfiguration;
         int rest = 1;
         for (int r = 0; r < 2; ++r)
             if (x.rest[r] >= 0) rest *= x.g.n[x.rest[r]];

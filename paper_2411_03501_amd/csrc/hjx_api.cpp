@@ -1131,8 +1131,10 @@ hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, co
         const int fit = std::max(1, 256 / (x.tl + 5));
         if (d == g.dim - 1)
             x.tw = std::max(1, std::min(fit, nc));
-        else
+        else {  // a power of two (the kernel shifts instead of dividing)
             x.tw = std::min(nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)), fit);
+            while (x.tw & (x.tw - 1)) --x.tw;
+        }
     }
     if constexpr (std::is_same<T, float>::value)
         e = launch_adj_axes_f32(xs, p->scheme.deriv, s);
