@@ -226,6 +226,17 @@ hipError_t launch_seed(const AdjSeedArgs<T> &a, int scheme, int ham, hipStream_t
 
 // LDS of one block: phi at l0-5 .. l0+tl+4, the two seeds at l0-3 .. l0+tl+2
 // and the five difference adjoints of each interval l0-3 .. l0+tl+1.
+// j modulo n for |j| < 2n (ghost positions at most 5 beyond an axis of
+// n >= 3 nodes): two corrections each way, with selects
+__device__ __forceinline__ int wrap_near(int j, int n)
+{
+    j += j < 0 ? n : 0;
+    j += j < 0 ? n : 0;
+    j -= j >= n ? n : 0;
+    j -= j >= n ? n : 0;
+    return j;
+}
+
 // (position, column) -> LDS index: columns of npos positions when the line
 // runs along the lanes (LX), else positions of tw = 2^lw columns
 template <bool LX>
@@ -275,7 +286,7 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
 
     auto phi_at = [&](int gpos) -> T {  // with ghosts along d
         if (gpos >= 0 && gpos < nd) return ld32(a.phi, base + gpos * sd);
-        if (per) return ld32(a.phi, base + wrap_index<T>(gpos, nd) * sd);
+        if (per) return ld32(a.phi, base + wrap_near(gpos, nd) * sd);
         const int e = gpos < 0 ? 0 : nd - 1, e2 = gpos < 0 ? 1 : nd - 2;
         const T c = T(gpos < 0 ? -gpos : gpos - (nd - 1));
         const T p0 = ld32(a.phi, base + e * sd), p1 = ld32(a.phi, base + e2 * sd);
@@ -288,7 +299,7 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
         int g = l0 - 3 + p;
         T m = T(0), pl = T(0);
         if (col_ok) {
-            if (g < 0 || g >= nd) g = per ? wrap_index<T>(g, nd) : -1;  // ghosts carry no seed
+            if (g < 0 || g >= nd) g = per ? wrap_near(g, nd) : -1;  // ghosts carry no seed
             if (g >= 0) {
                 m = ld32(a.seed_m, base + g * sd);
                 pl = ld32(a.seed_p, base + g * sd);
@@ -339,9 +350,17 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
         }
         return s;
     };
+    // the two half-nodes of a node of this tile, m = g - 1 and g, read the
+    // intervals ip .. ip + 5, all inside the tile: no bounds checks
+    auto ubar_in = [&](int m) -> T {
+        T s = T(0);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) s += UB[lds_at<LX>((m + 2 - r - (l0 - 3)) * 5 + r, ic, NI * 5, lw)];
+        return s;
+    };
     const int g = l0 + ip;
     if (ip < tl && g < nd && col_ok) {
-        T acc = (ubar(g - 1) - ubar(g)) * a.inv_dx;
+        T acc = (ubar_in(g - 1) - ubar_in(g)) * a.inv_dx;
         if (!per) {
             // ghosts phi[-k] = (1+k) phi_0 - k phi_1 and
             // phi[nd-1+k] = (1+k) phi_{nd-1} - k phi_{nd-2}, k = 1..3
