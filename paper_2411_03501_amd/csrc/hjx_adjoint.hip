@@ -56,8 +56,13 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[V], int lane)
         const bool upper = (lane & off) != 0;
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            const double send = upper ? v[i] : v[i + half];
-            const double keep = upper ? v[i + half] : v[i];
+            // the empty asm pins both values in registers: without it the
+            // two selects fold into one array access at a lane-dependent
+            // index, a chain of selects over all V values
+            double lo = v[i], hi = v[i + half];
+            asm volatile("" : "+v"(lo), "+v"(hi));
+            const double send = upper ? lo : hi;
+            const double keep = upper ? hi : lo;
             v[i] = keep + __shfl_xor(send, off, 64);
         }
     }
@@ -115,12 +120,21 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
 #pragma unroll
         for (int d = 0; d < D; ++d) idx += j[d] * st.g.stride[d];
 
+        // Every load comes first, and nothing waits for one before the
+        // arithmetic, so that a wave waits for memory once (an operand that a
+        // uniform flag leaves out is the constant 0, never a copy of another
+        // load).  The sweep never aliases lam_out, lam_in, lam_n and
+        // lam_target.
         T lo = ld32(a.lam_out, idx);
-        for (int k = 0; k < a.n_add; ++k) lo += ld32(a.lam_add[k], idx);
-        if (a.mask && ld32(a.mask, idx)) {  // the target was kept: its adjoint takes lam_out
-            if (a.lam_target) at32(a.lam_target, idx) += lo;
-            lo = T(0);
-        }
+        T add[kMaxDim];
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) add[k] = k < a.n_add ? ld32(a.lam_add[k], idx) : T(0);
+        // (the mask byte is read unconditionally, from lam_out's first bytes
+        // when there is no mask, so that its test is not a branch on a load)
+        const unsigned char mk = ld32(a.mask ? a.mask : reinterpret_cast<const unsigned char *>(a.lam_out), idx);
+        const T in_old = a.in_mode ? ld32(a.lam_in, idx) : T(0);
+        const T n_old = a.n_mode == 2 ? ld32(a.lam_n, idx) : T(0);
+        const T tg_old = a.lam_target ? ld32(a.lam_target, idx) : T(0);
         T pm[D], pp[D];
         if constexpr (STORED) {  // the replay kept them
 #pragma unroll
@@ -137,6 +151,13 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
                 node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], pm[d], pp[d]);
             }
         }
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k)
+            if (k < a.n_add) lo += add[k];
+        // where the target was kept, its adjoint takes lam_out
+        const bool kept = a.mask != nullptr && mk != 0;
+        const T tg_new = tg_old + lo;
+        if (kept) lo = T(0);
         T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
 #pragma unroll
         for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (pm[d] + pp[d]);
@@ -157,11 +178,12 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
         for (int m = 0; m < NP; ++m) part[1 + D + m] = (double)(w * dmH[m]);
         part[0] = (double)(a.cb * lo) * (double)L;
 
+        if (kept && a.lam_target) at32(a.lam_target, idx) = tg_new;
         const T cin = a.cb * lo;
-        at32(a.lam_in, idx) = a.in_mode ? ld32(a.lam_in, idx) + cin : cin;
+        at32(a.lam_in, idx) = a.in_mode ? in_old + cin : cin;
         if (a.n_mode) {
             const T cn = a.ca * lo;
-            at32(a.lam_n, idx) = a.n_mode == 2 ? ld32(a.lam_n, idx) + cn : cn;
+            at32(a.lam_n, idx) = a.n_mode == 2 ? n_old + cn : cn;
         }
     }
 
@@ -249,10 +271,13 @@ __device__ __forceinline__ int lds_at(int pos, int col, int npos, int lw)
 // runs along the lanes (thread t: position t % tl, column t / tl);
 // otherwise the columns run along the lanes (column t % tw, position t / tw).
 // Threads t >= tl * tw only take part in the barriers.
-template <typename T, int SCHEME, bool LX>
+// TWC > 0 (off the line axis only): the tile width is that constant, so every
+// LDS offset between the accesses of one thread is an immediate.
+template <typename T, int SCHEME, bool LX, int TWC>
 __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int by, int tid, unsigned char *smem_raw)
 {
-    const int tl = a.tl, tw = a.tw;
+    static_assert(TWC == 0 || (!LX && (TWC & (TWC - 1)) == 0), "constant tile widths are powers of two off the line axis");
+    const int tl = a.tl, tw = TWC > 0 ? TWC : a.tw;
     constexpr bool lx = LX;
     // off the line axis tw is a power of two (the launcher checks): shifts
     // and masks instead of integer division and multiplication
@@ -351,16 +376,19 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
         return s;
     };
     // the two half-nodes of a node of this tile, m = g - 1 and g, read the
-    // intervals ip .. ip + 5, all inside the tile: no bounds checks
-    auto ubar_in = [&](int m) -> T {
+    // intervals ip .. ip + 5, all inside the tile: no bounds checks.  Half-node
+    // g - 1 + o (o = 0, 1) takes difference r of interval ip + 4 + o - r, at
+    // position 5 ip + 20 + 5 o - 4 r: one base per thread, constant offsets.
+    const T *ub_node = UB + lds_at<LX>(5 * ip, ic, NI * 5, lw);
+    auto ubar_in = [&](int o) -> T {
         T s = T(0);
 #pragma unroll
-        for (int r = 0; r < 5; ++r) s += UB[lds_at<LX>((m + 2 - r - (l0 - 3)) * 5 + r, ic, NI * 5, lw)];
+        for (int r = 0; r < 5; ++r) s += ub_node[lx ? 20 + 5 * o - 4 * r : (20 + 5 * o - 4 * r) << lw];
         return s;
     };
     const int g = l0 + ip;
     if (ip < tl && g < nd && col_ok) {
-        T acc = (ubar_in(g - 1) - ubar_in(g)) * a.inv_dx;
+        T acc = (ubar_in(0) - ubar_in(1)) * a.inv_dx;
         if (!per) {
             // ghosts phi[-k] = (1+k) phi_0 - k phi_1 and
             // phi[nd-1+k] = (1+k) phi_{nd-1} - k phi_{nd-2}, k = 1..3
@@ -397,8 +425,9 @@ __global__ __launch_bounds__(kAxisThreads) void adj_axes_kernel(AdjAxesArgs<T> a
     const int lb = b - a.start[k];
     const int bx = lb % a.gx[k], by = lb / a.gx[k];
     const AdjAxisArgs<T> &A = a.ax[k];
-    if (A.d == A.g.dim - 1) axis_tile<T, SCHEME, true>(A, bx, by, (int)threadIdx.x, smem_raw);
-    else axis_tile<T, SCHEME, false>(A, bx, by, (int)threadIdx.x, smem_raw);
+    if (A.d == A.g.dim - 1) axis_tile<T, SCHEME, true, 0>(A, bx, by, (int)threadIdx.x, smem_raw);
+    else if (A.tw == 8) axis_tile<T, SCHEME, false, 8>(A, bx, by, (int)threadIdx.x, smem_raw);
+    else axis_tile<T, SCHEME, false, 0>(A, bx, by, (int)threadIdx.x, smem_raw);
 }
 
 // lam += c[0] (+ c[1]) (+ c[2]) (+ c[3]), added in that order
