@@ -261,10 +261,9 @@ hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, con
  * gradient of the loss with respect to phi(t1).  dL_dphi0: device array
  * (output).  dL_dtarget: device array (output) or NULL; must be NULL when
  * the solve had no target.  dL_dparams: host array of 8 doubles (output, the
- * entries past the kind's parameter count are 0) or NULL.  The segment
- * replays run on the tape's own stream (default priority), each overlapping
- * the reverse sweep of the segment after it; they wait for the work enqueued
- * on `stream` before the call, and `stream` is synchronised at the end. */
+ * entries past the kind's parameter count are 0) or NULL.  All work runs on
+ * `stream`: each segment's replay shares launches with the reverse sweep of
+ * the segment after it.  `stream` is synchronised at the end. */
 hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *tape, const void *dL_dphiT, void *dL_dphi0, void *dL_dtarget,
                        double *dL_dparams, void *stream);
 

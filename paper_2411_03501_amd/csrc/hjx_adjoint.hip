@@ -81,11 +81,14 @@ constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 
 
 // ---------------------------------------------------------------- seeds
 
+// Block (bx, by) of the seed pass: nodes bx*256 .. of the plane by of the
+// slow axes; its block sums go to accumulator slot `slot`.  Every thread of
+// the block must call it (block reduction).
 template <typename T, int D, int SCHEME, int HAM, bool STORED>
-__global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a)
+__device__ __forceinline__ void seed_block(const AdjSeedArgs<T> &a, int bx, int by, int slot)
 {
     const StageArgs<T> &st = a.st;
-    const int q = blockIdx.x * kSeedThreads + threadIdx.x;
+    const int q = bx * kSeedThreads + threadIdx.x;
     const bool live = q < st.g.plane;
     // per-node contributions: [0] dL/dh, [1..D] dL/dalpha_d, [D+1..D+NP] dL/dtheta
     constexpr int NP = ham_params<HAM>();
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
             j[D - 2] = jm;
             j[D - 1] = jl;
         }
-        const int sy = blockIdx.y;
+        const int sy = by;
         if constexpr (D == 3) j[0] = sy;
         if constexpr (D == 4) {
             j[0] = sy / st.g.n[1];
@@ -198,16 +201,98 @@ __global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a
         const int k = threadIdx.x;
         double s = 0.0;
         for (int w = 0; w < kSeedThreads / 64; ++w) s += red[w][k];
-        const int slot = k == 0 ? a.h_slot : (k <= D ? kAccAlpha + (k - 1) : kAccTheta + (k - 1 - D));
-        const int b = blockIdx.y * gridDim.x + blockIdx.x;
-        a.acc[b * kAccCount + slot] += s;
+        const int acc_slot = k == 0 ? a.h_slot : (k <= D ? kAccAlpha + (k - 1) : kAccTheta + (k - 1 - D));
+        a.acc[slot * kAccCount + acc_slot] += s;
     }
 }
 
-template <typename T, int D, int SCHEME, int HAM>
-hipError_t launch_seed_one(const AdjSeedArgs<T> &a, hipStream_t s)
+template <typename T, int D, int SCHEME, int HAM, bool STORED>
+__global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a)
 {
-    dim3 grid((a.st.g.plane + kSeedThreads - 1) / kSeedThreads, a.st.g.slow);
+    seed_block<T, D, SCHEME, HAM, STORED>(a, (int)blockIdx.x, (int)blockIdx.y,
+                                          (int)(blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// The seed pass of one reversed stage and one forward stage of the replay of
+// the preceding segment, in one launch.  The two are independent: the seed
+// pass waits on memory, the forward stage on arithmetic, so blocks of both
+// kinds sharing the CUs overlap well.  Both cover the grid in blocks of 256
+// nodes of a plane: nb blocks each (gx per plane).  They are dealt in runs of
+// eight, seed blocks then stage blocks, so that each XCD (blocks go to the
+// eight XCDs in turn) takes both kinds; a block keeps its XCD's residue mod 8
+// in its own numbering, and the stage blocks are renumbered, as in the direct
+// stage kernel, so that each XCD walks a contiguous run of them.  The stage
+// keeps p-, p+ (dp_out) exactly when the seed pass reads them.
+template <typename T, int D, int SCHEME, int HAM, bool STORED>
+__global__ __launch_bounds__(kSeedThreads) void adj_seed_replay_kernel(AdjSeedArgs<T> a, StageArgs<T> r, int gx,
+                                                                       int nb)
+{
+    const int lb = (int)blockIdx.x;
+    const int m = nb & ~7;  // interleaved part; the nb - m leftover blocks of each kind follow
+    bool seed;
+    int idx;
+    if (lb < 2 * m) {
+        seed = ((lb >> 3) & 1) == 0;
+        idx = ((lb >> 4) << 3) | (lb & 7);
+    } else {
+        const int t = lb - 2 * m;
+        seed = t < nb - m;
+        idx = m + (seed ? t : t - (nb - m));
+    }
+    if (seed) {
+        seed_block<T, D, SCHEME, HAM, STORED>(a, idx % gx, idx / gx, idx);
+        return;
+    }
+    if ((nb & 7) == 0) idx = (idx & 7) * (nb >> 3) + (idx >> 3);
+    const int bx = idx % gx, by = idx / gx;
+    const int q = bx * kSeedThreads + threadIdx.x;
+    if (q >= r.g.plane) return;
+    int j[kMaxDim] = {0, 0, 0, 0};
+    if constexpr (D == 1) {
+        j[0] = q;
+    } else {
+        const int nl = r.g.n[D - 1];
+        int jm = (int)((double)q / (double)nl);
+        int jl = q - jm * nl;
+        if (jl < 0) {
+            --jm;
+            jl += nl;
+        } else if (jl >= nl) {
+            ++jm;
+            jl -= nl;
+        }
+        j[D - 2] = jm;
+        j[D - 1] = jl;
+    }
+    if constexpr (D == 3) j[0] = by;
+    if constexpr (D == 4) {
+        j[0] = by / r.g.n[1];
+        j[1] = by - j[0] * r.g.n[1];
+    }
+    direct_node<T, D, SCHEME, HAM, STORED>(r, j);
+}
+
+template <typename T, int D, int SCHEME, int HAM>
+hipError_t launch_seed_one(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, hipStream_t s)
+{
+    const int gx = (a.st.g.plane + kSeedThreads - 1) / kSeedThreads;
+    if (rep) {
+        // same geometry for both jobs; p-, p+ kept exactly when read
+        if ((rep->dp_out != nullptr) != (a.dp_in != nullptr) || rep->g.plane != a.st.g.plane ||
+            rep->g.slow != a.st.g.slow)
+            return hipErrorInvalidValue;
+        const long nb = (long)gx * a.st.g.slow;
+        if (2 * nb > 0x7fffffffL) return hipErrorInvalidConfiguration;
+        const dim3 grid((unsigned)(2 * nb));
+        if (a.dp_in)
+            hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a,
+                               *rep, gx, (int)nb);
+        else
+            hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, false>), grid, dim3(kSeedThreads), 0, s, a,
+                               *rep, gx, (int)nb);
+        return hipGetLastError();
+    }
+    dim3 grid(gx, a.st.g.slow);
     if (a.dp_in)
         hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a);
     else
@@ -216,30 +301,30 @@ hipError_t launch_seed_one(const AdjSeedArgs<T> &a, hipStream_t s)
 }
 
 template <typename T, int D, int HAM>
-hipError_t launch_seed_scheme(const AdjSeedArgs<T> &a, int scheme, hipStream_t s)
+hipError_t launch_seed_scheme(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int scheme, hipStream_t s)
 {
     switch (scheme) {
-    case kSchemeFirst: return launch_seed_one<T, D, kSchemeFirst, HAM>(a, s);
-    case kSchemeEno2: return launch_seed_one<T, D, kSchemeEno2, HAM>(a, s);
-    case kSchemeEno3: return launch_seed_one<T, D, kSchemeEno3, HAM>(a, s);
-    case kSchemeWeno5: return launch_seed_one<T, D, kSchemeWeno5, HAM>(a, s);
+    case kSchemeFirst: return launch_seed_one<T, D, kSchemeFirst, HAM>(a, rep, s);
+    case kSchemeEno2: return launch_seed_one<T, D, kSchemeEno2, HAM>(a, rep, s);
+    case kSchemeEno3: return launch_seed_one<T, D, kSchemeEno3, HAM>(a, rep, s);
+    case kSchemeWeno5: return launch_seed_one<T, D, kSchemeWeno5, HAM>(a, rep, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_seed(const AdjSeedArgs<T> &a, int scheme, int ham, hipStream_t s)
+hipError_t launch_seed(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int scheme, int ham, hipStream_t s)
 {
     if (a.st.g.slow > 65535) return hipErrorInvalidConfiguration;
-    if (ham == kHamDubins3) return a.st.g.dim == 3 ? launch_seed_scheme<T, 3, kHamDubins3>(a, scheme, s)
+    if (ham == kHamDubins3) return a.st.g.dim == 3 ? launch_seed_scheme<T, 3, kHamDubins3>(a, rep, scheme, s)
                                                    : hipErrorInvalidValue;
-    if (ham == kHamDubins4) return a.st.g.dim == 4 ? launch_seed_scheme<T, 4, kHamDubins4>(a, scheme, s)
+    if (ham == kHamDubins4) return a.st.g.dim == 4 ? launch_seed_scheme<T, 4, kHamDubins4>(a, rep, scheme, s)
                                                    : hipErrorInvalidValue;
     switch (a.st.g.dim) {
-    case 1: return launch_seed_scheme<T, 1, kHamNormal>(a, scheme, s);
-    case 2: return launch_seed_scheme<T, 2, kHamNormal>(a, scheme, s);
-    case 3: return launch_seed_scheme<T, 3, kHamNormal>(a, scheme, s);
-    case 4: return launch_seed_scheme<T, 4, kHamNormal>(a, scheme, s);
+    case 1: return launch_seed_scheme<T, 1, kHamNormal>(a, rep, scheme, s);
+    case 2: return launch_seed_scheme<T, 2, kHamNormal>(a, rep, scheme, s);
+    case 3: return launch_seed_scheme<T, 3, kHamNormal>(a, rep, scheme, s);
+    case 4: return launch_seed_scheme<T, 4, kHamNormal>(a, rep, scheme, s);
     }
     return hipErrorInvalidValue;
 }
@@ -550,13 +635,15 @@ hipError_t launch_loss(const T *phi, int n, double eps, double vol, T *grad, dou
 
 int adj_seed_blocks(const GridGeom &g) { return ((g.plane + kSeedThreads - 1) / kSeedThreads) * g.slow; }
 
-hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, int scheme, int ham, hipStream_t s)
+hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, const StageArgs<float> *rep, int scheme, int ham,
+                               hipStream_t s)
 {
-    return launch_seed<float>(a, scheme, ham, s);
+    return launch_seed<float>(a, rep, scheme, ham, s);
 }
-hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham, hipStream_t s)
+hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, const StageArgs<double> *rep, int scheme, int ham,
+                               hipStream_t s)
 {
-    return launch_seed<double>(a, scheme, ham, s);
+    return launch_seed<double>(a, rep, scheme, ham, s);
 }
 hipError_t launch_adj_axes_f32(const AdjAxesArgs<float> &a, int scheme, hipStream_t s)
 {

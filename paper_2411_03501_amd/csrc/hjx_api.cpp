@@ -703,15 +703,13 @@ struct hjx_tape {
     int64_t steps = 0;
     int K = 1, nseg = 0;
     std::vector<void *> ckpt;          // phi at the start of every segment
-    // replay workspace, two sets: the replay of one segment (on rstream)
-    // runs while the reverse sweep of the next reads the other set
+    // replay workspace, two sets: the replay of one segment writes one set
+    // while the reverse sweep of the next reads the other
     struct ReplaySet {
         std::vector<void *> phin, x1, xh;  // stage inputs of each step of a segment
         std::vector<unsigned char *> mask; // where the target was the smaller
         std::vector<void *> dp;            // p-, p+ of every stage (empty: recompute)
     } rs[2];
-    hipStream_t rstream = nullptr;
-    hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
     void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
     void *seed_m[kMaxDim] = {}, *seed_p[kMaxDim] = {};
     void *contrib[kMaxDim] = {};       // per-axis transpose contributions (dim >= 2)
@@ -741,9 +739,6 @@ void tape_release(hjx_tape *t)
         for (unsigned char *x : r.mask) f(x);
         for (void *x : r.dp) f(x);
     }
-    for (hipEvent_t e : {t->ev_start, t->ev_rep[0], t->ev_rep[1], t->ev_rev[0], t->ev_rev[1]})
-        if (e) (void)hipEventDestroy(e);
-    if (t->rstream) (void)hipStreamDestroy(t->rstream);
     for (void *x : t->lam) f(x);
     for (int d = 0; d < kMaxDim; ++d) {
         f(t->seed_m[d]);
@@ -913,9 +908,6 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
         r.mask.assign(K, nullptr);
         for (auto &x : r.mask) grab(reinterpret_cast<void **>(&x), (size_t)p->total);
     }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&t->rstream, hipStreamNonBlocking);
-    for (hipEvent_t *ev : {&t->ev_start, &t->ev_rep[0], &t->ev_rep[1], &t->ev_rev[0], &t->ev_rev[1]})
-        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     for (auto &x : t->lam) grab(&x, field);
     for (int d = 0; d < p->grid.dim; ++d) {
         grab(&t->seed_m[d], field);
@@ -1025,42 +1017,47 @@ hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, con
 namespace {
 
 // one forward stage for the replay, writing the min-with-target mask
-hipError_t replay_stage(const hjx_problem *p, const double *alpha, const void *in, const void *phin,
-                        const void *target, void *out, double h, double ca, double cb, unsigned char *mask,
-                        void *dp_out, hipStream_t s)
+// One forward stage of a replay: out = ca phin + cb (in + h L(in)), min with
+// the target (its mask kept) when target is set, p-, p+ kept in dp (nullable).
+struct ReplayStage {
+    const void *in, *phin, *target;
+    void *out;
+    double h, ca, cb;
+    unsigned char *mask;
+    void *dp;
+};
+
+template <typename T>
+StageArgs<T> replay_args(const hjx_problem *p, const double *alpha, const ReplayStage &r)
 {
-    if (p->scheme.dtype == HJX_F32) {
-        StageArgs<float> a = stage_args<float>(p, alpha);
-        a.dp_out = static_cast<float *>(dp_out);
-        a.dp_stride = (int)p->total;
-        a.phi_in = static_cast<const float *>(in);
-        a.phi_n = static_cast<const float *>(phin);
-        a.target = static_cast<const float *>(target);
-        a.out = static_cast<float *>(out);
-        a.dt = float(h);
-        a.ca = float(ca);
-        a.cb = float(cb);
-        a.mask = target ? mask : nullptr;
-        return launch_stage_f32(a, p->scheme.deriv, p->ham.kind, s);
-    }
-    StageArgs<double> a = stage_args<double>(p, alpha);
-    a.dp_out = static_cast<double *>(dp_out);
+    StageArgs<T> a = stage_args<T>(p, alpha);
+    a.dp_out = static_cast<T *>(r.dp);
     a.dp_stride = (int)p->total;
-    a.phi_in = static_cast<const double *>(in);
-    a.phi_n = static_cast<const double *>(phin);
-    a.target = static_cast<const double *>(target);
-    a.out = static_cast<double *>(out);
-    a.dt = h;
-    a.ca = ca;
-    a.cb = cb;
-    a.mask = target ? mask : nullptr;
-    return launch_stage_f64(a, p->scheme.deriv, p->ham.kind, s);
+    a.phi_in = static_cast<const T *>(r.in);
+    a.phi_n = static_cast<const T *>(r.phin);
+    a.target = static_cast<const T *>(r.target);
+    a.out = static_cast<T *>(r.out);
+    a.dt = T(r.h);
+    a.ca = T(r.ca);
+    a.cb = T(r.cb);
+    a.mask = r.target ? r.mask : nullptr;
+    return a;
 }
 
+hipError_t replay_stage(const hjx_problem *p, const double *alpha, const ReplayStage &r, hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32)
+        return launch_stage_f32(replay_args<float>(p, alpha, r), p->scheme.deriv, p->ham.kind, s);
+    return launch_stage_f64(replay_args<double>(p, alpha, r), p->scheme.deriv, p->ham.kind, s);
+}
+
+// Reverse one stage.  rep (nullable): a forward stage of the replay of the
+// preceding segment, evaluated in the same launch as the seed pass.
 template <typename T>
 hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,
                            const unsigned char *mask, void *lam_target, void *lam_in, int in_mode, void *lam_n,
-                           int n_mode, double ca, double cb, double h, int h_slot, const void *dp, hipStream_t s)
+                           int n_mode, double ca, double cb, double h, int h_slot, const void *dp,
+                           const ReplayStage *rep, hipStream_t s)
 {
     AdjSeedArgs<T> a{};
     a.dp_in = static_cast<const T *>(dp);
@@ -1087,11 +1084,13 @@ hipError_t reverse_stage_t(const hjx_problem *p, hjx_tape *t, const void *in, co
     a.h = T(h);
     a.acc = t->acc;
     a.h_slot = h_slot;
+    StageArgs<T> ra;
+    if (rep) ra = replay_args<T>(p, t->alpha, *rep);
     hipError_t e;
     if constexpr (std::is_same<T, float>::value)
-        e = launch_adj_seed_f32(a, p->scheme.deriv, p->ham.kind, s);
+        e = launch_adj_seed_f32(a, rep ? &ra : nullptr, p->scheme.deriv, p->ham.kind, s);
     else
-        e = launch_adj_seed_f64(a, p->scheme.deriv, p->ham.kind, s);
+        e = launch_adj_seed_f64(a, rep ? &ra : nullptr, p->scheme.deriv, p->ham.kind, s);
     if (e != hipSuccess) return e;
     // the transposes of all axes in one launch; with several axes each
     // writes its own contribution, added to lam_in afterwards in axis order
@@ -1163,13 +1162,14 @@ hipError_t flush_contrib(const hjx_problem *p, hjx_tape *t, void *lam, hipStream
 
 hipError_t reverse_stage(const hjx_problem *p, hjx_tape *t, const void *in, const void *lam_out,
                          const unsigned char *mask, void *lam_target, void *lam_in, int in_mode, void *lam_n,
-                         int n_mode, double ca, double cb, double h, int h_slot, const void *dp, hipStream_t s)
+                         int n_mode, double ca, double cb, double h, int h_slot, const void *dp,
+                         const ReplayStage *rep, hipStream_t s)
 {
     if (p->scheme.dtype == HJX_F32)
         return reverse_stage_t<float>(p, t, in, lam_out, mask, lam_target, lam_in, in_mode, lam_n, n_mode, ca, cb,
-                                      h, h_slot, dp, s);
+                                      h, h_slot, dp, rep, s);
     return reverse_stage_t<double>(p, t, in, lam_out, mask, lam_target, lam_in, in_mode, lam_n, n_mode, ca, cb, h,
-                                   h_slot, dp, s);
+                                   h_slot, dp, rep, s);
 }
 
 hipError_t zero(const hjx_problem *p, void *x, hipStream_t s)
@@ -1202,56 +1202,46 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
     if (dL_dtarget) HIP_TRY(zero(p, dL_dtarget, s));
     HIP_TRY(launch_zero_f64acc(t->acc, kAccCount * t->acc_blocks, s));
 
-    // The replay of segment seg - 1 only reads its checkpoint, so it runs on
-    // the tape's own stream, into the other replay set, while the reverse
-    // sweep of segment seg runs on `stream`.  Events order the two: a replay
-    // into a set waits until the reverse sweep that read that set is done;
-    // a reverse sweep waits for the replay of its segment.
-    hipStream_t r = t->rstream;
-    auto replay = [&](int seg) -> hipError_t {
+    // The replay of segment seg - 1 only reads its checkpoint and writes the
+    // other replay set, so it is independent of the reverse sweep of segment
+    // seg: each reversed stage carries one of its forward stages in the
+    // launch of its seed pass (memory-bound work beside arithmetic-bound
+    // work), and the stages left over, if any, follow the sweep.  Only the
+    // last segment's replay runs on its own.
+    auto plan = [&](int seg) {
+        std::vector<ReplayStage> v;
         const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
         const int len = (int)(s1 - s0);
         hjx_tape::ReplaySet &R = t->rs[seg & 1];
         auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : R.phin[i]; };
         auto dp = [&](int i, int k) -> void * { return R.dp.empty() ? nullptr : R.dp[(size_t)i * rk + k]; };
-        hipError_t e = hipSuccess;
-        for (int i = 0; i < len && e == hipSuccess; ++i) {
+        for (int i = 0; i < len; ++i) {
             const double h = s0 + i == t->steps - 1 ? t->dt_last : t->dt;
             if (rk == 1) {
-                e = replay_stage(p, t->alpha, phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, R.mask[i], dp(i, 0),
-                                 r);
+                v.push_back({phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, R.mask[i], dp(i, 0)});
             } else if (rk == 2) {
-                e = replay_stage(p, t->alpha, phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0), r);
-                if (e == hipSuccess)
-                    e = replay_stage(p, t->alpha, R.x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, R.mask[i],
-                                     dp(i, 1), r);
+                v.push_back({phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0)});
+                v.push_back({R.x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, R.mask[i], dp(i, 1)});
             } else {
-                e = replay_stage(p, t->alpha, phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0), r);
-                if (e == hipSuccess)
-                    e = replay_stage(p, t->alpha, R.x1[i], phin(i), nullptr, R.xh[i], h, 0.75, 0.25, nullptr, dp(i, 1),
-                                     r);
-                if (e == hipSuccess)
-                    e = replay_stage(p, t->alpha, R.xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0,
-                                     R.mask[i], dp(i, 2), r);
+                v.push_back({phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0)});
+                v.push_back({R.x1[i], phin(i), nullptr, R.xh[i], h, 0.75, 0.25, nullptr, dp(i, 1)});
+                v.push_back(
+                    {R.xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0, R.mask[i], dp(i, 2)});
             }
         }
-        if (e == hipSuccess) e = hipEventRecord(t->ev_rep[seg & 1], r);
-        return e;
+        return v;
     };
-    HIP_TRY(hipEventRecord(t->ev_start, s));
-    HIP_TRY(hipStreamWaitEvent(r, t->ev_start, 0));
-    if (t->nseg > 0) HIP_TRY(replay(t->nseg - 1));
+    if (t->nseg > 0) {
+        TraceRange trace_rep("hjx_adjoint replay of segment %ld", (long)(t->nseg - 1));
+        for (const ReplayStage &r : plan(t->nseg - 1)) HIP_TRY(replay_stage(p, t->alpha, r, s));
+    }
     for (int seg = t->nseg - 1; seg >= 0; --seg) {
-        const int b = seg & 1;
-        if (seg > 0) {
-            if (seg + 1 < t->nseg) HIP_TRY(hipStreamWaitEvent(r, t->ev_rev[b ^ 1], 0));
-            HIP_TRY(replay(seg - 1));
-        }
-        HIP_TRY(hipStreamWaitEvent(s, t->ev_rep[b], 0));
         TraceRange trace_seg("hjx_adjoint reverse segment %ld", (long)seg);
+        const std::vector<ReplayStage> next = seg > 0 ? plan(seg - 1) : std::vector<ReplayStage>();
+        size_t carried = 0;
         const int64_t s0 = (int64_t)seg * t->K, s1 = std::min<int64_t>(t->steps, s0 + t->K);
         const int len = (int)(s1 - s0);
-        hjx_tape::ReplaySet &R = t->rs[b];
+        hjx_tape::ReplaySet &R = t->rs[seg & 1];
         auto phin = [&](int i) -> void * { return i == 0 ? t->ckpt[seg] : R.phin[i]; };
         auto dp = [&](int i, int k) -> void * { return R.dp.empty() ? nullptr : R.dp[(size_t)i * rk + k]; };
         // reverse steps
@@ -1282,13 +1272,14 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
                     n_mode = n_written ? 2 : 1;
                     n_written = true;
                 }
+                const ReplayStage *rep = carried < next.size() ? &next[carried++] : nullptr;
                 HIP_TRY(reverse_stage(p, t, inputs[k], lout, mk, ltgt, lin, in_mode, lnew, n_mode, ca, cb, h, slot,
-                                      dp(i, k), s));
+                                      dp(i, k), rep, s));
                 lout = lin;
             }
             std::swap(lbar, lnew);
         }
-        HIP_TRY(hipEventRecord(t->ev_rev[b], s));
+        for (; carried < next.size(); ++carried) HIP_TRY(replay_stage(p, t->alpha, next[carried], s));
     }
     HIP_TRY(flush_contrib(p, t, lbar, s));
     HIP_TRY(launch_copy(p, lbar, dL_dphi0, s));

@@ -179,8 +179,12 @@ hipError_t launch_batch_f64(const BatchArgs<double> &a, int scheme, int blocks, 
 // resident blocks of the batch kernel on one CU (occupancy)
 int batch_blocks_per_cu(int dtype_f64, int scheme);
 
-hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, int scheme, int ham, hipStream_t s);
-hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, int scheme, int ham, hipStream_t s);
+// The seed pass; with rep (nullable) one forward stage of the replay (same
+// grid; p-, p+ kept exactly when a.dp_in is set) runs in the same launch.
+hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, const StageArgs<float> *rep, int scheme, int ham,
+                               hipStream_t s);
+hipError_t launch_adj_seed_f64(const AdjSeedArgs<double> &a, const StageArgs<double> *rep, int scheme, int ham,
+                               hipStream_t s);
 hipError_t launch_adj_axes_f32(const AdjAxesArgs<float> &a, int scheme, hipStream_t s);
 hipError_t launch_adj_axes_f64(const AdjAxesArgs<double> &a, int scheme, hipStream_t s);
 hipError_t launch_combine_f32(float *lam, const AdjCombineArgs<float> &c, int n, hipStream_t s);
