@@ -13,6 +13,8 @@
 // the tiling.
 #include "hjx_device.h"
 
+#include <type_traits>
+
 namespace hjx {
 namespace {
 
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 // Best for grids of a few million nodes, where the plane-march tiling cannot
 // keep enough waves in flight.
 template <typename T, int D, int SCHEME, int HAM, bool KEEP>
-__global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
+__device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 {
     // XCD-aware order: the hardware deals consecutive blocks round-robin to
     // the 8 XCDs, each with its own L2.  Renumber the blocks so that each
@@ -279,6 +281,24 @@ __global__ __launch_bounds__(256) void stage_direct_kernel(StageArgs<T> a)
     }
 }
 
+// FP32: at most 96 scalar registers, so that 8 waves fit on a SIMD (the
+// vector registers allow 8; the compiler's own choice, about 106 scalar
+// registers, allows 7).  The few scalar values over the cap live in vector
+// lanes: a handful of lane moves per thread, against an eighth more waves
+// to hide latency (about 2% faster at 101^3).
+template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void stage_direct_kernel(StageArgs<T> a)
+{
+    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
+}
+
+// FP64: the vector registers bound the occupancy (5 waves), so no cap.
+template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+__global__ __launch_bounds__(256) void stage_direct_kernel_f64(StageArgs<T> a)
+{
+    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
+}
+
 template <typename T, int D, int SCHEME, int HAM>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
@@ -293,8 +313,14 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         return hipErrorInvalidConfiguration;
     if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
         dim3 grid((a.g.plane + 255) / 256, a.g.slow < 65535 ? a.g.slow : 65535);
-        if (a.dp_out) hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
+        if constexpr (std::is_same<T, float>::value) {
+            if (a.dp_out) hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
+        } else {
+            if (a.dp_out)
+                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
+        }
         return hipGetLastError();
     }
     const size_t lds = stage_lds_bytes(t, sizeof(T));
