@@ -368,8 +368,12 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     // and masks instead of integer division and multiplication
     const int lw = lx ? 0 : __builtin_ctz((unsigned)tw);
     const bool active = tid < tl * tw;
-    const int ip = active ? (lx ? tid % tl : tid >> lw) : tl;
-    const int ic = active ? (lx ? tid / tl : tid & (tw - 1)) : 0;
+    // along the lanes, t / tl as (t + 1/2) times a one-ulp reciprocal: t < 256
+    // and tl <= 64 keep the product within 1e-4 of the exact quotient, whose
+    // fraction is at least 1/128 from an integer
+    const int qt = lx ? (int)(((float)tid + 0.5f) * __builtin_amdgcn_rcpf((float)tl)) : 0;
+    const int ip = active ? (lx ? tid - qt * tl : tid >> lw) : tl;
+    const int ic = active ? (lx ? qt : tid & (tw - 1)) : 0;
     const int NP = tl + 10, NS = tl + 6, NI = tl + 5;
     T *PH = reinterpret_cast<T *>(smem_raw);   // NP x tw
     T *SM = PH + NP * tw;                      // NS x tw
@@ -379,23 +383,24 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     const int d = a.d, nd = a.g.n[d], sd = a.g.stride[d];
     const bool per = (a.g.periodic >> d) & 1u;
     const int nc = a.c >= 0 ? a.g.n[a.c] : 1, sc = a.c >= 0 ? a.g.stride[a.c] : 0;
-    const int tiles_d = (nd + tl - 1) / tl;
-    const int l0 = (bx % tiles_d) * tl, c0 = (bx / tiles_d) * tw;
+    const int tiles_d = a.tiles_d;
+    const int ct = udiv(bx, tiles_d, a.m_tiles);
+    const int l0 = (bx - ct * tiles_d) * tl, c0 = ct * tw;
     const int col = c0 + ic;
     const bool col_ok = active && col < nc;
     int base = col_ok ? col * sc : 0;
-    {
-        int r = by;
-        for (int k = 1; k >= 0; --k)
-            if (a.rest[k] >= 0) {
-                const int n = a.g.n[a.rest[k]];
-                base += (r % n) * a.g.stride[a.rest[k]];
-                r /= n;
-            }
+    // the remaining axes: by = r0 n1 + r1 (one of them, or none, may be absent)
+    if (a.rest[1] >= 0) {
+        const int n1 = a.g.n[a.rest[1]];
+        const int r0 = udiv(by, n1, a.m_rest1);
+        base += (by - r0 * n1) * a.g.stride[a.rest[1]] + r0 * a.g.stride[a.rest[0]];
+    } else if (a.rest[0] >= 0) {
+        base += by * a.g.stride[a.rest[0]];
     }
 
-    auto phi_at = [&](int gpos) -> T {  // with ghosts along d
-        if (gpos >= 0 && gpos < nd) return ld32(a.phi, base + gpos * sd);
+    // a ghost along d: periodic wrap, else linear extrapolation from the two
+    // end nodes
+    auto phi_ghost = [&](int gpos) -> T {
         if (per) return ld32(a.phi, base + wrap_near(gpos, nd) * sd);
         const int e = gpos < 0 ? 0 : nd - 1, e2 = gpos < 0 ? 1 : nd - 2;
         const T c = T(gpos < 0 ? -gpos : gpos - (nd - 1));
@@ -403,20 +408,37 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
         return fmaT(c, p0 - p1, p0);
     };
 
-    // stage phi and the seeds of this axis
-    for (int p = active ? ip : NP; p < NP; p += tl) PH[lds_at<LX>(p, ic, NP, lw)] = col_ok ? phi_at(l0 - 5 + p) : T(0);
-    for (int p = active ? ip : NS; p < NS; p += tl) {
-        int g = l0 - 3 + p;
-        T m = T(0), pl = T(0);
-        if (col_ok) {
-            if (g < 0 || g >= nd) g = per ? wrap_near(g, nd) : -1;  // ghosts carry no seed
-            if (g >= 0) {
-                m = ld32(a.seed_m, base + g * sd);
-                pl = ld32(a.seed_p, base + g * sd);
-            }
+    // stage phi and the seeds of this axis: thread (ip, ic) takes positions
+    // ip, ip + tl, ... of column ic, stepping its offset by tl strides (the
+    // line axis along the lanes is the fastest axis: stride 1)
+    const int sdl = lx ? 1 : sd;
+    const int step = tl * sdl;
+    if (active) {
+        int gpos = l0 - 5 + ip, off = base + gpos * sdl;
+        for (int p = ip; p < NP; p += tl, gpos += tl, off += step) {
+            T v = T(0);
+            if (col_ok) v = (unsigned)gpos < (unsigned)nd ? ld32(a.phi, off) : phi_ghost(gpos);
+            PH[lds_at<LX>(p, ic, NP, lw)] = v;
         }
-        SM[lds_at<LX>(p, ic, NS, lw)] = m;
-        SP[lds_at<LX>(p, ic, NS, lw)] = pl;
+        gpos = l0 - 3 + ip;
+        off = base + gpos * sdl;
+        for (int p = ip; p < NS; p += tl, gpos += tl, off += step) {
+            T m = T(0), pl = T(0);
+            if (col_ok) {
+                int o = off;
+                bool has = (unsigned)gpos < (unsigned)nd;
+                if (!has && per) {  // ghosts carry no seed unless they wrap
+                    o = base + wrap_near(gpos, nd) * sd;
+                    has = true;
+                }
+                if (has) {
+                    m = ld32(a.seed_m, o);
+                    pl = ld32(a.seed_p, o);
+                }
+            }
+            SM[lds_at<LX>(p, ic, NS, lw)] = m;
+            SP[lds_at<LX>(p, ic, NS, lw)] = pl;
+        }
     }
     __syncthreads();
 
@@ -425,7 +447,7 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     // tiles so that there are at most as many pairs as threads), consecutive
     // lanes taking consecutive intervals of a line (lx) or consecutive
     // columns (otherwise), as the LDS layout is laid out
-    const float inv_ni = 1.0f / (float)NI;
+    const float inv_ni = __builtin_amdgcn_rcpf((float)NI);  // e < 256, NI <= 69: as above
     for (int e = tid; e < NI * tw; e += kAxisThreads) {  // every thread of the block takes part
         int iv, cc;
         if (lx) {
@@ -508,7 +530,7 @@ __global__ __launch_bounds__(kAxisThreads) void adj_axes_kernel(AdjAxesArgs<T> a
     int k = 0;
     while (k + 1 < a.nax && b >= a.start[k + 1]) ++k;
     const int lb = b - a.start[k];
-    const int bx = lb % a.gx[k], by = lb / a.gx[k];
+    const int by = udiv(lb, a.gx[k], a.m_gx[k]), bx = lb - by * a.gx[k];
     const AdjAxisArgs<T> &A = a.ax[k];
     if (A.d == A.g.dim - 1) axis_tile<T, SCHEME, true, 0>(A, bx, by, (int)threadIdx.x, smem_raw);
     else if (A.tw == 8) axis_tile<T, SCHEME, false, 8>(A, bx, by, (int)threadIdx.x, smem_raw);
@@ -541,9 +563,13 @@ hipError_t launch_axes(const AdjAxesArgs<T> &in, int scheme, hipStream_t s)
         int rest = 1;
         for (int r = 0; r < 2; ++r)
             if (x.rest[r] >= 0) rest *= x.g.n[x.rest[r]];
-        a.gx[k] = ((nd + x.tl - 1) / x.tl) * ((nc + x.tw - 1) / x.tw);
+        a.ax[k].tiles_d = (nd + x.tl - 1) / x.tl;
+        a.gx[k] = a.ax[k].tiles_d * ((nc + x.tw - 1) / x.tw);
         a.start[k] = (int)total;
         total += (long)a.gx[k] * rest;
+        a.m_gx[k] = fast_div_multiplier(a.gx[k], (long)a.gx[k] * rest);
+        a.ax[k].m_tiles = fast_div_multiplier(a.ax[k].tiles_d, a.gx[k]);
+        a.ax[k].m_rest1 = x.rest[1] >= 0 ? fast_div_multiplier(x.g.n[x.rest[1]], rest) : 0;
         lds = std::max(lds, sizeof(T) * (size_t)x.tw * ((x.tl + 10) + 2 * (x.tl + 6) + 5 * (x.tl + 5)));
     }
     if (total > 0x7fffffffL) return hipErrorInvalidConfiguration;

@@ -120,7 +120,27 @@ struct AdjAxisArgs {
     T inv_dx, dx;
     int tl, tw;
     T *out;          // nullable: write the contribution here instead of adding it to lam
+    // filled in by the launcher: line tiles per line and the divisors below
+    // as multipliers for udiv()
+    int tiles_d;
+    unsigned m_tiles, m_rest1;
 };
+
+// x / d for a uniform divisor d, from m = fast_div_multiplier(d, bound):
+// m = 0 means d = 1; m = 1 means x d may reach 2^32 (plain division);
+// otherwise m = ceil(2^32 / d), exact for 0 <= x < bound with bound d <= 2^32.
+__device__ __forceinline__ int udiv(int x, int d, unsigned m)
+{
+    if (m == 0) return x;
+    if (m == 1) return x / d;
+    return (int)__umulhi((unsigned)x, m);
+}
+inline unsigned fast_div_multiplier(long d, long bound)
+{
+    if (d <= 1) return 0;
+    if ((unsigned long long)bound * (unsigned long long)d > 0x100000000ull) return 1;
+    return (unsigned)((0x100000000ull + (unsigned long long)d - 1) / (unsigned long long)d);
+}
 
 // The transposes of several axes in one launch (start and gx are filled in
 // by the launcher).
@@ -130,6 +150,7 @@ struct AdjAxesArgs {
     int nax;
     int start[kMaxDim + 1];
     int gx[kMaxDim];
+    unsigned m_gx[kMaxDim];
 };
 
 // lam += c[0] + ... + c[n-1], in that order
