@@ -81,169 +81,231 @@ constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 
 
 // ---------------------------------------------------------------- seeds
 
-// Block (bx, by) of the seed pass: nodes bx*256 .. of the plane by of the
-// slow axes; its block sums go to accumulator slot `slot`.  Every thread of
-// the block must call it (block reduction).
+// Planes of the slow axes per seed block: with two, each thread has the
+// loads of two nodes in flight at once and the block reduction serves twice
+// the nodes.  Only FP32 with stored derivatives stays within 64 vector
+// registers (8 waves per SIMD) that way.
+template <typename T, int D, bool STORED>
+constexpr int seed_planes()
+{
+    return sizeof(T) == 4 && STORED && D >= 3 ? 2 : 1;
+}
+
+// The operands of one node of the seed pass, all loaded before any is used.
+template <typename T, int D>
+struct SeedNode {
+    int idx, j[kMaxDim];
+    T lo, add[kMaxDim], in_old, n_old, tg_old;
+    unsigned char mk;
+    T pm[D], pp[D];
+    HamTab<T> tb;
+};
+
+// Every load of a node, issued before any arithmetic needs one, so that a
+// wave waits for memory once (an operand that a uniform flag leaves out is
+// the constant 0, never a copy of another load).  The sweep never aliases
+// lam_out, lam_in, lam_n and lam_target.
 template <typename T, int D, int SCHEME, int HAM, bool STORED>
-__device__ __forceinline__ void seed_block(const AdjSeedArgs<T> &a, int bx, int by, int slot)
+__device__ __forceinline__ void seed_load(const AdjSeedArgs<T> &a, SeedNode<T, D> &s)
 {
     const StageArgs<T> &st = a.st;
+    const int idx = s.idx;
+    s.lo = ld32(a.lam_out, idx);
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k) s.add[k] = k < a.n_add ? ld32(a.lam_add[k], idx) : T(0);
+    // (the mask byte is read unconditionally, from lam_out's first bytes
+    // when there is no mask, so that its test is not a branch on a load)
+    s.mk = ld32(a.mask ? a.mask : reinterpret_cast<const unsigned char *>(a.lam_out), idx);
+    s.in_old = a.in_mode ? ld32(a.lam_in, idx) : T(0);
+    s.n_old = a.n_mode == 2 ? ld32(a.lam_n, idx) : T(0);
+    s.tg_old = a.lam_target ? ld32(a.lam_target, idx) : T(0);
+    if constexpr (STORED) {  // the replay kept them
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            s.pm[d] = ld32(a.dp_in + (size_t)(2 * d) * (size_t)a.dp_stride, idx);
+            s.pp[d] = ld32(a.dp_in + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            T v[7];
+            if (d == D - 1) gather7_row(st.phi_in, idx, s.j[d], st.g.n[d], (st.g.periodic >> d) & 1u, v);
+            else gather7(st.phi_in, idx, s.j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
+            node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], s.pm[d], s.pp[d]);
+        }
+    }
+    s.tb = ham_tab<T, D, HAM>(st, s.j);
+}
+
+// The arithmetic and stores of one node; its block-sum terms are added to
+// part: [0] dL/dh, [1..D] dL/dalpha_d, [D+1..D+NP] dL/dtheta.
+template <typename T, int D, int HAM, int V>
+__device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedNode<T, D> &s, double (&part)[V])
+{
+    const StageArgs<T> &st = a.st;
+    constexpr int NP = ham_params<HAM>();
+    const int idx = s.idx;
+    T lo = s.lo;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k)
+        if (k < a.n_add) lo += s.add[k];
+    // where the target was kept, its adjoint takes lam_out
+    const bool kept = a.mask != nullptr && s.mk != 0;
+    const T tg_new = s.tg_old + lo;
+    if (kept) lo = T(0);
+    T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
+#pragma unroll
+    for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (s.pm[d] + s.pp[d]);
+    T hhat = ham_grad<T, D, HAM>(st, s.tb, pbar, dHdp, dmH);
+#pragma unroll
+    for (int d = 0; d < D; ++d) hhat = fmaT(-st.alpha[d], T(0.5) * (s.pp[d] - s.pm[d]), hhat);
+    const T L = -hhat;
+
+    const T w = a.cb * a.h * lo;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
+        at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
+        at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
+        part[1 + d] += (double)(w * T(0.5) * (s.pp[d] - s.pm[d]));
+    }
+#pragma unroll
+    for (int m = 0; m < NP; ++m) part[1 + D + m] += (double)(w * dmH[m]);
+    part[0] += (double)(a.cb * lo) * (double)L;
+
+    if (kept && a.lam_target) at32(a.lam_target, idx) = tg_new;
+    const T cin = a.cb * lo;
+    at32(a.lam_in, idx) = a.in_mode ? s.in_old + cin : cin;
+    if (a.n_mode) {
+        const T cn = a.ca * lo;
+        at32(a.lam_n, idx) = a.n_mode == 2 ? s.n_old + cn : cn;
+    }
+}
+
+// Block (bx, by) of the seed pass: nodes bx*256 .. of the planes
+// by*P .. by*P+P-1 of the slow axes (P = seed_planes), gx blocks per plane.
+// Every thread of the block must call it (block reduction).
+template <typename T, int D, int SCHEME, int HAM, bool STORED>
+__device__ __forceinline__ void seed_block(const AdjSeedArgs<T> &a, int bx, int by, int gx)
+{
+    const StageArgs<T> &st = a.st;
+    constexpr int P = seed_planes<T, D, STORED>();
     const int q = bx * kSeedThreads + threadIdx.x;
     const bool live = q < st.g.plane;
-    // per-node contributions: [0] dL/dh, [1..D] dL/dalpha_d, [D+1..D+NP] dL/dtheta
     constexpr int NP = ham_params<HAM>();
     constexpr int V = pow2_at_least(1 + D + NP);
     double part[V] = {};
 
-    int j[kMaxDim] = {0, 0, 0, 0};
-    if (live) {
-        if constexpr (D == 1) {
-            j[0] = q;
-        } else {
-            const int nl = st.g.n[D - 1];
-            int jm = (int)((double)q / (double)nl);
-            int jl = q - jm * nl;
-            if (jl < 0) {
-                --jm;
-                jl += nl;
-            } else if (jl >= nl) {
-                ++jm;
-                jl -= nl;
-            }
-            j[D - 2] = jm;
-            j[D - 1] = jl;
-        }
-        const int sy = by;
-        if constexpr (D == 3) j[0] = sy;
-        if constexpr (D == 4) {
-            j[0] = sy / st.g.n[1];
-            j[1] = sy - j[0] * st.g.n[1];
-        }
-        int idx = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) idx += j[d] * st.g.stride[d];
-
-        // Every load comes first, and nothing waits for one before the
-        // arithmetic, so that a wave waits for memory once (an operand that a
-        // uniform flag leaves out is the constant 0, never a copy of another
-        // load).  The sweep never aliases lam_out, lam_in, lam_n and
-        // lam_target.
-        T lo = ld32(a.lam_out, idx);
-        T add[kMaxDim];
-#pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) add[k] = k < a.n_add ? ld32(a.lam_add[k], idx) : T(0);
-        // (the mask byte is read unconditionally, from lam_out's first bytes
-        // when there is no mask, so that its test is not a branch on a load)
-        const unsigned char mk = ld32(a.mask ? a.mask : reinterpret_cast<const unsigned char *>(a.lam_out), idx);
-        const T in_old = a.in_mode ? ld32(a.lam_in, idx) : T(0);
-        const T n_old = a.n_mode == 2 ? ld32(a.lam_n, idx) : T(0);
-        const T tg_old = a.lam_target ? ld32(a.lam_target, idx) : T(0);
-        T pm[D], pp[D];
-        if constexpr (STORED) {  // the replay kept them
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                pm[d] = ld32(a.dp_in + (size_t)(2 * d) * (size_t)a.dp_stride, idx);
-                pp[d] = ld32(a.dp_in + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx);
-            }
-        } else {
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                T v[7];
-                if (d == D - 1) gather7_row(st.phi_in, idx, j[d], st.g.n[d], (st.g.periodic >> d) & 1u, v);
-                else gather7(st.phi_in, idx, j[d], st.g.n[d], st.g.stride[d], (st.g.periodic >> d) & 1u, v);
-                node_derivs<T, SCHEME>(v, st.inv_dx[d], st.dx[d], pm[d], pp[d]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kMaxDim; ++k)
-            if (k < a.n_add) lo += add[k];
-        // where the target was kept, its adjoint takes lam_out
-        const bool kept = a.mask != nullptr && mk != 0;
-        const T tg_new = tg_old + lo;
-        if (kept) lo = T(0);
-        T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
-#pragma unroll
-        for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (pm[d] + pp[d]);
-        T hhat = ham_grad<T, D, HAM>(st, j, pbar, dHdp, dmH);
-#pragma unroll
-        for (int d = 0; d < D; ++d) hhat = fmaT(-st.alpha[d], T(0.5) * (pp[d] - pm[d]), hhat);
-        const T L = -hhat;
-
-        const T w = a.cb * a.h * lo;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
-            at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
-            at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
-            part[1 + d] = (double)(w * T(0.5) * (pp[d] - pm[d]));
-        }
-#pragma unroll
-        for (int m = 0; m < NP; ++m) part[1 + D + m] = (double)(w * dmH[m]);
-        part[0] = (double)(a.cb * lo) * (double)L;
-
-        if (kept && a.lam_target) at32(a.lam_target, idx) = tg_new;
-        const T cin = a.cb * lo;
-        at32(a.lam_in, idx) = a.in_mode ? in_old + cin : cin;
-        if (a.n_mode) {
-            const T cn = a.ca * lo;
-            at32(a.lam_n, idx) = a.n_mode == 2 ? n_old + cn : cn;
+    int jm = 0, jl = 0;
+    if (live && D >= 2) {
+        const int nl = st.g.n[D - 1];
+        jm = (int)((double)q / (double)nl);
+        jl = q - jm * nl;
+        if (jl < 0) {
+            --jm;
+            jl += nl;
+        } else if (jl >= nl) {
+            ++jm;
+            jl -= nl;
         }
     }
-
-    // block sums, accumulated into this block's slots (a fixed order: deterministic)
+    SeedNode<T, D> nd[P];
+    bool ok[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const int sy = by * P + r;
+        ok[r] = live && sy < st.g.slow;
+        if (ok[r]) {
+            int *j = nd[r].j;
+            j[0] = j[1] = j[2] = j[3] = 0;
+            if constexpr (D == 1) {
+                j[0] = q;
+            } else {
+                j[D - 2] = jm;
+                j[D - 1] = jl;
+            }
+            if constexpr (D == 3) j[0] = sy;
+            if constexpr (D == 4) {
+                j[0] = sy / st.g.n[1];
+                j[1] = sy - j[0] * st.g.n[1];
+            }
+            int idx = 0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) idx += j[d] * st.g.stride[d];
+            nd[r].idx = idx;
+            seed_load<T, D, SCHEME, HAM, STORED>(a, nd[r]);
+        }
+    }
+    // Block sums of each plane apart, into the slot of that plane's blocks,
+    // (plane) gx + bx, in a fixed order: the same sums, to the bit, for any
+    // number of planes per block.  Whether a plane exists is uniform over
+    // the block, so every thread reaches the same barriers.
     __shared__ double red[kSeedThreads / 64][V];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int kShift = 6 - (V == 1 ? 0 : V == 2 ? 1 : V == 4 ? 2 : V == 8 ? 3 : V == 16 ? 4 : 5);
-    const double mine = wave_reduce_scatter<V>(part, lane);
-    if ((lane & ((1 << kShift) - 1)) == 0) red[wave][lane >> kShift] = mine;
-    __syncthreads();
-    if (threadIdx.x < 1 + D + NP) {
-        const int k = threadIdx.x;
-        double s = 0.0;
-        for (int w = 0; w < kSeedThreads / 64; ++w) s += red[w][k];
-        const int acc_slot = k == 0 ? a.h_slot : (k <= D ? kAccAlpha + (k - 1) : kAccTheta + (k - 1 - D));
-        a.acc[slot * kAccCount + acc_slot] += s;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const int sy = by * P + r;
+        if (sy >= st.g.slow) break;
+#pragma unroll
+        for (int k = 0; k < V; ++k) part[k] = 0.0;
+        if (ok[r]) seed_finish<T, D, HAM, V>(a, nd[r], part);
+        if (r > 0) __syncthreads();  // red of the plane before has been read
+        const double mine = wave_reduce_scatter<V>(part, lane);
+        if ((lane & ((1 << kShift) - 1)) == 0) red[wave][lane >> kShift] = mine;
+        __syncthreads();
+        if (threadIdx.x < 1 + D + NP) {
+            const int k = threadIdx.x;
+            double s = 0.0;
+            for (int w = 0; w < kSeedThreads / 64; ++w) s += red[w][k];
+            const int acc_slot = k == 0 ? a.h_slot : (k <= D ? kAccAlpha + (k - 1) : kAccTheta + (k - 1 - D));
+            a.acc[(sy * gx + bx) * kAccCount + acc_slot] += s;
+        }
     }
 }
 
 template <typename T, int D, int SCHEME, int HAM, bool STORED>
-__global__ __launch_bounds__(kSeedThreads) void adj_seed_kernel(AdjSeedArgs<T> a)
+__global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) void adj_seed_kernel(AdjSeedArgs<T> a)
 {
-    seed_block<T, D, SCHEME, HAM, STORED>(a, (int)blockIdx.x, (int)blockIdx.y,
-                                          (int)(blockIdx.y * gridDim.x + blockIdx.x));
+    seed_block<T, D, SCHEME, HAM, STORED>(a, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // The seed pass of one reversed stage and one forward stage of the replay of
 // the preceding segment, in one launch.  The two are independent: the seed
 // pass waits on memory, the forward stage on arithmetic, so blocks of both
 // kinds sharing the CUs overlap well.  Both cover the grid in blocks of 256
-// nodes of a plane: nb blocks each (gx per plane).  They are dealt in runs of
-// eight, seed blocks then stage blocks, so that each XCD (blocks go to the
-// eight XCDs in turn) takes both kinds; a block keeps its XCD's residue mod 8
-// in its own numbering, and the stage blocks are renumbered, as in the direct
-// stage kernel, so that each XCD walks a contiguous run of them.  The stage
-// keeps p-, p+ (dp_out) exactly when the seed pass reads them.
+// nodes of a plane (gx per plane): ns seed blocks of P planes each, nr stage
+// blocks of one plane.  They are dealt in groups of one run of eight seed
+// blocks and P runs of eight stage blocks, so that each XCD (blocks go to the
+// eight XCDs in turn) takes both kinds; the leftovers of each kind follow.  A
+// block keeps its XCD's residue mod 8 in its own numbering, and the stage
+// blocks are renumbered, as in the direct stage kernel, so that each XCD
+// walks a contiguous run of them.  The stage keeps p-, p+ (dp_out) exactly
+// when the seed pass reads them.
 template <typename T, int D, int SCHEME, int HAM, bool STORED>
-__global__ __launch_bounds__(kSeedThreads) void adj_seed_replay_kernel(AdjSeedArgs<T> a, StageArgs<T> r, int gx,
-                                                                       int nb)
+__global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) void adj_seed_replay_kernel(
+    AdjSeedArgs<T> a, StageArgs<T> r, int gx, int ns, int nr)
 {
+    constexpr int P = seed_planes<T, D, STORED>();
+    constexpr int G = 8 * (1 + P);
     const int lb = (int)blockIdx.x;
-    const int m = nb & ~7;  // interleaved part; the nb - m leftover blocks of each kind follow
+    const int groups = min(ns / 8, nr / (8 * P));
     bool seed;
     int idx;
-    if (lb < 2 * m) {
-        seed = ((lb >> 3) & 1) == 0;
-        idx = ((lb >> 4) << 3) | (lb & 7);
+    if (lb < groups * G) {
+        const int g = lb / G, o = lb - g * G;
+        seed = o < 8;
+        idx = seed ? g * 8 + o : (g * P + ((o - 8) >> 3)) * 8 + (o & 7);
     } else {
-        const int t = lb - 2 * m;
-        seed = t < nb - m;
-        idx = m + (seed ? t : t - (nb - m));
+        const int t = lb - groups * G, left = ns - groups * 8;
+        seed = t < left;
+        idx = seed ? groups * 8 + t : groups * 8 * P + (t - left);
     }
     if (seed) {
-        seed_block<T, D, SCHEME, HAM, STORED>(a, idx % gx, idx / gx, idx);
+        seed_block<T, D, SCHEME, HAM, STORED>(a, idx % gx, idx / gx, gx);
         return;
     }
-    if ((nb & 7) == 0) idx = (idx & 7) * (nb >> 3) + (idx >> 3);
+    if ((nr & 7) == 0) idx = (idx & 7) * (nr >> 3) + (idx >> 3);
     const int bx = idx % gx, by = idx / gx;
     const int q = bx * kSeedThreads + threadIdx.x;
     if (q >= r.g.plane) return;
@@ -281,18 +343,21 @@ hipError_t launch_seed_one(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, hip
         if ((rep->dp_out != nullptr) != (a.dp_in != nullptr) || rep->g.plane != a.st.g.plane ||
             rep->g.slow != a.st.g.slow)
             return hipErrorInvalidValue;
-        const long nb = (long)gx * a.st.g.slow;
-        if (2 * nb > 0x7fffffffL) return hipErrorInvalidConfiguration;
-        const dim3 grid((unsigned)(2 * nb));
+        const long nr = (long)gx * a.st.g.slow;
+        const int P = a.dp_in ? seed_planes<T, D, true>() : seed_planes<T, D, false>();
+        const long ns = (long)gx * ((a.st.g.slow + P - 1) / P);
+        if (ns + nr > 0x7fffffffL) return hipErrorInvalidConfiguration;
+        const dim3 grid((unsigned)(ns + nr));
         if (a.dp_in)
             hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a,
-                               *rep, gx, (int)nb);
+                               *rep, gx, (int)ns, (int)nr);
         else
             hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, false>), grid, dim3(kSeedThreads), 0, s, a,
-                               *rep, gx, (int)nb);
+                               *rep, gx, (int)ns, (int)nr);
         return hipGetLastError();
     }
-    dim3 grid(gx, a.st.g.slow);
+    const int P = a.dp_in ? seed_planes<T, D, true>() : seed_planes<T, D, false>();
+    dim3 grid(gx, (a.st.g.slow + P - 1) / P);
     if (a.dp_in)
         hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a);
     else
@@ -659,6 +724,8 @@ hipError_t launch_loss(const T *phi, int n, double eps, double vol, T *grad, dou
 
 }  // namespace
 
+// accumulator slots: one per seed block of one plane, the most any variant
+// uses (slots a variant leaves unwritten stay zero)
 int adj_seed_blocks(const GridGeom &g) { return ((g.plane + kSeedThreads - 1) / kSeedThreads) * g.slow; }
 
 hipError_t launch_adj_seed_f32(const AdjSeedArgs<float> &a, const StageArgs<float> *rep, int scheme, int ham,

@@ -12,11 +12,35 @@ namespace dev {
 template <typename T>
 __device__ __forceinline__ T vsign(T a) { return a > T(0) ? T(1) : (a < T(0) ? T(-1) : T(0)); }
 
+// The per-node table values a Hamiltonian reads (coordinates, cosine and
+// sine of the angle axis), loaded apart from its arithmetic.
+template <typename T>
+struct HamTab {
+    T x, y, c, s, v;
+};
+
+template <typename T, int D, int HAM>
+__device__ __forceinline__ HamTab<T> ham_tab(const StageArgs<T> &a, const int *j)
+{
+    HamTab<T> t{T(0), T(0), T(0), T(0), T(0)};
+    if constexpr (HAM == kHamDubins3) {
+        t.x = a.tab.coord[0][j[0]];
+        t.y = a.tab.coord[1][j[1]];
+        t.c = a.tab.cosv[2][j[2]];
+        t.s = a.tab.sinv[2][j[2]];
+    } else if constexpr (HAM == kHamDubins4) {
+        t.c = a.tab.cosv[2][j[2]];
+        t.s = a.tab.sinv[2][j[2]];
+        t.v = a.tab.coord[3][j[3]];
+    }
+    return t;
+}
+
 // H at p with its gradient in p (dHdp[d]) and the gradient of -H in the
 // Hamiltonian parameters (dmH[m]); |.| has derivative sign(.) with
-// sign(0) = 0.
+// sign(0) = 0.  tb: the node's table values (ham_tab).
 template <typename T, int D, int HAM>
-__device__ __forceinline__ T ham_grad(const StageArgs<T> &a, const int *j, const T *p, T *dHdp, T *dmH)
+__device__ __forceinline__ T ham_grad(const StageArgs<T> &a, const HamTab<T> &tb, const T *p, T *dHdp, T *dmH)
 {
 #pragma clang fp contract(off)
     if constexpr (HAM == kHamNormal) {  // H = a |p|
@@ -30,8 +54,8 @@ __device__ __forceinline__ T ham_grad(const StageArgs<T> &a, const int *j, const
         dmH[0] = -n;
         return a.hp[0] * n;
     } else if constexpr (HAM == kHamDubins3) {
-        const T x = a.tab.coord[0][j[0]], y = a.tab.coord[1][j[1]];
-        const T c = a.tab.cosv[2][j[2]], sn = a.tab.sinv[2][j[2]];
+        const T x = tb.x, y = tb.y;
+        const T c = tb.c, sn = tb.s;
         const T ve = a.hp[0], vp = a.hp[1], we = a.hp[2], wp = a.hp[3];
         const T drift = fmaT(p[0], fmaT(vp, c, -ve), p[1] * (vp * sn));
         const T arg = fmaT(p[0], y, -fmaT(p[1], x, p[2]));
@@ -45,8 +69,8 @@ __device__ __forceinline__ T ham_grad(const StageArgs<T> &a, const int *j, const
         dmH[3] = -vabs(p[2]);                  // d(-H)/dwbar_p
         return -fmaT(we, vabs(arg), fmaT(-wp, vabs(p[2]), drift));
     } else {
-        const T c = a.tab.cosv[2][j[2]], sn = a.tab.sinv[2][j[2]];
-        const T v = a.tab.coord[3][j[3]];
+        const T c = tb.c, sn = tb.s;
+        const T v = tb.v;
         dHdp[0] = -v * c;
         dHdp[1] = -v * sn;
         dHdp[2] = a.hp[0] * vsign(p[2]);
