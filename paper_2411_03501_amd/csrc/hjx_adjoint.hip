@@ -5,13 +5,15 @@
 // and p-_d, p+_d are the upwind derivative approximations (LevelSetPy,
 // arXiv 2411.03501: Sec. IV-A..IV-D, Sec. V, Sec. VI).  Its reverse takes
 // two kinds of kernel:
-//   adj_seed_kernel  one thread per node: reads p-, p+ kept by the replay (or
-//                    evaluates them again) and H at phi_in, turns lam_out
-//                    (plus the per-axis sums still pending from the stage
-//                    reversed before) into the seeds w dL/dp-_d, w dL/dp+_d
-//                    (w = cb h lam_out), writes the pass-through parts of the
-//                    adjoint and accumulates dL/dh, dL/dalpha and dL/dtheta
-//                    per block;
+//   adj_seed_kernel  one or two nodes per thread: reads p-, p+ kept by the
+//                    replay (or evaluates them again) and H at phi_in, turns
+//                    lam_out (plus the per-axis sums still pending from the
+//                    stage reversed before) into the seeds w dL/dp-_d,
+//                    w dL/dp+_d (w = cb h lam_out), writes the pass-through
+//                    parts of the adjoint and accumulates dL/dh, dL/dalpha
+//                    and dL/dtheta per block; adj_seed_replay_kernel runs the
+//                    same blocks beside those of one forward stage of the
+//                    replay of the preceding segment;
 //   adj_axes_kernel  one launch for all axes, line tiles of each axis in LDS:
 //                    every derivative interval is recomputed once, its
 //                    transpose applied to the seeds of its two nodes, and
