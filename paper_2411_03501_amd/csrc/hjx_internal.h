@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hjx_fastdiv.h"
+
 namespace hjx {
 
 constexpr int kMaxDim = 4;
@@ -126,20 +128,14 @@ struct AdjAxisArgs {
     unsigned m_tiles, m_rest1;
 };
 
-// x / d for a uniform divisor d, from m = fast_div_multiplier(d, bound):
-// m = 0 means d = 1; m = 1 means x d may reach 2^32 (plain division);
-// otherwise m = ceil(2^32 / d), exact for 0 <= x < bound with bound d <= 2^32.
+// x / d for a uniform divisor d, from m = fast_div_multiplier(d, bound)
+// (hjx_fastdiv.h): m = 0 means d = 1; m = 1 means plain division; otherwise
+// the high half of x m, exact for 0 <= x < bound.
 __device__ __forceinline__ int udiv(int x, int d, unsigned m)
 {
     if (m == 0) return x;
     if (m == 1) return x / d;
     return (int)__umulhi((unsigned)x, m);
-}
-inline unsigned fast_div_multiplier(long d, long bound)
-{
-    if (d <= 1) return 0;
-    if ((unsigned long long)bound * (unsigned long long)d > 0x100000000ull) return 1;
-    return (unsigned)((0x100000000ull + (unsigned long long)d - 1) / (unsigned long long)d);
 }
 
 // The transposes of several axes in one launch (start and gx are filled in
