@@ -127,6 +127,34 @@ __device__ __forceinline__ void gather7(const T *__restrict__ phi, int idx, int 
 // periodic axis the wrap is then done with selects for every lane instead of
 // the boundary branch that the lanes of a wave would otherwise take in turn.
 // The same loads, so the same values as gather7.
+// Gather phi at offsets -3 .. N-4 along one axis of node idx, with the ghost
+// rules of gather7 (the same value for every position both cover).
+template <typename T, int N>
+__device__ __forceinline__ void gatherN(const T *__restrict__ phi, int idx, int j, int n, int s, bool per, T (&v)[N])
+{
+    if (j >= 3 && j + (N - 4) < n) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = ld32(phi, idx + (k - 3) * s);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int jj = j + k - 3;
+        if (per) {  // -3 <= jj - j <= N - 4 with n >= N - 4, so one wrap lands in [0, n)
+            jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
+            v[k] = ld32(phi, idx + (jj - j) * s);
+        } else if (jj < 0) {
+            const T p0 = ld32(phi, idx - j * s), p1 = ld32(phi, idx + (1 - j) * s);
+            v[k] = fmaT(T(-jj), p0 - p1, p0);
+        } else if (jj >= n) {
+            const T p0 = ld32(phi, idx + (n - 1 - j) * s), p1 = ld32(phi, idx + (n - 2 - j) * s);
+            v[k] = fmaT(T(jj - n + 1), p0 - p1, p0);
+        } else {
+            v[k] = ld32(phi, idx + (k - 3) * s);
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void gather7_row(const T *__restrict__ phi, int idx, int j, int n, bool per, T (&v)[7])
 {
@@ -273,6 +301,34 @@ __device__ __forceinline__ void node_derivs(const T *v, T inv_dx, T dx, T &pm, T
     }
 }
 
+// node_derivs for two neighbouring nodes j and j+1 of one axis, from
+// v[0..7] = phi at j-3 .. j+4: the interval between them is evaluated once
+// and gives the right-biased value of the first and the left-biased value of
+// the second, with exactly the arithmetic node_derivs uses for each.
+template <typename T, int SCHEME>
+__device__ __forceinline__ void pair_derivs(const T *v, T inv_dx, T dx, T &pm1, T &pp1, T &pm2, T &pp2)
+{
+    if constexpr (SCHEME == kSchemeWeno5) {
+#pragma clang fp contract(off)
+        T u[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) u[k] = (v[k + 1] - v[k]) * inv_dx;
+        T q0, q1, q2;
+        weno5_q(u[0], u[1], u[2], u[3], u[4], q0, q1, q2);
+        pm1 = weno5_fwd(u[0], u[1], u[2], u[3], u[4], q0, q1, q2);
+        weno5_q(u[1], u[2], u[3], u[4], u[5], q0, q1, q2);
+        pp1 = weno5_rev(u[1], u[2], u[3], u[4], u[5], q0, q1, q2);
+        pm2 = weno5_fwd(u[1], u[2], u[3], u[4], u[5], q0, q1, q2);
+        weno5_q(u[2], u[3], u[4], u[5], u[6], q0, q1, q2);
+        pp2 = weno5_rev(u[2], u[3], u[4], u[5], u[6], q0, q1, q2);
+    } else {
+        T unused;
+        interval<T, SCHEME>(v, inv_dx, dx, pm1, unused);
+        interval<T, SCHEME>(v + 1, inv_dx, dx, pm2, pp1);
+        interval<T, SCHEME>(v + 2, inv_dx, dx, unused, pp2);
+    }
+}
+
 // ---------------------------------------------------------------- Hamiltonians
 
 template <typename T, int D, int HAM>
@@ -353,6 +409,60 @@ __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
     }
     *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
         stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+}
+
+// The rest of one node of the direct variant once its axis-0 derivatives
+// (pm0, pp0) and its own value are known: axes 1 .. D-1, the LF Hamiltonian,
+// the stage combination, the store.
+template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+__device__ __forceinline__ void direct_rest(const StageArgs<T> &a, const int *j, int idx, T pm0, T pp0, T center)
+{
+    T pm[D], pp[D];
+    pm[0] = pm0;
+    pp[0] = pp0;
+#pragma unroll
+    for (int d = 1; d < D; ++d) {
+        T v[7];
+        if (d == D - 1) gather7_row(a.phi_in, idx, j[d], a.g.n[d], (a.g.periodic >> d) & 1u, v);
+        else gather7(a.phi_in, idx, j[d], a.g.n[d], a.g.stride[d], (a.g.periodic >> d) & 1u, v);
+        node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
+    }
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
+            at32(a.dp_out + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx) = pp[d];
+        }
+    }
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
+        stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+}
+
+// Two nodes of the direct variant: j and its neighbour one step along axis 0
+// (j[0] + 1 < n[0]).  Along axis 0 they share one 8-point gather and the
+// interval between them; then each node finishes on its own, the first
+// before the second.  Each node gets the bits direct_node would give it.
+template <typename T, int D, int SCHEME, int HAM, bool KEEP = false>
+__device__ __forceinline__ void direct_pair(const StageArgs<T> &a, const int *j)
+{
+    static_assert(D >= 2, "pairs run along axis 0 of a grid of two or more axes");
+    int idx = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) idx += j[d] * a.g.stride[d];
+    T pm1, pp1, pm2, pp2, c1, c2;
+    {
+        T v[8];
+        gatherN<T, 8>(a.phi_in, idx, j[0], a.g.n[0], a.g.stride[0], a.g.periodic & 1u, v);
+        c1 = v[3];
+        c2 = v[4];
+        pair_derivs<T, SCHEME>(v, a.inv_dx[0], a.dx[0], pm1, pp1, pm2, pp2);
+    }
+    asm volatile("" ::: "memory");
+    direct_rest<T, D, SCHEME, HAM, KEEP>(a, j, idx, pm1, pp1, c1);
+    // the second node's memory work after the first node's store
+    asm volatile("" ::: "memory");
+    const int j2[kMaxDim] = {j[0] + 1, j[1], D > 2 ? j[2] : 0, D > 3 ? j[3] : 0};
+    direct_rest<T, D, SCHEME, HAM, KEEP>(a, j2, idx + a.g.stride[0], pm2, pp2, c2);
 }
 
 }  // namespace dev

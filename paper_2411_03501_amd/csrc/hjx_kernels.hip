@@ -237,7 +237,9 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 // caches (fastest axis along the lanes), both halves evaluated at the node.
 // Best for grids of a few million nodes, where the plane-march tiling cannot
 // keep enough waves in flight.
-template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+// PAIR (3-D only): each thread takes two neighbouring planes of axis 0
+// (direct_pair), block row by covering planes 2 by and 2 by + 1.
+template <typename T, int D, int SCHEME, int HAM, bool KEEP, bool PAIR>
 __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 {
     // XCD-aware order: the hardware deals consecutive blocks round-robin to
@@ -271,6 +273,14 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
         direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
         return;
     }
+    if constexpr (D == 3 && PAIR) {
+        for (int sp = by; 2 * sp < a.g.slow; sp += gridDim.y) {
+            j[0] = 2 * sp;
+            if (j[0] + 1 < a.g.n[0]) direct_pair<T, D, SCHEME, HAM, KEEP>(a, j);
+            else direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
+        }
+        return;
+    }
     for (int sy = by; sy < a.g.slow; sy += gridDim.y) {
         if constexpr (D == 3) j[0] = sy;
         if constexpr (D == 4) {
@@ -285,18 +295,22 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 // vector registers allow 8; the compiler's own choice, about 106 scalar
 // registers, allows 7).  The few scalar values over the cap live in vector
 // lanes: a handful of lane moves per thread, against an eighth more waves
-// to hide latency (about 2% faster at 101^3).
+// to hide latency (about 2% faster at 101^3).  One node per thread: pairs
+// need 75 vector registers (6 waves) and were 2% slower.
 template <typename T, int D, int SCHEME, int HAM, bool KEEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void stage_direct_kernel(StageArgs<T> a)
 {
-    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
+    direct_stage<T, D, SCHEME, HAM, KEEP, false>(a);
 }
 
-// FP64: the vector registers bound the occupancy (5 waves), so no cap.
+// FP64: the vector registers bound the occupancy, so no cap.  3-D grids
+// take pairs of axis-0 planes: a quarter fewer axis-0 WENO windows, and so
+// fewer quarter-rate FP64 reciprocals, outweigh 4 waves per SIMD instead of
+// 5 (29.0 -> 27.3 us per stage at 101^3).
 template <typename T, int D, int SCHEME, int HAM, bool KEEP>
 __global__ __launch_bounds__(256) void stage_direct_kernel_f64(StageArgs<T> a)
 {
-    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
+    direct_stage<T, D, SCHEME, HAM, KEEP, true>(a);
 }
 
 template <typename T, int D, int SCHEME, int HAM>
@@ -312,7 +326,9 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
     if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
-        dim3 grid((a.g.plane + 255) / 256, a.g.slow < 65535 ? a.g.slow : 65535);
+        // FP64 3-D: two planes of axis 0 per thread (the pair form above)
+        const int rows = D == 3 && !std::is_same<T, float>::value ? (a.g.slow + 1) / 2 : a.g.slow;
+        dim3 grid((a.g.plane + 255) / 256, rows < 65535 ? rows : 65535);
         if constexpr (std::is_same<T, float>::value) {
             if (a.dp_out) hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
