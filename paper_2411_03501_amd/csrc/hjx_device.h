@@ -128,7 +128,9 @@ __device__ __forceinline__ void gather7(const T *__restrict__ phi, int idx, int 
 // the boundary branch that the lanes of a wave would otherwise take in turn.
 // The same loads, so the same values as gather7.
 // Gather phi at offsets -3 .. N-4 along one axis of node idx, with the ghost
-// rules of gather7 (the same value for every position both cover).
+// rules of gather7 (the same value for every position both cover).  With
+// N > 7 the node must be at least N - 7 from the axis end (direct_pair's
+// first node, j <= n - 2, for N = 8).
 template <typename T, int N>
 __device__ __forceinline__ void gatherN(const T *__restrict__ phi, int idx, int j, int n, int s, bool per, T (&v)[N])
 {
@@ -140,7 +142,7 @@ __device__ __forceinline__ void gatherN(const T *__restrict__ phi, int idx, int 
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         int jj = j + k - 3;
-        if (per) {  // -3 <= jj - j <= N - 4 with n >= N - 4, so one wrap lands in [0, n)
+        if (per) {  // -3 <= jj - j <= N - 4 and j <= n - 1 - (N - 7), n >= 3: one wrap lands in [0, n)
             jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
             v[k] = ld32(phi, idx + (jj - j) * s);
         } else if (jj < 0) {
