@@ -63,12 +63,41 @@ def describe(w, rk_steps):
 KERNEL_SOURCES = ["paper_2411_03501_amd/csrc/hjx_device.h", "paper_2411_03501_amd/csrc/hjx_kernels.hip"]
 
 
+def strip_comments(src):
+    """C++ source without its comments and with runs of whitespace made one
+    space: what the compiler sees, as far as a kernel's code goes.  String
+    and character literals are kept as they are."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_sources_sha256():
+    """sha256 of the stage-kernel sources without comments or layout, so
+    that the counters taken for a kernel stay attached to it until its code
+    changes."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()
 
 
