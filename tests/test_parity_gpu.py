@@ -177,6 +177,27 @@ def test_smallest_grids():
         assert np.abs(got - ref).max() <= 1e-12 * max(1, np.abs(ref).max()), w.name
 
 
+@pytest.mark.parametrize("scheme", ["weno5", "eno3", "first"])
+def test_fp64_plane_pairs_on_a_periodic_slowest_axis(scheme):
+    """In 3-D the FP64 direct kernel gives each thread two planes of axis 0
+    and gathers 8 values along it, wrapping once on a periodic axis; an odd
+    n[0] leaves the last plane alone.  The spatial operator against the
+    oracle, and bit for bit against the plane-march variant (one interval
+    per pair of nodes, no plane pairs), on short periodic axes."""
+    for n0 in (3, 4, 5, 8):
+        w = _w(f"pairs{n0}", [0, -1, 0], [1, 1, 2], [n0, 9, 11], periodic=(0, 2), scheme=scheme)
+        say(f"pairs {scheme} n={w.n}")
+        phi = inputs.rough_field(w.n, 13)
+        ref = O.rhs(oracle_problem(w), phi)
+        P = gpu_problem(w, "f64")
+        d = to_dev(phi, torch.float64)
+        P.tile = (1, 256, 1, 1)
+        got = to_host(P.rhs(d))
+        assert np.abs(got - ref).max() <= 1e-12 * max(1, np.abs(ref).max()), (scheme, n0)
+        P.tile = (0, 11, 3, 2)
+        assert np.array_equal(to_host(P.rhs(d)), got), (scheme, n0)
+
+
 def test_in_place_solve_and_target_rules():
     w = CASES["dubins3"]
     phi = inputs.smooth_field(w.n, 5)
