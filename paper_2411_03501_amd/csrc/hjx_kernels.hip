@@ -237,11 +237,23 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 // caches (fastest axis along the lanes), both halves evaluated at the node.
 // Best for grids of a few million nodes, where the plane-march tiling cannot
 // keep enough waves in flight.
-// PAIR (3-D only): each thread takes two neighbouring planes of axis 0
-// (direct_pair), block row by covering planes 2 by and 2 by + 1.
-template <typename T, int D, int SCHEME, int HAM, bool KEEP, bool PAIR>
+// Whether the direct kernel gives each thread two neighbouring planes of
+// axis 0 (direct_pair) instead of one node: in 2-D and 3-D, for FP64 (fewer
+// quarter-rate reciprocals outweigh the registers) and for first order in
+// either precision (fewer loads per node; few registers anyway).  FP32 WENO
+// and ENO keep one node per thread: pairs cost them occupancy.
+template <typename T, int D, int SCHEME>
+constexpr bool direct_pairs()
+{
+    return (D == 2 || D == 3) && (sizeof(T) == 8 || SCHEME == kSchemeFirst);
+}
+
+// With pairs, 2-D: thread q takes rows 2 (q / n1) and 2 (q / n1) + 1 of
+// column q % n1; 3-D: block row by takes planes 2 by and 2 by + 1.
+template <typename T, int D, int SCHEME, int HAM, bool KEEP>
 __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 {
+    constexpr bool PAIR = direct_pairs<T, D, SCHEME>();
     // XCD-aware order: the hardware deals consecutive blocks round-robin to
     // the 8 XCDs, each with its own L2.  Renumber the blocks so that each
     // XCD takes a contiguous run of them: the rows a block's stencils reach
@@ -251,6 +263,23 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
     if ((G & 7) == 0) lb = (lb & 7) * (G >> 3) + (lb >> 3);
     const int bx = lb % (int)gridDim.x, by = lb / (int)gridDim.x;
     const int q = bx * 256 + threadIdx.x;
+    if constexpr (D == 2 && PAIR) {
+        const int n1 = a.g.n[1];
+        if (q >= ((a.g.n[0] + 1) / 2) * n1) return;
+        int pr = (int)((double)q / (double)n1);
+        int jl = q - pr * n1;
+        if (jl < 0) {
+            --pr;
+            jl += n1;
+        } else if (jl >= n1) {
+            ++pr;
+            jl -= n1;
+        }
+        int j[kMaxDim] = {2 * pr, jl, 0, 0};
+        if (j[0] + 1 < a.g.n[0]) direct_pair<T, D, SCHEME, HAM, KEEP>(a, j);
+        else direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
+        return;
+    }
     if (q >= a.g.plane) return;
     int j[kMaxDim] = {0, 0, 0, 0};
     if constexpr (D == 1) {
@@ -295,22 +324,23 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 // vector registers allow 8; the compiler's own choice, about 106 scalar
 // registers, allows 7).  The few scalar values over the cap live in vector
 // lanes: a handful of lane moves per thread, against an eighth more waves
-// to hide latency (about 2% faster at 101^3).  One node per thread: pairs
-// need 75 vector registers (6 waves) and were 2% slower.
+// to hide latency (about 2% faster at 101^3).  WENO keeps one node per
+// thread: pairs need 75 vector registers (6 waves) and were 2% slower.
 template <typename T, int D, int SCHEME, int HAM, bool KEEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void stage_direct_kernel(StageArgs<T> a)
 {
-    direct_stage<T, D, SCHEME, HAM, KEEP, false>(a);
+    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
 }
 
-// FP64: the vector registers bound the occupancy, so no cap.  3-D grids
-// take pairs of axis-0 planes: a quarter fewer axis-0 WENO windows, and so
-// fewer quarter-rate FP64 reciprocals, outweigh 4 waves per SIMD instead of
-// 5 (29.0 -> 27.3 us per stage at 101^3).
+// FP64: the vector registers bound the occupancy, so no cap.  Pairs of
+// axis-0 planes: in 3-D WENO a quarter fewer axis-0 windows, and so fewer
+// quarter-rate FP64 reciprocals, outweigh 4 waves per SIMD instead of 5
+// (29.0 -> 27.3 us per stage at 101^3); first order in 2-D reads 4 values
+// per node instead of 5 (4.4 -> 4.8 TB/s at 4096^2).
 template <typename T, int D, int SCHEME, int HAM, bool KEEP>
 __global__ __launch_bounds__(256) void stage_direct_kernel_f64(StageArgs<T> a)
 {
-    direct_stage<T, D, SCHEME, HAM, KEEP, true>(a);
+    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
 }
 
 template <typename T, int D, int SCHEME, int HAM>
@@ -326,9 +356,11 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
     if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
-        // FP64 3-D: two planes of axis 0 per thread (the pair form above)
-        const int rows = D == 3 && !std::is_same<T, float>::value ? (a.g.slow + 1) / 2 : a.g.slow;
-        dim3 grid((a.g.plane + 255) / 256, rows < 65535 ? rows : 65535);
+        // with pairs: half the planes (3-D) or half the rows (2-D)
+        constexpr bool pairs = direct_pairs<T, D, SCHEME>();
+        const int rows = D == 3 && pairs ? (a.g.slow + 1) / 2 : a.g.slow;
+        const long cols = D == 2 && pairs ? (long)((a.g.n[0] + 1) / 2) * a.g.n[1] : (long)a.g.plane;
+        dim3 grid((unsigned)((cols + 255) / 256), rows < 65535 ? rows : 65535);
         if constexpr (std::is_same<T, float>::value) {
             if (a.dp_out) hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
