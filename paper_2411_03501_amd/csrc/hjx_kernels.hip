@@ -13,6 +13,7 @@
 // the tiling.
 #include "hjx_device.h"
 
+#include <cstdint>
 #include <type_traits>
 
 namespace hjx {
@@ -343,6 +344,84 @@ __global__ __launch_bounds__(256) void stage_direct_kernel_f64(StageArgs<T> a)
     direct_stage<T, D, SCHEME, HAM, KEEP>(a);
 }
 
+// First order in 2-D, two x-neighbours per thread, for an even row length
+// and arrays aligned to two elements: the two nodes' own values and those of
+// the rows above and below come in as one vector access each, the two x
+// halo values as scalars (5 loads for 2 nodes), and the results leave as one
+// vector store.  Each node is assembled into the stencils direct_node would
+// gather and goes through the same node_derivs and stage_result, so the
+// bits are direct_node's; threads with a node on the grid's edge take
+// direct_node itself.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
+template <typename T, int HAM, bool KEEP>
+__global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
+{
+    using T2 = typename Vec2<T>::type;
+    const int ny = a.g.n[0], nx = a.g.n[1], hx = nx >> 1;
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (long)ny * hx) return;
+    const int y = (int)(q / hx), x0 = 2 * (int)(q - (long)y * hx);
+    int j[kMaxDim] = {y, x0, 0, 0};
+    if (y < 1 || y > ny - 2 || x0 < 1 || x0 + 2 > nx - 1) {
+        direct_node<T, 2, kSchemeFirst, HAM, KEEP>(a, j);
+        j[1] = x0 + 1;
+        direct_node<T, 2, kSchemeFirst, HAM, KEEP>(a, j);
+        return;
+    }
+    const int idx = y * nx + x0;
+    const T2 c = *reinterpret_cast<const T2 *>(a.phi_in + idx);
+    const T2 up = *reinterpret_cast<const T2 *>(a.phi_in + (idx - nx));
+    const T2 dn = *reinterpret_cast<const T2 *>(a.phi_in + (idx + nx));
+    const T xl = ld32(a.phi_in, idx - 1), xr = ld32(a.phi_in, idx + 2);
+    // the stencils gather7 would give (first order reads positions 2..4)
+    T v0[7] = {T(0), T(0), up.x, c.x, dn.x, T(0), T(0)}, v1[7] = {T(0), T(0), xl, c.x, c.y, T(0), T(0)};
+    T w0[7] = {T(0), T(0), up.y, c.y, dn.y, T(0), T(0)}, w1[7] = {T(0), T(0), c.x, c.y, xr, T(0), T(0)};
+    T pm[2], pp[2], pm2[2], pp2[2];
+    node_derivs<T, kSchemeFirst>(v0, a.inv_dx[0], a.dx[0], pm[0], pp[0]);
+    node_derivs<T, kSchemeFirst>(v1, a.inv_dx[1], a.dx[1], pm[1], pp[1]);
+    node_derivs<T, kSchemeFirst>(w0, a.inv_dx[0], a.dx[0], pm2[0], pp2[0]);
+    node_derivs<T, kSchemeFirst>(w1, a.inv_dx[1], a.dx[1], pm2[1], pp2[1]);
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
+            at32(a.dp_out + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx) = pp[d];
+            at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx + 1) = pm2[d];
+            at32(a.dp_out + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx + 1) = pp2[d];
+        }
+    }
+    const T r0 = stage_result<T, 2, HAM>(a, j, pm, pp, c.x, idx);
+    j[1] = x0 + 1;
+    const T r1 = stage_result<T, 2, HAM>(a, j, pm2, pp2, c.y, idx + 1);
+    T2 r;
+    r.x = r0;
+    r.y = r1;
+    *reinterpret_cast<T2 *>(a.out + idx) = r;
+}
+
+// whether stage_x2_kernel applies: 2-D first order, an even row length, and
+// every array the stage reads or writes aligned to two elements
+template <typename T, int D, int SCHEME>
+bool x2_applies(const StageArgs<T> &a)
+{
+    if constexpr (D != 2 || SCHEME != kSchemeFirst) {
+        return false;
+    } else {
+        auto al = [](const void *p) { return p == nullptr || ((uintptr_t)p % (2 * sizeof(T))) == 0; };
+        return (a.g.n[1] % 2) == 0 && al(a.phi_in) && al(a.out) && (a.ca == T(0) || al(a.phi_n)) && al(a.target);
+    }
+}
+
 template <typename T, int D, int SCHEME, int HAM>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
@@ -356,6 +435,13 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
     if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
+        if (x2_applies<T, D, SCHEME>(a)) {
+            const long threads = (long)a.g.n[0] * (a.g.n[1] / 2);
+            const dim3 grid((unsigned)((threads + 255) / 256));
+            if (a.dp_out) hipLaunchKernelGGL((stage_x2_kernel<T, HAM, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((stage_x2_kernel<T, HAM, false>), grid, dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
         // with pairs: half the planes (3-D) or half the rows (2-D)
         constexpr bool pairs = direct_pairs<T, D, SCHEME>();
         const int rows = D == 3 && pairs ? (a.g.slow + 1) / 2 : a.g.slow;

@@ -198,6 +198,35 @@ def test_fp64_plane_pairs_on_a_periodic_slowest_axis(scheme):
         assert np.array_equal(to_host(P.rhs(d)), got), (scheme, n0)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_first_order_rows_in_vector_pairs(dtype):
+    """2-D first order with an even row length takes two x-neighbours per
+    thread through vector accesses, and edge threads take the one-node path:
+    rows of 4 to 64 nodes, periodic or not, RK1 and RK3, with a target,
+    against the oracle and bit for bit against the plane-march variant."""
+    shapes = [((5, 6), ()), ((4, 4), (0, 1)), ((33, 64), ()), ((17, 64), (1,)), ((64, 30), (0,))]
+    for n, per in shapes:
+        for rk in (1, 3):
+            w = _w(f"x2_{n[0]}x{n[1]}", [-1, -1], [1, 1], list(n), periodic=per, scheme="first", rk=rk)
+            say(f"x2 {dtype} n={n} periodic={per} rk{rk}")
+            phi = inputs.smooth_field(w.n, 21) - 0.3
+            P = gpu_problem(w, dtype)
+            d = to_dev(phi, TDT[dtype])
+            P.tile = (1, 256, 1, 1)
+            ref = O.rhs(oracle_problem(w), phi)
+            got = to_host(P.rhs(d))
+            tol = 1e-12 if dtype == "f64" else 1e-5
+            assert np.abs(got - ref).max() <= tol * max(1, np.abs(ref).max()), (n, per, rk)
+            out, st = P.solve(d, 0.05, target=d)
+            ref_s, steps, _ = O.solve(oracle_problem(w), phi, 0.05, target=phi)
+            assert st["steps"] == steps
+            assert_close(to_host(out), ref_s, dtype, w.periodic, what=f"x2 solve {n}")
+            P.tile = (0, n[1], 1, 1)
+            out2, _ = P.solve(d, 0.05, target=d)
+            assert torch.equal(out, out2), (n, per, rk)
+            assert np.array_equal(to_host(P.rhs(d)), got), (n, per, rk)
+
+
 def test_in_place_solve_and_target_rules():
     w = CASES["dubins3"]
     phi = inputs.smooth_field(w.n, 5)
