@@ -19,6 +19,8 @@ _LIB_PATH = os.path.join(_HERE, "libhjxo.so")
 MAXD = 4
 SCHEME = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2}
+# restricted update (see restricted_rate in hjxo.c)
+RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 
 
 class Problem(ctypes.Structure):
@@ -33,11 +35,12 @@ class Problem(ctypes.Structure):
         ("scheme", ctypes.c_int),
         ("rk", ctypes.c_int),
         ("cfl", ctypes.c_double),
+        ("restrict_update", ctypes.c_int),
     ]
 
 
 def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
-                 cfl=0.75):
+                 cfl=0.75, restrict="none"):
     """Build an oracle problem.  `periodic` lists periodic axes."""
     P = Problem()
     P.dim = len(n)
@@ -52,6 +55,7 @@ def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme
     P.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     P.rk = int(rk)
     P.cfl = float(cfl)
+    P.restrict_update = RESTRICT[restrict] if isinstance(restrict, str) else int(restrict)
     return P
 
 

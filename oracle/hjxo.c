@@ -38,6 +38,15 @@
  *   CFL time step ................ Sec. IV-D (lambda max|f'| <= 1) and Sec. V
  *   TVD-RK 1/2/3 ................. Sec. V (odeCFL1/2/3 averaging steps)
  *   min-with-target .............. Sec. VI, variational HJ PDE (tube form)
+ *   restricted update ............ Sec. VI: the variational form with
+ *                                  min[0, H], and the 'positive' field of
+ *                                  the rockets listing (Listing 4).  Read
+ *                                  as a clip of the rate of every Euler
+ *                                  move: L <- min(L, 0) (phi may only fall
+ *                                  in tau, the zero sublevel set only
+ *                                  grows) or L <- max(L, 0) (phi may only
+ *                                  rise).  The paper does not define the
+ *                                  flag; this is the reading.
  *
  * Conventions: time-to-go tau >= 0, phi_tau + H(x, grad phi) = 0,
  * phi(., 0) = phi0; the right-hand side is L(phi) = -Hhat.
@@ -73,6 +82,7 @@ typedef double real;
 
 enum { SCHEME_FIRST = 1, SCHEME_ENO2 = 2, SCHEME_ENO3 = 3, SCHEME_WENO5 = 5 };
 enum { HAM_NORMAL = 0, HAM_DUBINS3_PE = 1, HAM_DUBINS4 = 2 };
+enum { RESTRICT_NONE = 0, RESTRICT_NONPOSITIVE = 1, RESTRICT_POSITIVE = 2 };
 
 /* Problem description, laid out for ctypes. */
 typedef struct {
@@ -85,6 +95,7 @@ typedef struct {
     int scheme;     /* 1, 2, 3 or 5 */
     int rk;         /* 1, 2 or 3 */
     double cfl;
+    int restrict_update; /* RESTRICT_NONE, RESTRICT_NONPOSITIVE or RESTRICT_POSITIVE */
 } hjxo_problem;
 
 /* ------------------------------------------------------------------ */
@@ -453,13 +464,24 @@ static void ws_free(workspace *w)
     }
 }
 
-/* one Euler move: out = in + dt * L(in) */
+/* The rate of an Euler move under the restricted update (Sec. VI):
+ * min[0, .] of the variational form keeps only rates that lower phi; the
+ * 'positive' flag keeps only rates that raise it.  A clipped rate is an
+ * exact zero (value and complex-step tangent). */
+static real restricted_rate(const hjxo_problem *P, real L)
+{
+    if (P->restrict_update == RESTRICT_NONPOSITIVE && RE(L) > 0) return (real)0.0;
+    if (P->restrict_update == RESTRICT_POSITIVE && RE(L) < 0) return (real)0.0;
+    return L;
+}
+
+/* one Euler move: out = in + dt * L(in), L restricted as above */
 static void euler(const hjxo_problem *P, const real *hp, const real *in, const real alpha[MAXD],
                   real dt, real *out, workspace *w)
 {
     long total = npoints(P);
     lf_rhs(P, hp, in, alpha, w->L, w->pm, w->pp);
-    for (long f = 0; f < total; ++f) out[f] = in[f] + dt * w->L[f];
+    for (long f = 0; f < total; ++f) out[f] = in[f] + dt * restricted_rate(P, w->L[f]);
 }
 
 /* advance phi by one step of size dt (in place) */
@@ -525,6 +547,7 @@ static int check_problem(const hjxo_problem *P)
         P->scheme != SCHEME_WENO5)
         return -1;
     if (P->rk < 1 || P->rk > 3) return -1;
+    if (P->restrict_update < RESTRICT_NONE || P->restrict_update > RESTRICT_POSITIVE) return -1;
     if (P->ham_kind == HAM_DUBINS3_PE && P->dim != 3) return -1;
     if (P->ham_kind == HAM_DUBINS4 && P->dim != 4) return -1;
     if (P->ham_kind < 0 || P->ham_kind > 2) return -1;

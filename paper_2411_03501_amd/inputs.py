@@ -49,6 +49,7 @@ class Workload:
     dtype: str = "f64"
     steps: int = 0                # batch instances: number of full steps
     extra: dict = field(default_factory=dict)
+    restrict: str = "none"        # restricted update: none | nonpositive | positive
 
     @property
     def dim(self):
