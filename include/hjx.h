@@ -71,6 +71,21 @@ typedef enum {
 /* TVD Runge-Kutta order, Sec. V (odeCFL1, odeCFL2, odeCFL3). */
 typedef enum { HJX_RK1 = 1, HJX_RK2 = 2, HJX_RK3 = 3 } hjx_rk;
 
+/* Restricted update (Sec. VI: the variational HJ PDE with min[0, H], and
+ * the 'positive' field of the rockets listing, Listing 4, which the paper
+ * does not define).  The rate L of every RK stage is clipped before the
+ * stage combination:
+ *   HJX_RESTRICT_NONE         L unchanged;
+ *   HJX_RESTRICT_NONPOSITIVE  L <- min(L, 0): phi never rises in time to go,
+ *                             so {phi <= 0} only grows (the tube form);
+ *   HJX_RESTRICT_POSITIVE     L <- max(L, 0): phi never falls.
+ * hjx_rhs always returns the unclipped L; the CFL step is unchanged. */
+typedef enum {
+    HJX_RESTRICT_NONE = 0,
+    HJX_RESTRICT_NONPOSITIVE = 1,
+    HJX_RESTRICT_POSITIVE = 2
+} hjx_restrict;
+
 /* Built-in Hamiltonians (device code cannot call back into Python, so the
  * 'hamFunc'/'partialFunc' pair of Listing 4 is a kind plus parameters).
  *   HJX_HAM_NORMAL      any dim, p = {a}: H = a |p|, alpha_d = |a|.
@@ -116,7 +131,7 @@ typedef struct {
     int32_t rk;    /* hjx_rk */
     double cfl;    /* 0 < cfl <= 1 */
     int32_t dtype; /* hjx_dtype */
-    int32_t reserved;
+    int32_t restrict_update; /* hjx_restrict */
 } hjx_scheme_desc;
 
 typedef struct {
@@ -233,7 +248,8 @@ typedef struct hjx_tape hjx_tape;
  * `stream`) and allocates the checkpoints and the replay workspace: about
  * (steps/ckpt_every + 6 ckpt_every + 4 + 3 dim) arrays of the problem's size, plus
  * the derivative store of hjx_tape_set_mode.
- * Arrays must be under 4 GiB each (else HJX_ERR_UNSUPPORTED). */
+ * Arrays must be under 4 GiB each, and the scheme's restrict_update must be
+ * HJX_RESTRICT_NONE (else HJX_ERR_UNSUPPORTED). */
 hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream,
                            hjx_tape **out);
 hjx_status hjx_tape_destroy(hjx_tape *tape);

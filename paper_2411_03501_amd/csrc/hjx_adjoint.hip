@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) 
         j[0] = by / r.g.n[1];
         j[1] = by - j[0] * r.g.n[1];
     }
-    direct_node<T, D, SCHEME, HAM, STORED>(r, j);
+    direct_node<T, D, SCHEME, HAM, STORED ? kNodeKeep : kNodePlain>(r, j);
 }
 
 template <typename T, int D, int SCHEME, int HAM>

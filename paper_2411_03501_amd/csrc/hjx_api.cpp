@@ -202,6 +202,8 @@ hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_sch
     if (s->rk < 1 || s->rk > 3) return fail(HJX_ERR_INVALID_ARG, "rk order %d outside [1, 3]", s->rk);
     if (!(s->cfl > 0.0) || !(s->cfl <= 1.0)) return fail(HJX_ERR_INVALID_ARG, "cfl %g outside (0, 1]", s->cfl);
     if (s->dtype != HJX_F32 && s->dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", s->dtype);
+    if (s->restrict_update < HJX_RESTRICT_NONE || s->restrict_update > HJX_RESTRICT_POSITIVE)
+        return fail(HJX_ERR_INVALID_ARG, "unknown restrict_update %d", s->restrict_update);
     return HJX_OK;
 }
 
@@ -257,6 +259,9 @@ StageArgs<T> stage_args(const hjx_problem *p, const double *alpha)
         a.alpha[d] = d < p->grid.dim ? T(alpha[d]) : T(0);
     }
     for (int k = 0; k < 8; ++k) a.hp[k] = T(p->ham.p[k]);
+    a.clip = p->scheme.restrict_update == HJX_RESTRICT_NONPOSITIVE ? -1
+             : p->scheme.restrict_update == HJX_RESTRICT_POSITIVE  ? 1
+                                                                   : 0;
     return a;
 }
 
@@ -858,6 +863,8 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
         return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
     if (ckpt_every < 1) return fail(HJX_ERR_INVALID_ARG, "ckpt_every %d < 1", ckpt_every);
     if (!direct_ok(geometry(p), p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the adjoint needs arrays under 4 GiB");
+    if (p->scheme.restrict_update != HJX_RESTRICT_NONE)
+        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of a restricted update is not implemented");
     hjx_tape *t = new (std::nothrow) hjx_tape;
     if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
     t->p = p;
@@ -1338,6 +1345,7 @@ struct hjx_batch {
     int n = 0;
     int device = 0;
     int dtype = 0, deriv = 0, rk = 0;
+    int clip = 0;                     // some member has a restricted update
     size_t elem = 0, inst_bytes = 0;
     std::vector<hjx_problem *> probs;
     std::vector<double> alpha;        // n * kMaxDim
@@ -1393,11 +1401,11 @@ hipError_t batch_launch(const hjx_batch *b, int n_active, int s, int stage, hipS
     const int items = b->item0[n_active];
     if (b->dtype == HJX_F32) {
         BatchArgs<float> a{static_cast<const BatchInst<float> *>(b->dinst), b->dflag, n_active, items, s, stage,
-                           b->rk, b->item_nodes};
+                           b->rk, b->item_nodes, b->clip};
         return launch_batch_f32(a, b->deriv, b->blocks, st);
     }
     BatchArgs<double> a{static_cast<const BatchInst<double> *>(b->dinst), b->dflag, n_active, items, s, stage,
-                        b->rk, b->item_nodes};
+                        b->rk, b->item_nodes, b->clip};
     return launch_batch_f64(a, b->deriv, b->blocks, st);
 }
 
@@ -1545,6 +1553,7 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
     b->dtype = p0->scheme.dtype;
     b->deriv = p0->scheme.deriv;
     b->rk = p0->scheme.rk;
+    for (int i = 0; i < n; ++i) b->clip |= problems[i]->scheme.restrict_update != HJX_RESTRICT_NONE;
     b->elem = p0->elem;
     b->inst_bytes = b->dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
     b->probs.assign(problems, problems + n);
@@ -1573,7 +1582,7 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
         return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "batch allocation: %s",
                     hipGetErrorString(e));
     }
-    const int per_cu = batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv);
+    const int per_cu = batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv, b->clip);
     b->blocks_max = std::max(1, cus) * per_cu;
     b->blocks = b->blocks_max;
     *out = b;
@@ -1663,7 +1672,8 @@ hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *con
     if (!b) return fail(HJX_ERR_INVALID_ARG, "NULL batch");
     if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int cus = std::max(1, b->blocks_max / std::max(1, batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv)));
+    const int cus =
+        std::max(1, b->blocks_max / std::max(1, batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv, b->clip)));
     std::vector<std::pair<int, int>> cand;
     for (int items : {256, 1024, 4096}) {
         for (int per_cu : {1, 2, 4}) {

@@ -61,7 +61,7 @@ __device__ __forceinline__ StageArgs<T> batch_stage(const BatchInst<T> &I, int s
 
 // Nodes [f0, f1) of one instance; flat index -> grid index by multiplying
 // with a rounded reciprocal of n and correcting by one either way.
-template <typename T, int D, int SCHEME, int HAM>
+template <typename T, int D, int SCHEME, int HAM, int MODE>
 __device__ __forceinline__ void batch_run(const StageArgs<T> &a, int f0, int f1)
 {
     double rn[kMaxDim];
@@ -86,13 +86,16 @@ __device__ __forceinline__ void batch_run(const StageArgs<T> &a, int f0, int f1)
             rem = q;
         }
         j[0] = rem;
-        direct_node<T, D, SCHEME, HAM>(a, j);
+        direct_node<T, D, SCHEME, HAM, MODE>(a, j);
     }
 }
 
-template <typename T, int SCHEME>
+// CLIP: some instance has a restricted update (each applies its own a.clip,
+// which may be 0); batches without one never compile the clip.
+template <typename T, int SCHEME, bool CLIP>
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst<T> *__restrict__ inst, BatchArgs<T> b)
 {
+    constexpr int M = CLIP ? kNodeClip : kNodePlain;
     // XCD-aware order: the hardware deals consecutive blocks round-robin to
     // the 8 XCDs; renumber so that each XCD walks a contiguous run of items
     // (neighbouring nodes of an instance share halo lines in that XCD's L2).
@@ -126,38 +129,60 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst<T>
         }
         const StageArgs<T> a = batch_stage(I, b.s, b.stage, b.rk);
         if (I.ham == kHamDubins3) {
-            batch_run<T, 3, SCHEME, kHamDubins3>(a, f0, f1);
+            batch_run<T, 3, SCHEME, kHamDubins3, M>(a, f0, f1);
         } else if (I.ham == kHamDubins4) {
-            batch_run<T, 4, SCHEME, kHamDubins4>(a, f0, f1);
+            batch_run<T, 4, SCHEME, kHamDubins4, M>(a, f0, f1);
         } else {
             switch (a.g.dim) {
-            case 1: batch_run<T, 1, SCHEME, kHamNormal>(a, f0, f1); break;
-            case 2: batch_run<T, 2, SCHEME, kHamNormal>(a, f0, f1); break;
-            case 3: batch_run<T, 3, SCHEME, kHamNormal>(a, f0, f1); break;
-            default: batch_run<T, 4, SCHEME, kHamNormal>(a, f0, f1); break;
+            case 1: batch_run<T, 1, SCHEME, kHamNormal, M>(a, f0, f1); break;
+            case 2: batch_run<T, 2, SCHEME, kHamNormal, M>(a, f0, f1); break;
+            case 3: batch_run<T, 3, SCHEME, kHamNormal, M>(a, f0, f1); break;
+            default: batch_run<T, 4, SCHEME, kHamNormal, M>(a, f0, f1); break;
             }
         }
     }
 }
 
-template <typename T, int SCHEME>
+template <typename T, int SCHEME, bool CLIP>
 int occupancy()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, SCHEME>, kBatchThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, SCHEME, CLIP>, kBatchThreads, 0) !=
+        hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename T>
+template <typename T, bool CLIP>
 int occupancy_t(int scheme)
 {
     switch (scheme) {
-    case kSchemeFirst: return occupancy<T, kSchemeFirst>();
-    case kSchemeEno2: return occupancy<T, kSchemeEno2>();
-    case kSchemeEno3: return occupancy<T, kSchemeEno3>();
-    default: return occupancy<T, kSchemeWeno5>();
+    case kSchemeFirst: return occupancy<T, kSchemeFirst, CLIP>();
+    case kSchemeEno2: return occupancy<T, kSchemeEno2, CLIP>();
+    case kSchemeEno3: return occupancy<T, kSchemeEno3, CLIP>();
+    default: return occupancy<T, kSchemeWeno5, CLIP>();
     }
+}
+
+template <typename T, bool CLIP>
+hipError_t launch_batch_t(const BatchArgs<T> &a, int scheme, dim3 grid, hipStream_t s)
+{
+    switch (scheme) {
+    case kSchemeFirst:
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeFirst, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        break;
+    case kSchemeEno2:
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno2, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        break;
+    case kSchemeEno3:
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno3, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        break;
+    case kSchemeWeno5:
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeWeno5, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -165,22 +190,7 @@ hipError_t launch_batch(const BatchArgs<T> &a, int scheme, int blocks, hipStream
 {
     if (a.items <= 0) return hipSuccess;
     const dim3 grid(blocks < a.items ? blocks : a.items);
-    switch (scheme) {
-    case kSchemeFirst:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeFirst>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
-        break;
-    case kSchemeEno2:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno2>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
-        break;
-    case kSchemeEno3:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno3>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
-        break;
-    case kSchemeWeno5:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeWeno5>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return a.clip ? launch_batch_t<T, true>(a, scheme, grid, s) : launch_batch_t<T, false>(a, scheme, grid, s);
 }
 
 }  // namespace
@@ -193,9 +203,10 @@ hipError_t launch_batch_f64(const BatchArgs<double> &a, int scheme, int blocks, 
 {
     return launch_batch<double>(a, scheme, blocks, s);
 }
-int batch_blocks_per_cu(int dtype_f64, int scheme)
+int batch_blocks_per_cu(int dtype_f64, int scheme, int clip)
 {
-    return dtype_f64 ? occupancy_t<double>(scheme) : occupancy_t<float>(scheme);
+    if (clip) return dtype_f64 ? occupancy_t<double, true>(scheme) : occupancy_t<float, true>(scheme);
+    return dtype_f64 ? occupancy_t<double, false>(scheme) : occupancy_t<float, false>(scheme);
 }
 
 }  // namespace hjx

@@ -358,10 +358,18 @@ __device__ __forceinline__ T ham_value(const StageArgs<T> &a, const int *j, cons
     }
 }
 
+// What a stage node does besides its stage value: nothing (plain), keep
+// p-, p+ in a.dp_out (the replay of the adjoint), or clip the rate by
+// a.clip (a restricted update; a.clip may be 0 where one kernel serves
+// clipped and unclipped problems).  Unclipped solves never compile the clip.
+enum : int { kNodePlain = 0, kNodeKeep = 1, kNodeClip = 2 };
+
 // LF Hamiltonian (Sec. IV-D) and the stage combination (Sec. V, Sec. VI):
 // L = -(H(x, pbar) - sum_d alpha_d (p+_d - p-_d)/2); the result is L itself
-// (rhs_only) or ca phi_n + cb (phi + dt L), then min with the target.
-template <typename T, int D, int HAM>
+// (rhs_only) or ca phi_n + cb (phi + dt L), then min with the target.  With
+// CLIP, a restricted update (Sec. VI): L is first clipped to min(L, 0)
+// (a.clip < 0) or max(L, 0) (a.clip > 0).
+template <typename T, int D, int HAM, bool CLIP = false>
 __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, const T *pm, const T *pp, T center,
                                           int idx)
 {
@@ -372,8 +380,12 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
     T hhat = ham_value<T, D, HAM>(a, j, pbar);
 #pragma unroll
     for (int d = 0; d < D; ++d) hhat = fmaT(-a.alpha[d], T(0.5) * (pp[d] - pm[d]), hhat);
-    const T L = -hhat;
+    T L = -hhat;
     if (a.rhs_only) return L;
+    if constexpr (CLIP) {
+        if (a.clip < 0) L = L > T(0) ? T(0) : L;
+        if (a.clip > 0) L = L < T(0) ? T(0) : L;
+    }
     T res = a.cb * fmaT(a.dt, L, center);
     if (a.ca != T(0)) res = fmaT(a.ca, ld32(a.phi_n, idx), res);
     if (a.target) {
@@ -386,8 +398,8 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
 
 // One node of the direct variant: gather every axis through the caches,
 // both derivative halves at the node, LF Hamiltonian, stage combination.
-// KEEP: also write p-, p+ to a.dp_out (the replay of the adjoint).
-template <typename T, int D, int SCHEME, int HAM, bool KEEP = false>
+// MODE: kNodePlain, kNodeKeep or kNodeClip (above).
+template <typename T, int D, int SCHEME, int HAM, int MODE = kNodePlain>
 __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
 {
     int idx = 0;
@@ -402,7 +414,7 @@ __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
         center = v[3];
         node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
     }
-    if constexpr (KEEP) {
+    if constexpr (MODE == kNodeKeep) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
@@ -410,13 +422,13 @@ __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
         }
     }
     *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
-        stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+        stage_result<T, D, HAM, MODE == kNodeClip>(a, j, pm, pp, center, idx);
 }
 
 // The rest of one node of the direct variant once its axis-0 derivatives
 // (pm0, pp0) and its own value are known: axes 1 .. D-1, the LF Hamiltonian,
 // the stage combination, the store.
-template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+template <typename T, int D, int SCHEME, int HAM, int MODE>
 __device__ __forceinline__ void direct_rest(const StageArgs<T> &a, const int *j, int idx, T pm0, T pp0, T center)
 {
     T pm[D], pp[D];
@@ -429,7 +441,7 @@ __device__ __forceinline__ void direct_rest(const StageArgs<T> &a, const int *j,
         else gather7(a.phi_in, idx, j[d], a.g.n[d], a.g.stride[d], (a.g.periodic >> d) & 1u, v);
         node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
     }
-    if constexpr (KEEP) {
+    if constexpr (MODE == kNodeKeep) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
@@ -437,14 +449,14 @@ __device__ __forceinline__ void direct_rest(const StageArgs<T> &a, const int *j,
         }
     }
     *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
-        stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+        stage_result<T, D, HAM, MODE == kNodeClip>(a, j, pm, pp, center, idx);
 }
 
 // Two nodes of the direct variant: j and its neighbour one step along axis 0
 // (j[0] + 1 < n[0]).  Along axis 0 they share one 8-point gather and the
 // interval between them; then each node finishes on its own, the first
 // before the second.  Each node gets the bits direct_node would give it.
-template <typename T, int D, int SCHEME, int HAM, bool KEEP = false>
+template <typename T, int D, int SCHEME, int HAM, int MODE = kNodePlain>
 __device__ __forceinline__ void direct_pair(const StageArgs<T> &a, const int *j)
 {
     static_assert(D >= 2, "pairs run along axis 0 of a grid of two or more axes");
@@ -460,11 +472,11 @@ __device__ __forceinline__ void direct_pair(const StageArgs<T> &a, const int *j)
         pair_derivs<T, SCHEME>(v, a.inv_dx[0], a.dx[0], pm1, pp1, pm2, pp2);
     }
     asm volatile("" ::: "memory");
-    direct_rest<T, D, SCHEME, HAM, KEEP>(a, j, idx, pm1, pp1, c1);
+    direct_rest<T, D, SCHEME, HAM, MODE>(a, j, idx, pm1, pp1, c1);
     // the second node's memory work after the first node's store
     asm volatile("" ::: "memory");
     const int j2[kMaxDim] = {j[0] + 1, j[1], D > 2 ? j[2] : 0, D > 3 ? j[3] : 0};
-    direct_rest<T, D, SCHEME, HAM, KEEP>(a, j2, idx + a.g.stride[0], pm2, pp2, c2);
+    direct_rest<T, D, SCHEME, HAM, MODE>(a, j2, idx + a.g.stride[0], pm2, pp2, c2);
 }
 
 }  // namespace dev

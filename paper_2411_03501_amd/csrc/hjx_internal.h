@@ -47,7 +47,7 @@ enum : int { kVariantPlaneMarch = 0, kVariantDirect = 1 };
 
 // One fused stage: out = ca * phi_n + cb * (phi_in + dt * L(phi_in)),
 // then out = min(out, target) if target != nullptr; with rhs_only the
-// kernel writes L(phi_in) itself.
+// kernel writes L(phi_in) itself.  L is clipped first when clip != 0.
 template <typename T>
 struct StageArgs {
     const T *phi_in;
@@ -62,6 +62,7 @@ struct StageArgs {
     T hp[8];
     T dt, ca, cb;
     int rhs_only;
+    int clip;  // restricted update: 0 none, -1 L <- min(L, 0), +1 L <- max(L, 0) (not with rhs_only)
     Tile tile;
     unsigned char *mask;  // nullable: 1 where the target was the smaller (replay for the adjoint)
     T *dp_out;            // nullable: p-_d at dp_out + 2d dp_stride, p+_d at dp_out + (2d+1) dp_stride
@@ -189,12 +190,14 @@ struct BatchArgs {
     const BatchInst<T> *inst;
     int *flags;
     int n_active, items, s, stage, rk, item_nodes;
+    int clip;  // some instance has a restricted update
 };
 
 hipError_t launch_batch_f32(const BatchArgs<float> &a, int scheme, int blocks, hipStream_t s);
 hipError_t launch_batch_f64(const BatchArgs<double> &a, int scheme, int blocks, hipStream_t s);
-// resident blocks of the batch kernel on one CU (occupancy)
-int batch_blocks_per_cu(int dtype_f64, int scheme);
+// resident blocks of the batch kernel on one CU (occupancy); clip: the
+// kernel for batches with a restricted update
+int batch_blocks_per_cu(int dtype_f64, int scheme, int clip);
 
 // The seed pass; with rep (nullable) one forward stage of the replay (same
 // grid; p-, p+ kept exactly when a.dp_in is set) runs in the same launch.

@@ -41,9 +41,10 @@ using namespace dev;
 //   5. Hamiltonian, LF dissipation, RK combination, min with target, store.
 // Each interval is evaluated by exactly the same arithmetic whichever thread
 // or tile evaluates it, so results do not depend on the launch shape.
+// CLIP: a restricted update (the rate clipped by a.clip before step 5).
 
 
-template <typename T, int D, int SCHEME, int HAM>
+template <typename T, int D, int SCHEME, int HAM, bool CLIP>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 {
     constexpr int AF = D - 1;  // fastest axis: along the lanes
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
                 node_derivs<T, SCHEME>(v, a.inv_dx[0], a.dx[0], pm[0], pp[0]);
             }
             // 5. LF Hamiltonian and the stage combination
-            a.out[idx] = stage_result<T, D, HAM>(a, j, pm, pp, center, idx);
+            a.out[idx] = stage_result<T, D, HAM, CLIP>(a, j, pm, pp, center, idx);
         }
 
         if constexpr (D >= 3) {  // advance the marched queue
@@ -251,7 +252,7 @@ constexpr bool direct_pairs()
 
 // With pairs, 2-D: thread q takes rows 2 (q / n1) and 2 (q / n1) + 1 of
 // column q % n1; 3-D: block row by takes planes 2 by and 2 by + 1.
-template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+template <typename T, int D, int SCHEME, int HAM, int MODE>
 __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 {
     constexpr bool PAIR = direct_pairs<T, D, SCHEME>();
@@ -277,8 +278,8 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
             jl -= n1;
         }
         int j[kMaxDim] = {2 * pr, jl, 0, 0};
-        if (j[0] + 1 < a.g.n[0]) direct_pair<T, D, SCHEME, HAM, KEEP>(a, j);
-        else direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
+        if (j[0] + 1 < a.g.n[0]) direct_pair<T, D, SCHEME, HAM, MODE>(a, j);
+        else direct_node<T, D, SCHEME, HAM, MODE>(a, j);
         return;
     }
     if (q >= a.g.plane) return;
@@ -300,14 +301,14 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
         j[D - 1] = jl;
     }
     if constexpr (D <= 2) {  // one plane: no loop over the slow axes
-        direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
+        direct_node<T, D, SCHEME, HAM, MODE>(a, j);
         return;
     }
     if constexpr (D == 3 && PAIR) {
         for (int sp = by; 2 * sp < a.g.slow; sp += gridDim.y) {
             j[0] = 2 * sp;
-            if (j[0] + 1 < a.g.n[0]) direct_pair<T, D, SCHEME, HAM, KEEP>(a, j);
-            else direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
+            if (j[0] + 1 < a.g.n[0]) direct_pair<T, D, SCHEME, HAM, MODE>(a, j);
+            else direct_node<T, D, SCHEME, HAM, MODE>(a, j);
         }
         return;
     }
@@ -317,7 +318,7 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
             j[0] = sy / a.g.n[1];
             j[1] = sy - j[0] * a.g.n[1];
         }
-        direct_node<T, D, SCHEME, HAM, KEEP>(a, j);
+        direct_node<T, D, SCHEME, HAM, MODE>(a, j);
     }
 }
 
@@ -327,10 +328,10 @@ __device__ __forceinline__ void direct_stage(const StageArgs<T> &a)
 // lanes: a handful of lane moves per thread, against an eighth more waves
 // to hide latency (about 2% faster at 101^3).  WENO keeps one node per
 // thread: pairs need 75 vector registers (6 waves) and were 2% slower.
-template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+template <typename T, int D, int SCHEME, int HAM, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void stage_direct_kernel(StageArgs<T> a)
 {
-    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
+    direct_stage<T, D, SCHEME, HAM, MODE>(a);
 }
 
 // FP64: the vector registers bound the occupancy, so no cap.  Pairs of
@@ -338,10 +339,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(96))) void stag
 // quarter-rate FP64 reciprocals, outweigh 4 waves per SIMD instead of 5
 // (29.0 -> 27.3 us per stage at 101^3); first order in 2-D reads 4 values
 // per node instead of 5 (4.4 -> 4.8 TB/s at 4096^2).
-template <typename T, int D, int SCHEME, int HAM, bool KEEP>
+template <typename T, int D, int SCHEME, int HAM, int MODE>
 __global__ __launch_bounds__(256) void stage_direct_kernel_f64(StageArgs<T> a)
 {
-    direct_stage<T, D, SCHEME, HAM, KEEP>(a);
+    direct_stage<T, D, SCHEME, HAM, MODE>(a);
 }
 
 // First order in 2-D, two x-neighbours per thread, for an even row length
@@ -363,7 +364,7 @@ struct Vec2<double> {
     using type = double2;
 };
 
-template <typename T, int HAM, bool KEEP>
+template <typename T, int HAM, int MODE>
 __global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
 {
     using T2 = typename Vec2<T>::type;
@@ -373,9 +374,9 @@ __global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
     const int y = (int)(q / hx), x0 = 2 * (int)(q - (long)y * hx);
     int j[kMaxDim] = {y, x0, 0, 0};
     if (y < 1 || y > ny - 2 || x0 < 1 || x0 + 2 > nx - 1) {
-        direct_node<T, 2, kSchemeFirst, HAM, KEEP>(a, j);
+        direct_node<T, 2, kSchemeFirst, HAM, MODE>(a, j);
         j[1] = x0 + 1;
-        direct_node<T, 2, kSchemeFirst, HAM, KEEP>(a, j);
+        direct_node<T, 2, kSchemeFirst, HAM, MODE>(a, j);
         return;
     }
     const int idx = y * nx + x0;
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
     node_derivs<T, kSchemeFirst>(v1, a.inv_dx[1], a.dx[1], pm[1], pp[1]);
     node_derivs<T, kSchemeFirst>(w0, a.inv_dx[0], a.dx[0], pm2[0], pp2[0]);
     node_derivs<T, kSchemeFirst>(w1, a.inv_dx[1], a.dx[1], pm2[1], pp2[1]);
-    if constexpr (KEEP) {
+    if constexpr (MODE == kNodeKeep) {
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
             at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
@@ -400,9 +401,9 @@ __global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
             at32(a.dp_out + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx + 1) = pp2[d];
         }
     }
-    const T r0 = stage_result<T, 2, HAM>(a, j, pm, pp, c.x, idx);
+    const T r0 = stage_result<T, 2, HAM, MODE == kNodeClip>(a, j, pm, pp, c.x, idx);
     j[1] = x0 + 1;
-    const T r1 = stage_result<T, 2, HAM>(a, j, pm2, pp2, c.y, idx + 1);
+    const T r1 = stage_result<T, 2, HAM, MODE == kNodeClip>(a, j, pm2, pp2, c.y, idx + 1);
     T2 r;
     r.x = r0;
     r.y = r1;
@@ -434,12 +435,17 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
     if (t.variant == kVariantPlaneMarch &&
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
+    // the replay that keeps p-, p+ never clips (the adjoint rejects a
+    // restricted update); unclipped stages run the kernels without the clip
+    if (a.dp_out && a.clip) return hipErrorInvalidValue;
+    const bool clip = !a.rhs_only && a.clip != 0;
     if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
         if (x2_applies<T, D, SCHEME>(a)) {
             const long threads = (long)a.g.n[0] * (a.g.n[1] / 2);
             const dim3 grid((unsigned)((threads + 255) / 256));
-            if (a.dp_out) hipLaunchKernelGGL((stage_x2_kernel<T, HAM, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((stage_x2_kernel<T, HAM, false>), grid, dim3(256), 0, s, a);
+            if (a.dp_out) hipLaunchKernelGGL((stage_x2_kernel<T, HAM, kNodeKeep>), grid, dim3(256), 0, s, a);
+            else if (clip) hipLaunchKernelGGL((stage_x2_kernel<T, HAM, kNodeClip>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((stage_x2_kernel<T, HAM, kNodePlain>), grid, dim3(256), 0, s, a);
             return hipGetLastError();
         }
         // with pairs: half the planes (3-D) or half the rows (2-D)
@@ -448,17 +454,24 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         const long cols = D == 2 && pairs ? (long)((a.g.n[0] + 1) / 2) * a.g.n[1] : (long)a.g.plane;
         dim3 grid((unsigned)((cols + 255) / 256), rows < 65535 ? rows : 65535);
         if constexpr (std::is_same<T, float>::value) {
-            if (a.dp_out) hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
+            if (a.dp_out)
+                hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, kNodeKeep>), grid, dim3(256), 0, s, a);
+            else if (clip)
+                hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, kNodeClip>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, kNodePlain>), grid, dim3(256), 0, s, a);
         } else {
             if (a.dp_out)
-                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, false>), grid, dim3(256), 0, s, a);
+                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, kNodeKeep>), grid, dim3(256), 0, s, a);
+            else if (clip)
+                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, kNodeClip>), grid, dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, kNodePlain>), grid, dim3(256), 0, s, a);
         }
         return hipGetLastError();
     }
     const size_t lds = stage_lds_bytes(t, sizeof(T));
-    hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
+    if (clip) hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, true>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
+    else hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, false>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ HJX_OK, HJX_ERR_INVALID_ARG, HJX_ERR_UNSUPPORTED, HJX_ERR_DEVICE, HJX_ERR_NONFIN
 HJX_F32, HJX_F64 = 0, 1
 DERIV = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2}
+RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 MAX_DIM = 4
 
 
@@ -33,7 +34,7 @@ class HamDesc(ctypes.Structure):
 
 class SchemeDesc(ctypes.Structure):
     _fields_ = [("deriv", ctypes.c_int32), ("rk", ctypes.c_int32), ("cfl", ctypes.c_double),
-                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("restrict_update", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -284,7 +285,7 @@ def hjx_batch_tune(batch, phi0_ptrs, target_ptrs, out_ptrs, t1, reps=2, stream=N
 # ------------------------------------------------------------------ handle wrapper
 
 def descriptors(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3, cfl=0.75,
-                dtype="f64"):
+                dtype="f64", restrict="none"):
     g = GridDesc()
     g.dim = len(n)
     g.periodic_mask = sum(1 << d for d in periodic)
@@ -299,6 +300,7 @@ def descriptors(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme=
     s.rk = int(rk)
     s.cfl = float(cfl)
     s.dtype = HJX_F32 if dtype in ("f32", torch.float32) else HJX_F64
+    s.restrict_update = RESTRICT[restrict] if isinstance(restrict, str) else int(restrict)
     return g, h, s
 
 
@@ -306,7 +308,7 @@ class Problem:
     """A problem handle: grid, Hamiltonian and scheme (see include/hjx.h)."""
 
     def __init__(self, gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
-                 cfl=0.75, dtype="f64"):
+                 cfl=0.75, dtype="f64", restrict="none"):
         self.shape = tuple(int(v) for v in n)
         self.dim = len(self.shape)
         self.numel = 1
@@ -315,11 +317,12 @@ class Problem:
         self.dtype = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
         self.handle = None
         self.handle = hjx_problem_create(*descriptors(gmin, gmax, n, periodic, ham, params, scheme, rk, cfl,
-                                                      dtype))
+                                                      dtype, restrict))
 
     @classmethod
     def from_workload(cls, w, dtype=None):
-        return cls(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params, w.scheme, w.rk, w.cfl, dtype or w.dtype)
+        return cls(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params, w.scheme, w.rk, w.cfl, dtype or w.dtype,
+                   w.restrict)
 
     def close(self):
         if self.handle is not None:

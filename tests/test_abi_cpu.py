@@ -40,6 +40,7 @@ def test_struct_layouts_match_the_header():
     assert hjx.GridDesc.n.offset == 8 + 2 * 8 * hjx.MAX_DIM
     assert ctypes.sizeof(hjx.HamDesc) == 8 + 64
     assert ctypes.sizeof(hjx.SchemeDesc) == 24
+    assert hjx.SchemeDesc.restrict_update.offset == 20
     assert ctypes.sizeof(hjx.Stats) == 8 * (4 + hjx.MAX_DIM + 2)
 
 
@@ -67,6 +68,8 @@ def _create(**kw):
     (dict(rk=4), "rk order"),
     (dict(cfl=0.0), "cfl"),
     (dict(cfl=1.5), "cfl"),
+    (dict(restrict=3), "restrict_update"),
+    (dict(restrict=-1), "restrict_update"),
     (dict(gmin=[0] * 4, gmax=[1] * 4, n=[300, 300, 300, 300]), "2\\^31"),
 ])
 def test_invalid_descriptors_are_rejected(kw, msg):

@@ -1,0 +1,177 @@
+"""Restricted update on the GPU (Sec. VI: the tube form with min[0, H] and
+the listing's 'positive' field; the rate of every RK stage is clipped to
+min(L, 0) or max(L, 0)) through the C ABI, against the oracle element by
+element: every derivative scheme and RK order, both precisions, 1-D to 4-D,
+ragged sizes, with and without a target, the direct, paired, two-node and
+plane-march kernels, batches that mix clipped and unclipped members, and
+the full-size dubins3d grid."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_03501_amd import inputs
+from helpers import assert_close, gpu_problem, oracle_problem, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_03501_amd import hjx  # noqa: E402
+
+TDT = {"f32": torch.float32, "f64": torch.float64}
+MODES = ["nonpositive", "positive"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_field(w, seed):
+    """The initial surface plus seeded bumps and noise: rates of both signs."""
+    return (inputs.initial_surface(w) + 0.3 * inputs.smooth_field(w.n, seed)
+            + 0.05 * inputs.rough_field(w.n, seed + 1))
+
+
+CASES = {
+    "normal1d": inputs.Workload("line1d", (-1.0,), (1.0,), (77,), (), "normal", (0.8,), radius=0.4),
+    "normal2d": inputs.NORMAL2D.with_(n=(37, 29)),
+    "normal2d_even": inputs.NORMAL2D.with_(n=(33, 64)),          # two-node kernel for first order
+    "dubins3d": inputs.DUBINS3D.with_(n=(19, 23, 17), radius=3.0),
+    "car4d": inputs.CAR4D.with_(n=(9, 11, 8, 7), radius=1.5),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scheme,rk", [("first", 1), ("eno2", 2), ("eno3", 3), ("weno5", 3), ("weno5", 1)])
+@pytest.mark.parametrize("case", list(CASES))
+def test_restricted_solve_matches_the_oracle(case, scheme, rk, dtype):
+    for k, mode in enumerate(MODES):
+        w = CASES[case].with_(scheme=scheme, rk=rk, restrict=mode)
+        say(f"restrict {case} {scheme} rk{rk} {dtype} {mode} n={w.n}")
+        phi0 = mixed_field(w, 11 + k)
+        Po = oracle_problem(w)
+        t1 = 5.5 * O.cfl_dt(Po)
+        target = phi0 + 0.02 if k == 0 else None
+        ref, n_ref, _ = O.solve(Po, phi0, t1, target=target)
+        P = gpu_problem(w, dtype)
+        got, st = P.solve(to_dev(phi0, TDT[dtype]), t1,
+                          target=None if target is None else to_dev(target, TDT[dtype]))
+        assert st["steps"] == n_ref == 6
+        assert_close(to_host(got), ref, dtype, w.periodic, f"{case} {scheme} rk{rk} {mode}")
+        # the clip changed the answer: compare with the unclipped oracle
+        plain, _, _ = O.solve(oracle_problem(w.with_(restrict="none")), phi0, t1, target=target)
+        assert np.abs(plain - ref).max() > 1e-3
+        P.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case,scheme", [("dubins3d", "weno5"), ("dubins3d", "first"), ("normal2d", "eno3"),
+                                         ("car4d", "weno5"), ("normal2d_even", "first")])
+def test_launch_shape_does_not_change_clipped_results(case, scheme, dtype):
+    """The plane-march tiles and the direct kernels (with pairs or two-node
+    rows where they apply) give the same bits under the clip."""
+    w = CASES[case].with_(scheme=scheme, rk=3, restrict="nonpositive")
+    phi0 = to_dev(mixed_field(w, 3), TDT[dtype])
+    P = gpu_problem(w, dtype)
+    t1 = 4.5 * P.dissipation()[1]
+    P.tile = (1, 256, 1, 1)
+    ref, _ = P.solve(phi0, t1)
+    ref = ref.clone()
+    for tile in [(0, 11, 3, 2), (0, 32, 8, 1), (0, w.n[-1], 1, 1)]:
+        P.tile = tile
+        got, _ = P.solve(phi0, t1)
+        assert torch.equal(got, ref), tile
+    P.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["first", "eno2", "eno3", "weno5"])
+def test_one_clipped_euler_step_is_a_min_with_the_previous_value(scheme, dtype):
+    """phi + dt min(L, 0) = min(phi + dt L, phi) in any rounding: one
+    forward-Euler step of the tube form equals the plain step with target
+    phi^n, bit for bit, on the GPU as in the oracle."""
+    w = CASES["dubins3d"].with_(scheme=scheme, rk=1)
+    phi = to_dev(mixed_field(w, 5), TDT[dtype])
+    Pc = gpu_problem(w.with_(restrict="nonpositive"), dtype)
+    Pp = gpu_problem(w, dtype)
+    dt = Pp.dissipation()[1]
+    a = Pc.step(phi.clone(), dt)
+    b = Pp.step(phi.clone(), dt, target=phi.clone())
+    assert torch.equal(a, b)
+    assert not torch.equal(a, phi)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_full_size_dubins3d_clipped_steps(mode):
+    """The 101^3 dubins3d grid in the configuration of the benchmark, FP64:
+    one clipped RK3 step against the oracle at every node, then a few FP32
+    steps that must move phi only the allowed way (to the rounding of the
+    RK3 averages, two ulps)."""
+    w = inputs.DUBINS3D.with_(restrict=mode)
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+    dt = O.cfl_dt(Po)
+    say(f"full size {mode}: oracle step")
+    ref = O.step(Po, phi0, dt, target=phi0)
+    P = gpu_problem(w, "f64")
+    got = P.step(to_dev(phi0, torch.float64), dt, target=to_dev(phi0, torch.float64))
+    assert_close(to_host(got), ref, "f64", w.periodic, f"101^3 {mode}")
+    P.close()
+    P = gpu_problem(w, "f32")
+    cur = to_dev(phi0, torch.float32)
+    eps = float(np.finfo(np.float32).eps)
+    for k in range(4):
+        nxt = P.step(cur.clone(), dt)
+        slack = 2 * eps * cur.abs()
+        ok = (nxt <= cur + slack) if mode == "nonpositive" else (nxt >= cur - slack)
+        assert bool(ok.all()), (mode, k)
+        cur = nxt
+    assert not torch.equal(cur, to_dev(phi0, torch.float32))
+    P.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_mixing_clipped_and_plain_members_equals_single_solves(dtype):
+    ws = [CASES["normal2d"].with_(restrict="nonpositive"), CASES["dubins3d"],
+          CASES["car4d"].with_(restrict="positive"), CASES["normal1d"].with_(restrict="nonpositive"),
+          CASES["dubins3d"].with_(n=(12, 17, 9), restrict="positive")]
+    ws = [w.with_(scheme="weno5", rk=3) for w in ws]
+    probs = [gpu_problem(w, dtype) for w in ws]
+    phi0 = [to_dev(mixed_field(w, 20 + i), TDT[dtype]) for i, w in enumerate(ws)]
+    steps = [5, 4, 6, 3, 7]
+    t1 = [(k - 0.5) * P.dissipation()[1] for P, k in zip(probs, steps)]
+    target = [phi0[0] + 0.01, None, None, phi0[3], None]
+    B = hjx.Batch(probs)
+    B.tune(phi0, t1, target=target, reps=1)     # occupancy of the kernel with the clip
+    got, st = B.solve(phi0, t1, target=target)
+    assert [s["steps"] for s in st] == steps
+    for i, (P, x, t, g) in enumerate(zip(probs, phi0, t1, target)):
+        y, _ = P.solve(x, t, target=g)
+        assert torch.equal(got[i], y), f"member {i}"
+    B.close()
+    # an all-plain batch still takes the kernel without the clip and agrees
+    plain = [gpu_problem(w.with_(restrict="none"), dtype) for w in ws[:2]]
+    B = hjx.Batch(plain)
+    got, _ = B.solve(phi0[:2], t1[:2])
+    for i in range(2):
+        y, _ = plain[i].solve(phi0[i], t1[i])
+        assert torch.equal(got[i], y)
+    B.close()
+
+
+def test_the_adjoint_rejects_a_restricted_update():
+    w = CASES["dubins3d"].with_(restrict="nonpositive")
+    P = gpu_problem(w, "f32")
+    with pytest.raises(hjx.HjxError) as e:
+        P.tape(0.1)
+    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED
+    assert "restricted" in str(e.value)
+    # the right-hand side itself is never clipped
+    Pn = gpu_problem(w.with_(restrict="none"), "f32")
+    phi = to_dev(mixed_field(w, 9), torch.float32)
+    assert torch.equal(P.rhs(phi), Pn.rhs(phi))
