@@ -319,6 +319,23 @@ def run_first_order_large(n=4096, steps=2, warmup=1):
             "hbm_frac": gbs / PEAK_HBM_GBS}
 
 
+def run_tube(w, dtype="f32", steps=2, warmup=1, plain_us=None):
+    """The restricted update (tube form: every stage's rate clipped to
+    min(L, 0)) on the headline workload: the same grid, scheme, horizon and
+    target, through the stage kernels compiled with the clip."""
+    wt = w.with_(restrict="nonpositive")
+    elapsed, st, loop_ms = run_gpu(wt, dtype, steps, warmup)
+    kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / (st["steps"] * wt.rk)
+    ops = alg_ops_per_point(wt.scheme, wt.ham, wt.dim) * wt.points
+    res = {"workload": f"{w.name} {dtype} with the tube form's clip min(L, 0), {st['steps']} RK steps",
+           "updates_per_s": wt.points * st["steps"] * steps / elapsed, "stage_kernel_us": kern_s * 1e6,
+           "tile": st["tile"], "alu_frac": ops / kern_s / 1e12 / PEAK_VALU_TOPS}
+    if plain_us:
+        res["stage_us_over_plain"] = kern_s * 1e6 / plain_us
+    log(f"  tube form: {kern_s * 1e6:.2f} us per stage launch")
+    return res
+
+
 def run_small(reps=20):
     """The launch-bound workload: normal2d (101^2, FP64, first-order upwind +
     forward Euler, 40 steps).  Per solve: hjx_solve (host-driven launches,
@@ -420,7 +437,7 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
-    ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large"],
+    ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -441,6 +458,8 @@ def main():
             res = run_small()
         elif args.only == "first_order_large":
             res = run_first_order_large()
+        elif args.only == "tube":
+            res = run_tube(inputs.WORKLOADS[args.workload], args.dtype)
         else:
             res = run_copy()
         print(json.dumps({"only": args.only, **res}), flush=True)
@@ -490,6 +509,9 @@ def main():
             "stage_kernel_us": k4 * 1e6,
             "alu_frac": alg_ops_per_point(w4.scheme, w4.ham, w4.dim) * w4.points / k4 / 1e12 / PEAK_VALU_TOPS,
             "hbm_alg_frac": stage_bytes_per_point(w4.rk, w4.with_target, 4) * w4.points / k4 / 1e9 / PEAK_HBM_GBS}
+
+        log(f"tube form: {w.name} {args.dtype} with the clip")
+        extra[f"{w.name}_tube_{args.dtype}"] = run_tube(w, args.dtype, plain_us=kern_s * 1e6)
 
         log("normal2d f64: launch-bound solve, host-driven vs graph replay")
         extra["normal2d_f64"] = run_small()
