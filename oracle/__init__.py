@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "libhjxo.so")
 
 MAXD = 4
 SCHEME = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
-HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2}
+HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 # restricted update (see restricted_rate in hjxo.c)
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 

@@ -81,7 +81,7 @@ typedef double real;
 #define R 3 /* widest stencil radius (ENO3 / WENO5) */
 
 enum { SCHEME_FIRST = 1, SCHEME_ENO2 = 2, SCHEME_ENO3 = 3, SCHEME_WENO5 = 5 };
-enum { HAM_NORMAL = 0, HAM_DUBINS3_PE = 1, HAM_DUBINS4 = 2 };
+enum { HAM_NORMAL = 0, HAM_DUBINS3_PE = 1, HAM_DUBINS4 = 2, HAM_ROCKETS = 3 };
 enum { RESTRICT_NONE = 0, RESTRICT_NONPOSITIVE = 1, RESTRICT_POSITIVE = 2 };
 
 /* Problem description, laid out for ctypes. */
@@ -335,7 +335,20 @@ static void derivative_axis(const hjxo_problem *P, const real *phi, int d, real 
  * HAM_DUBINS4    hp = [wbar, abar]: car with speed state (x, y, theta, v),
  *                xdot = v cos th, ydot = v sin th, thdot = w, vdot = a;
  *                the control minimises p.f (reach), so
- *                H = -v(p1 cos th + p2 sin th) + wbar |p3| + abar |p4|.      */
+ *                H = -v(p1 cos th + p2 sin th) + wbar |p3| + abar |p4|.
+ * HAM_ROCKETS    hp = [a, g, ubar_e, ubar_p]: the two-rocket game of Sec. VI,
+ *                state (x, z, theta), with the vector field inside the
+ *                max-min of eq. (ham_def) and a_e = a_p = a:
+ *                  xdot = a cos th + u_e x
+ *                  zdot = a sin th + a + u_p x - g
+ *                  thdot = u_p - u_e,  |u_e| <= ubar_e, |u_p| <= ubar_p;
+ *                the evader maximises and the pursuer minimises p.f.  The
+ *                terms in u_e and u_p separate, so
+ *                H = -[a p1 cos th + p2 (a sin th + a - g)
+ *                      + ubar_e |p1 x - p3| - ubar_p |p2 x + p3|].
+ *                (The closed form printed as eq. (rocket_hamfunc) differs
+ *                from this in the sign of the p2 term and of both absolute
+ *                values; the definition is followed.)                       */
 
 static real ham_value(const hjxo_problem *P, const real *hp, const double *x, const real *p)
 {
@@ -355,6 +368,12 @@ static real ham_value(const hjxo_problem *P, const real *hp, const double *x, co
         double c = cos(x[2]), sn = sin(x[2]);
         real wb = hp[0], ab = hp[1];
         return -x[3] * (p[0] * c + p[1] * sn) + wb * r_abs(p[2]) + ab * r_abs(p[3]);
+    }
+    case HAM_ROCKETS: {
+        double c = cos(x[2]), sn = sin(x[2]);
+        real a = hp[0], g = hp[1], ue = hp[2], up = hp[3];
+        real drift = a * c * p[0] + (a * sn + a - g) * p[1];
+        return -(drift + ue * r_abs(p[0] * x[0] - p[2]) - up * r_abs(p[1] * x[0] + p[2]));
     }
     }
     return 0.0;
@@ -378,6 +397,12 @@ static real partial_bound(const hjxo_problem *P, const real *hp, const double *x
         if (d == 1) return r_abs((real)(x[3] * sin(x[2])));
         if (d == 2) return wb;
         return ab;
+    }
+    case HAM_ROCKETS: {
+        real a = hp[0], g = hp[1], ue = hp[2], up = hp[3];
+        if (d == 0) return r_abs(a * cos(x[2])) + ue * fabs(x[0]);
+        if (d == 1) return r_abs(a * sin(x[2]) + a - g) + up * fabs(x[0]);
+        return ue + up;
     }
     }
     return 0.0;
@@ -550,7 +575,8 @@ static int check_problem(const hjxo_problem *P)
     if (P->restrict_update < RESTRICT_NONE || P->restrict_update > RESTRICT_POSITIVE) return -1;
     if (P->ham_kind == HAM_DUBINS3_PE && P->dim != 3) return -1;
     if (P->ham_kind == HAM_DUBINS4 && P->dim != 4) return -1;
-    if (P->ham_kind < 0 || P->ham_kind > 2) return -1;
+    if (P->ham_kind == HAM_ROCKETS && P->dim != 3) return -1;
+    if (P->ham_kind < 0 || P->ham_kind > 3) return -1;
     return 0;
 }
 

@@ -72,7 +72,15 @@ DUBINS3D_81 = DUBINS3D.with_(name="dubins3d_81", n=(81, 81, 81), dtype="f32")
 CAR4D = Workload("car4d", (-5.0, -5.0, 0.0, 0.0), (5.0, 5.0, 2 * math.pi, 2.0), (81, 81, 81, 81), (2,),
                  "dubins4", (1.0, 1.0), "weno5", 3, 0.75, 1.5, False, 1.0, "cylinder", "f32")
 
-WORKLOADS = {w.name: w for w in (NORMAL2D, DUBINS3D, DUBINS3D_81, CAR4D)}
+# The two-rocket game (Sec. VI): 100 nodes per axis, x and z over [-64, 64],
+# the angle over [-pi/2, pi/2]; a = 1, g = 32, unit control bounds; ENO2 with
+# second-order TVD-RK over 2.5 s; capture radius 1.5 (a cylinder along the
+# angle); the listing's 'positive' restricted update.
+ROCKETS = Workload("rockets", (-64.0, -64.0, -math.pi / 2), (64.0, 64.0, math.pi / 2), (100, 100, 100), (),
+                   "rockets", (1.0, 32.0, 1.0, 1.0), "eno2", 2, 0.75, 2.5, False, 1.5, "cylinder", "f32",
+                   restrict="positive")
+
+WORKLOADS = {w.name: w for w in (NORMAL2D, DUBINS3D, DUBINS3D_81, CAR4D, ROCKETS)}
 
 
 def node_axes(w):
