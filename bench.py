@@ -51,7 +51,8 @@ def describe(w, rk_steps):
     """The workload in words: problem, grid, scheme, horizon."""
     what = {"normal": f"{w.dim}-D motion in the normal direction",
             "dubins3_pe": "3-D pursuit-evasion game of two Dubins cars",
-            "dubins4": "4-D Dubins car with a speed state"}[w.ham]
+            "dubins4": "4-D Dubins car with a speed state",
+            "rockets": "3-D game of two rockets"}[w.ham]
     scheme = {"first": "first-order upwind", "eno2": "ENO2", "eno3": "ENO3", "weno5": "WENO5"}[w.scheme]
     rk = {1: "forward Euler", 2: "TVD-RK2", 3: "TVD-RK3"}[w.rk]
     tube = ", min-with-target (BRT)" if w.with_target else ""
@@ -336,6 +337,22 @@ def run_tube(w, dtype="f32", steps=2, warmup=1, plain_us=None):
     return res
 
 
+def run_rockets(steps=2, warmup=1):
+    """The paper's own workload, the two-rocket game: 100^3 nodes, ENO2 +
+    LF + TVD-RK2 over 2.5 s with the positive restricted update, FP32."""
+    from paper_2411_03501_amd import inputs
+
+    w = inputs.ROCKETS
+    elapsed, st, loop_ms = run_gpu(w, "f32", steps, warmup)
+    kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / (st["steps"] * w.rk)
+    bytes_launch = stage_bytes_per_point(w.rk, w.with_target, 4) * w.points
+    log(f"  rockets: {st['steps']} RK steps, {kern_s * 1e6:.2f} us per stage launch")
+    return {"workload": describe(w, st["steps"]) + ", positive restricted update, FP32",
+            "updates_per_s": w.points * st["steps"] * steps / elapsed, "stage_kernel_us": kern_s * 1e6,
+            "tile": st["tile"], "hbm_alg_gbs": bytes_launch / kern_s / 1e9,
+            "hbm_alg_frac": bytes_launch / kern_s / 1e9 / PEAK_HBM_GBS}
+
+
 def run_small(reps=20):
     """The launch-bound workload: normal2d (101^2, FP64, first-order upwind +
     forward Euler, 40 steps).  Per solve: hjx_solve (host-driven launches,
@@ -437,7 +454,8 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
-    ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube"],
+    ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube",
+                                       "rockets"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -458,6 +476,8 @@ def main():
             res = run_small()
         elif args.only == "first_order_large":
             res = run_first_order_large()
+        elif args.only == "rockets":
+            res = run_rockets()
         elif args.only == "tube":
             res = run_tube(inputs.WORKLOADS[args.workload], args.dtype)
         else:
@@ -512,6 +532,9 @@ def main():
 
         log(f"tube form: {w.name} {args.dtype} with the clip")
         extra[f"{w.name}_tube_{args.dtype}"] = run_tube(w, args.dtype, plain_us=kern_s * 1e6)
+
+        log("rockets f32: the paper's own workload")
+        extra["rockets_f32"] = run_rockets()
 
         log("normal2d f64: launch-bound solve, host-driven vs graph replay")
         extra["normal2d_f64"] = run_small()

@@ -98,11 +98,21 @@ typedef enum {
  *   HJX_HAM_DUBINS4     dim 4, axes (x, y, theta, v), p = {wbar, abar}:
  *       car with speed state, reach: H = -v(p1 cos th + p2 sin th)
  *       + wbar|p3| + abar|p4|, alpha = (|v cos th|, |v sin th|, wbar, abar).
- *       Requires wbar, abar >= 0. */
+ *       Requires wbar, abar >= 0.
+ *   HJX_HAM_ROCKETS     dim 3, axes (x, z, theta), p = {a, g, ubar_e, ubar_p}:
+ *       the two-rocket game of Sec. VI with the vector field of the max-min
+ *       in eq. (ham_def) (a_e = a_p = a; |u_e| <= ubar_e, |u_p| <= ubar_p):
+ *       H = -[a p1 cos th + p2 (a sin th + a - g)
+ *             + ubar_e |p1 x - p3| - ubar_p |p2 x + p3|],
+ *       alpha = (|a cos th| + ubar_e|x|, |a sin th + a - g| + ubar_p|x|,
+ *                ubar_e + ubar_p).  Requires ubar_e, ubar_p >= 0.  Not
+ *       available to hjx_tape_create or hjx_batch_create
+ *       (HJX_ERR_UNSUPPORTED). */
 typedef enum {
     HJX_HAM_NORMAL = 0,
     HJX_HAM_DUBINS3_PE = 1,
-    HJX_HAM_DUBINS4 = 2
+    HJX_HAM_DUBINS4 = 2,
+    HJX_HAM_ROCKETS = 3
 } hjx_ham_kind;
 
 #define HJX_MAX_DIM 4
@@ -248,8 +258,9 @@ typedef struct hjx_tape hjx_tape;
  * `stream`) and allocates the checkpoints and the replay workspace: about
  * (steps/ckpt_every + 6 ckpt_every + 4 + 3 dim) arrays of the problem's size, plus
  * the derivative store of hjx_tape_set_mode.
- * Arrays must be under 4 GiB each, and the scheme's restrict_update must be
- * HJX_RESTRICT_NONE (else HJX_ERR_UNSUPPORTED). */
+ * Arrays must be under 4 GiB each, the scheme's restrict_update must be
+ * HJX_RESTRICT_NONE and the Hamiltonian not ROCKETS (else
+ * HJX_ERR_UNSUPPORTED). */
 hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream,
                            hjx_tape **out);
 hjx_status hjx_tape_destroy(hjx_tape *tape);
@@ -308,7 +319,8 @@ typedef struct hjx_batch hjx_batch;
 /* Create a batch of n >= 1 problems (host array of handles, each used once).
  * Runs the dissipation reduction of every member and fixes its CFL step
  * (synchronises `stream`).  The launch shape defaults to the resident
- * block count and 1024-node items. */
+ * block count and 1024-node items.  Members with the ROCKETS Hamiltonian are
+ * rejected (HJX_ERR_UNSUPPORTED). */
 hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *stream, hjx_batch **out);
 hjx_status hjx_batch_destroy(hjx_batch *b);
 

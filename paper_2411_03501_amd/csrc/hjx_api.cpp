@@ -102,6 +102,7 @@ int n_params(int kind)
     case HJX_HAM_NORMAL: return 1;
     case HJX_HAM_DUBINS3_PE: return 4;
     case HJX_HAM_DUBINS4: return 2;
+    case HJX_HAM_ROCKETS: return 4;
     }
     return 0;
 }
@@ -195,6 +196,10 @@ hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_sch
     if (h->kind == HJX_HAM_DUBINS4) {
         if (g->dim != 4) return fail(HJX_ERR_INVALID_ARG, "DUBINS4 needs dim 4, got %d", g->dim);
         if (h->p[0] < 0 || h->p[1] < 0) return fail(HJX_ERR_INVALID_ARG, "control bounds must be >= 0");
+    }
+    if (h->kind == HJX_HAM_ROCKETS) {
+        if (g->dim != 3) return fail(HJX_ERR_INVALID_ARG, "ROCKETS needs dim 3, got %d", g->dim);
+        if (h->p[2] < 0 || h->p[3] < 0) return fail(HJX_ERR_INVALID_ARG, "control bounds must be >= 0");
     }
     if (s->deriv != HJX_DERIV_FIRST && s->deriv != HJX_DERIV_ENO2 && s->deriv != HJX_DERIV_ENO3 &&
         s->deriv != HJX_DERIV_WENO5)
@@ -865,6 +870,8 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     if (!direct_ok(geometry(p), p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the adjoint needs arrays under 4 GiB");
     if (p->scheme.restrict_update != HJX_RESTRICT_NONE)
         return fail(HJX_ERR_UNSUPPORTED, "the adjoint of a restricted update is not implemented");
+    if (p->ham.kind == HJX_HAM_ROCKETS)
+        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the ROCKETS Hamiltonian is not implemented");
     hjx_tape *t = new (std::nothrow) hjx_tape;
     if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
     t->p = p;
@@ -1538,6 +1545,8 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
         if (p->device != p0->device) return fail(HJX_ERR_INVALID_ARG, "problems[%d] is on another device", i);
         if (!direct_ok(geometry(p), p->elem))
             return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: arrays of 4 GiB or more", i);
+        if (p->ham.kind == HJX_HAM_ROCKETS)
+            return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: the batch kernel has no ROCKETS Hamiltonian", i);
     }
     {
         const size_t need = (p0->scheme.dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>)) *

@@ -350,6 +350,14 @@ __device__ __forceinline__ T ham_value(const StageArgs<T> &a, const int *j, cons
         const T drift = fmaT(p[0], fmaT(vp, c, -ve), p[1] * (vp * sn));
         const T arg = fmaT(p[0], y, -fmaT(p[1], x, p[2]));
         return -fmaT(we, vabs(arg), fmaT(-wp, vabs(p[2]), drift));
+    } else if constexpr (HAM == kHamRockets) {
+        // -[a p1 cos th + p2 (a sin th + a - g) + ubar_e |p1 x - p3| - ubar_p |p2 x + p3|]
+        const T x = a.tab.coord[0][j[0]];
+        const T c = a.tab.cosv[2][j[2]], sn = a.tab.sinv[2][j[2]];
+        const T ac = a.hp[0], g = a.hp[1], ue = a.hp[2], up = a.hp[3];
+        const T drift = fmaT(p[0], ac * c, p[1] * (fmaT(ac, sn, ac) - g));
+        const T e = fmaT(p[0], x, -p[2]), q = fmaT(p[1], x, p[2]);
+        return -fmaT(ue, vabs(e), fmaT(-up, vabs(q), drift));
     } else {
         // -v (p1 cos th + p2 sin th) + wbar |p3| + abar |p4|
         const T c = a.tab.cosv[2][j[2]], sn = a.tab.sinv[2][j[2]];

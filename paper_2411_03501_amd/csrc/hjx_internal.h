@@ -242,7 +242,7 @@ inline size_t stage_lds_bytes(const Tile &t, size_t elem)
 }
 
 enum : int { kSchemeFirst = 1, kSchemeEno2 = 2, kSchemeEno3 = 3, kSchemeWeno5 = 5 };
-enum : int { kHamNormal = 0, kHamDubins3 = 1, kHamDubins4 = 2 };
+enum : int { kHamNormal = 0, kHamDubins3 = 1, kHamDubins4 = 2, kHamRockets = 3 };
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_stage_f32(const StageArgs<float> &a, int scheme, int ham, hipStream_t s);

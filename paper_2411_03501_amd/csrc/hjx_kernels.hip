@@ -498,6 +498,10 @@ hipError_t launch_stage(const StageArgs<T> &a, int scheme, int ham, hipStream_t 
         if (a.g.dim != 4) return hipErrorInvalidValue;
         return launch_scheme<T, 4, kHamDubins4>(a, scheme, s);
     }
+    if (ham == kHamRockets) {
+        if (a.g.dim != 3) return hipErrorInvalidValue;
+        return launch_scheme<T, 3, kHamRockets>(a, scheme, s);
+    }
     switch (a.g.dim) {
     case 1: return launch_scheme<T, 1, kHamNormal>(a, scheme, s);
     case 2: return launch_scheme<T, 2, kHamNormal>(a, scheme, s);
@@ -521,6 +525,13 @@ __device__ __forceinline__ double partial_bound(const AlphaArgs<T> &a, const int
         if (d == 0) return (double)(vabs(-ve + vp * a.tab.cosv[2][j[2]]) + we * vabs(a.tab.coord[1][j[1]]));
         if (d == 1) return (double)(vabs(vp * a.tab.sinv[2][j[2]]) + we * vabs(a.tab.coord[0][j[0]]));
         return (double)(we + wp);
+    }
+    if (a.ham == kHamRockets) {
+        const T ac = a.hp[0], g = a.hp[1], ue = a.hp[2], up = a.hp[3];
+        const T ax = vabs(a.tab.coord[0][j[0]]);
+        if (d == 0) return (double)(vabs(ac * a.tab.cosv[2][j[2]]) + ue * ax);
+        if (d == 1) return (double)(vabs(ac * a.tab.sinv[2][j[2]] + ac - g) + up * ax);
+        return (double)(ue + up);
     }
     const T v = a.tab.coord[3][j[3]];
     if (d == 0) return (double)vabs(v * a.tab.cosv[2][j[2]]);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhjx.so")
 HJX_OK, HJX_ERR_INVALID_ARG, HJX_ERR_UNSUPPORTED, HJX_ERR_DEVICE, HJX_ERR_NONFINITE, HJX_ERR_OOM = range(6)
 HJX_F32, HJX_F64 = 0, 1
 DERIV = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
-HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2}
+HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 MAX_DIM = 4
 
