@@ -59,6 +59,35 @@ def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme
     return P
 
 
+class Claw(ctypes.Structure):
+    """A scalar conservation law v_t + sum_d f_d(v)_{x_d} = 0 on a grid."""
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("gmin", ctypes.c_double * MAXD),
+        ("gmax", ctypes.c_double * MAXD),
+        ("n", ctypes.c_long * MAXD),
+        ("periodic_mask", ctypes.c_uint),
+        ("flux", ctypes.c_int),
+        ("c", ctypes.c_double * MAXD),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+FLUX = {"linear": 0, "burgers": 1}
+
+
+def make_claw(gmin, gmax, n, periodic=(), flux="burgers", c=(1.0,), cfl=0.9):
+    C = Claw()
+    C.dim = len(n)
+    for d in range(len(n)):
+        C.gmin[d], C.gmax[d], C.n[d] = float(gmin[d]), float(gmax[d]), int(n[d])
+        C.c[d] = float(c[d] if d < len(c) else c[-1])
+    C.periodic_mask = sum(1 << d for d in periodic)
+    C.flux = FLUX[flux] if isinstance(flux, str) else int(flux)
+    C.cfl = float(cfl)
+    return C
+
+
 _lib = None
 
 
@@ -92,6 +121,12 @@ def lib():
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          dp, dp, dp, dp]
         L.hjxo_cs_solve_loss.restype = ctypes.c_long
+        CP = ctypes.POINTER(Claw)
+        L.hjxo_claw_dt.argtypes = [CP, dp]
+        L.hjxo_claw_dt.restype = ctypes.c_double
+        L.hjxo_claw_step.argtypes = [CP, dp, dp, ctypes.c_double]
+        L.hjxo_claw_solve.argtypes = [CP, dp, ctypes.c_double, dp, dp]
+        L.hjxo_claw_solve.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -219,3 +254,27 @@ def cs_solve_loss(P, phi0, t1, dphi0=None, dparams=None, with_target=True, t0=0.
     if want_state:
         return loss.value, dloss.value, n, phT, tan
     return loss.value, dloss.value, n
+
+
+def claw_dt(C, v):
+    dt = lib().hjxo_claw_dt(ctypes.byref(C), _ptr(_f64(v)))
+    if dt < 0:
+        raise ValueError("oracle claw_dt rejected its arguments")
+    return dt
+
+
+def claw_step(C, v, dt):
+    v = _f64(v)
+    out = np.empty_like(v)
+    _check(lib().hjxo_claw_step(ctypes.byref(C), _ptr(v), _ptr(out), float(dt)), "claw_step")
+    return out
+
+
+def claw_solve(C, v0, t1):
+    """Returns (v(t1), number of steps, dt)."""
+    v0 = _f64(v0)
+    out = np.empty_like(v0)
+    dt = ctypes.c_double(0.0)
+    n = _check(lib().hjxo_claw_solve(ctypes.byref(C), _ptr(v0), float(t1), _ptr(out), ctypes.byref(dt)),
+               "claw_solve")
+    return out, n, dt.value

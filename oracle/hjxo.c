@@ -38,6 +38,9 @@
  *   CFL time step ................ Sec. IV-D (lambda max|f'| <= 1) and Sec. V
  *   TVD-RK 1/2/3 ................. Sec. V (odeCFL1/2/3 averaging steps)
  *   min-with-target .............. Sec. VI, variational HJ PDE (tube form)
+ *   conservation-law LF scheme ... Sec. IV-D: v_t + sum_d f_d(v)_{x_d} = 0 by
+ *                                  the Lax-Friedrichs scheme (hjxo_claw_*),
+ *                                  with the CFL condition of the same section
  *   restricted update ............ Sec. VI: the variational form with
  *                                  min[0, H], and the 'positive' field of
  *                                  the rockets listing (Listing 4).  Read
@@ -703,6 +706,154 @@ long hjxo_solve(const hjxo_problem *P, const double *phi0, const double *target,
     if (phi_out != phi0) memcpy(phi_out, phi0, sizeof(double) * (size_t)total);
     long steps = solve(P, P->hp, phi_out, target, t0, t1, &w, dt_first);
     ws_free(&w);
+    return steps;
+}
+
+/* ------------------------------------------------------------------ */
+/* Scalar conservation laws v_t + sum_d f_d(v)_{x_d} = 0 (Sec. IV-D).
+ *
+ * The paper gives the Lax-Friedrichs scheme in one dimension,
+ *   v_j^{n+1} = v_j^n - (lambda/2) (f(v_{j+1}) - f(v_{j-1}))
+ *               + (1/2) (v_{j+1} - 2 v_j + v_{j-1}),   lambda = dt/dx,
+ * monotone when lambda max |f'| <= 1.  In N dimensions (the reading used
+ * here) the new value is the mean of the 2N axis neighbours minus the
+ * central flux differences of every axis,
+ *   v^{n+1} = (1/2N) sum_d (v_{+d} + v_{-d}) - sum_d (lambda_d/2) (f_d(v_{+d}) - f_d(v_{-d})),
+ * which is monotone when lambda_d max |f_d'| <= 1/N on every axis, and is the
+ * printed scheme for N = 1.  Periodic axes wrap; on the others the value
+ * beyond the edge is the edge value.
+ *
+ * Fluxes: CLAW_LINEAR f_d(v) = c_d v; CLAW_BURGERS f_d(v) = c_d v^2 / 2.   */
+
+enum { CLAW_LINEAR = 0, CLAW_BURGERS = 1 };
+
+typedef struct {
+    int dim;
+    double gmin[MAXD], gmax[MAXD];
+    long n[MAXD];
+    unsigned periodic_mask;
+    int flux;        /* CLAW_LINEAR or CLAW_BURGERS */
+    double c[MAXD];  /* flux coefficient per axis */
+    double cfl;      /* 0 < cfl <= 1 */
+} hjxo_claw;
+
+/* the grid of a conservation law as a problem (for the grid helpers) */
+static hjxo_problem claw_grid(const hjxo_claw *C)
+{
+    hjxo_problem P;
+    memset(&P, 0, sizeof P);
+    P.dim = C->dim;
+    for (int d = 0; d < MAXD; ++d) {
+        P.gmin[d] = C->gmin[d];
+        P.gmax[d] = C->gmax[d];
+        P.n[d] = C->n[d];
+    }
+    P.periodic_mask = C->periodic_mask;
+    P.scheme = SCHEME_FIRST;
+    P.rk = 1;
+    P.cfl = C->cfl;
+    return P;
+}
+
+static int claw_check(const hjxo_claw *C)
+{
+    if (C->dim < 1 || C->dim > MAXD) return -1;
+    for (int d = 0; d < C->dim; ++d)
+        if (C->n[d] < 3 || !(C->gmax[d] > C->gmin[d])) return -1;
+    if (C->flux != CLAW_LINEAR && C->flux != CLAW_BURGERS) return -1;
+    if (!(C->cfl > 0) || !(C->cfl <= 1)) return -1;
+    return 0;
+}
+
+static double claw_flux(const hjxo_claw *C, int d, double v)
+{
+    if (C->flux == CLAW_LINEAR) return C->c[d] * v;
+    return C->c[d] * v * v / 2.0;
+}
+
+/* value of the neighbour of flat node f at offset s (+1 or -1) along axis d */
+static double claw_neighbour(const hjxo_problem *G, const double *v, long f, const long idx[MAXD], int d, int s)
+{
+    long stride = 1;
+    for (int e = G->dim - 1; e > d; --e) stride *= G->n[e];
+    long j = idx[d] + s;
+    if (j < 0 || j >= G->n[d]) {
+        if ((G->periodic_mask >> d) & 1u) j = j < 0 ? j + G->n[d] : j - G->n[d];
+        else j = idx[d];  /* the edge value */
+    }
+    return v[f + (j - idx[d]) * stride];
+}
+
+/* the CFL step of the data v: cfl * min_d dx_d / (N max |f_d'|), with
+ * max |f_d'| = |c_d| (linear) or |c_d| max |v| (Burgers); +inf if nothing moves */
+double hjxo_claw_dt(const hjxo_claw *C, const double *v)
+{
+    if (claw_check(C)) return -1.0;
+    hjxo_problem G = claw_grid(C);
+    double vmax = 0.0;
+    if (C->flux == CLAW_BURGERS)
+        for (long f = 0; f < npoints(&G); ++f) vmax = fabs(v[f]) > vmax ? fabs(v[f]) : vmax;
+    double dt = INFINITY;
+    for (int d = 0; d < C->dim; ++d) {
+        double speed = C->flux == CLAW_LINEAR ? fabs(C->c[d]) : fabs(C->c[d]) * vmax;
+        if (speed > 0) {
+            double h = C->cfl * spacing(&G, d) / ((double)C->dim * speed);
+            dt = h < dt ? h : dt;
+        }
+    }
+    return dt;
+}
+
+/* one Lax-Friedrichs step of size dt from v into out (no aliasing) */
+int hjxo_claw_step(const hjxo_claw *C, const double *v, double *out, double dt)
+{
+    if (claw_check(C) || !(dt >= 0) || v == out) return -1;
+    hjxo_problem G = claw_grid(C);
+    long total = npoints(&G);
+#pragma omp parallel for schedule(static)
+    for (long f = 0; f < total; ++f) {
+        long idx[MAXD];
+        unflatten(&G, f, idx);
+        double mean = 0.0, flux = 0.0;
+        for (int d = 0; d < C->dim; ++d) {
+            double vp = claw_neighbour(&G, v, f, idx, d, +1), vm = claw_neighbour(&G, v, f, idx, d, -1);
+            mean += vp + vm;
+            flux += (dt / spacing(&G, d)) / 2.0 * (claw_flux(C, d, vp) - claw_flux(C, d, vm));
+        }
+        out[f] = mean / (2.0 * C->dim) - flux;
+    }
+    return 0;
+}
+
+/* solve from 0 to t1 with the CFL step of v0 (the scheme is monotone, so
+ * max |v| and with it every speed bound never grows); the step that would
+ * reach t1 (or come within 1e-12 relative of it) lands on t1.  Returns the
+ * number of steps. */
+long hjxo_claw_solve(const hjxo_claw *C, const double *v0, double t1, double *out, double *dt_out)
+{
+    if (claw_check(C) || !(t1 >= 0)) return -1;
+    hjxo_problem G = claw_grid(C);
+    long total = npoints(&G);
+    double dt = hjxo_claw_dt(C, v0);
+    if (dt_out) *dt_out = dt;
+    double *a = (double *)malloc(sizeof(double) * (size_t)total);
+    if (!a) return -2;
+    memcpy(out, v0, sizeof(double) * (size_t)total);
+    double t = 0.0, slack = 1e-12 * (fabs(t1) > 1.0 ? fabs(t1) : 1.0);
+    long steps = 0;
+    while (t < t1) {
+        double h = dt;
+        int last = 0;
+        if (t + h >= t1 - slack) {
+            h = t1 - t;
+            last = 1;
+        }
+        hjxo_claw_step(C, out, a, h);
+        memcpy(out, a, sizeof(double) * (size_t)total);
+        ++steps;
+        t = last ? t1 : t + h;
+    }
+    free(a);
     return steps;
 }
 
