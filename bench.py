@@ -353,6 +353,47 @@ def run_rockets(steps=2, warmup=1):
             "hbm_alg_frac": bytes_launch / kern_s / 1e9 / PEAK_HBM_GBS}
 
 
+def run_claw(steps=400, warmup=20):
+    """Scalar conservation law (Sec. IV-D, Lax-Friedrichs): periodic 2-D
+    Burgers at 4096^2, FP32.  Algorithmic bytes per step: the old values
+    read once and the new ones written once (the neighbours' re-reads are
+    halo), 8 bytes per node."""
+    import torch
+
+    from paper_2411_03501_amd import hjx, inputs
+
+    w = inputs.BURGERS2D
+    G = hjx.Claw(w.gmin, w.gmax, w.n, periodic=w.periodic, flux="burgers", c=w.params, cfl=w.cfl, dtype="f32")
+    a = torch.from_numpy(inputs.burgers_initial(w)).to("cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    dt = G.dt(a)
+    for _ in range(warmup):
+        G.step(a, dt, out=b)
+        a, b = b, a
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        G.step(a, dt, out=b)
+        a, b = b, a
+    e1.record()
+    torch.cuda.synchronize()
+    kern_s = e0.elapsed_time(e1) / 1e3 / steps
+    # a whole solve (input check, CFL reduction, the steps, output check)
+    v0 = torch.from_numpy(inputs.burgers_initial(w)).to("cuda", dtype=torch.float32)
+    t0 = time.perf_counter()
+    _, st = G.solve(v0, (steps - 0.5) * G.dt(v0), out=b)
+    solve_s = time.perf_counter() - t0
+    G.close()
+    bytes_step = 2 * 4 * w.points
+    gbs = bytes_step / kern_s / 1e9
+    log(f"  burgers2d: {kern_s * 1e6:.2f} us per step, {gbs:.0f} GB/s algorithmic")
+    return {"workload": "burgers2d: 2-D Burgers, 4096x4096 periodic, Lax-Friedrichs, CFL 0.9, FP32",
+            "step_kernel_us": kern_s * 1e6, "updates_per_s": w.points / kern_s,
+            "solve_updates_per_s": w.points * st["steps"] / solve_s, "solve_steps": st["steps"],
+            "bytes_per_step": bytes_step, "hbm_alg_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+
+
 def run_small(reps=20):
     """The launch-bound workload: normal2d (101^2, FP64, first-order upwind +
     forward Euler, 40 steps).  Per solve: hjx_solve (host-driven launches,
@@ -455,7 +496,7 @@ def main():
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
     ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube",
-                                       "rockets"],
+                                       "rockets", "claw"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -476,6 +517,8 @@ def main():
             res = run_small()
         elif args.only == "first_order_large":
             res = run_first_order_large()
+        elif args.only == "claw":
+            res = run_claw()
         elif args.only == "rockets":
             res = run_rockets()
         elif args.only == "tube":
@@ -535,6 +578,9 @@ def main():
 
         log("rockets f32: the paper's own workload")
         extra["rockets_f32"] = run_rockets()
+
+        log("burgers2d f32: the conservation-law scheme")
+        extra["burgers2d_f32"] = run_claw()
 
         log("normal2d f64: launch-bound solve, host-driven vs graph replay")
         extra["normal2d_f64"] = run_small()

@@ -349,6 +349,50 @@ hjx_status hjx_batch_solve(hjx_batch *b, const void *const *phi0, const void *co
 hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *const *target, void *const *phi_out,
                           const double *t1, int32_t reps, void *stream, double *best_ms);
 
+/* ------------------------------------------------------------------
+ * Scalar conservation laws (Sec. IV-D): v_t + sum_d f_d(v)_{x_d} = 0 by the
+ * Lax-Friedrichs scheme.  The paper prints it in one dimension,
+ *   v_j' = v_j - (lambda/2)(f(v_{j+1}) - f(v_{j-1})) + (v_{j+1} - 2 v_j + v_{j-1})/2,
+ * lambda = dt/dx, monotone when lambda max|f'| <= 1.  In N dimensions the new
+ * value is the mean of the 2N axis neighbours minus the central flux
+ * differences of every axis,
+ *   v' = (1/2N) sum_d (v_{+d} + v_{-d}) - sum_d (dt/2dx_d)(f_d(v_{+d}) - f_d(v_{-d})),
+ * monotone when (dt/dx_d) max|f_d'| <= 1/N on every axis.  Periodic axes wrap
+ * (the grid of hjx_grid_desc); beyond a non-periodic edge the value is the
+ * edge value.  Arrays are device memory of n[0]*..*n[dim-1] elements of the
+ * handle's dtype, row-major, last axis fastest.                          */
+typedef enum {
+    HJX_FLUX_LINEAR = 0,  /* f_d(v) = c_d v       (|f_d'| = |c_d|) */
+    HJX_FLUX_BURGERS = 1  /* f_d(v) = c_d v^2 / 2 (|f_d'| = |c_d| |v|) */
+} hjx_flux_kind;
+
+typedef struct hjx_claw hjx_claw;
+
+/* Create a conservation law on `grid` with flux `flux`, coefficients c[0..dim-1]
+ * (host array, finite), dtype HJX_F32 or HJX_F64 and CFL number 0 < cfl <= 1.
+ * Allocates one work array of the grid's size.  Selects the current device. */
+hjx_status hjx_claw_create(const hjx_grid_desc *grid, int32_t flux, const double *c, int32_t dtype, double cfl,
+                           hjx_claw **out);
+hjx_status hjx_claw_destroy(hjx_claw *h);
+
+/* The CFL step for data v: cfl min_d dx_d / (N max|f_d'|), the maximum taken
+ * over v for Burgers (a device reduction; synchronises `stream`); +inf when
+ * nothing moves.  v may be NULL for the linear flux. */
+hjx_status hjx_claw_dt(hjx_claw *h, const void *v, double *dt_out, void *stream);
+
+/* One step of size dt >= 0 from v into v_out (must not alias).
+ * Asynchronous on `stream`. */
+hjx_status hjx_claw_step(hjx_claw *h, const void *v, void *v_out, double dt, void *stream);
+
+/* Solve from 0 to t1 >= 0: checks v0 for NaN/Inf, takes the CFL step of v0
+ * for every step (the scheme is monotone, so max|v| never grows) and lands
+ * the step that would reach t1 (within 1e-12 relative) on t1.  v0 and v_out
+ * must not alias; v0 is not modified.  Synchronises `stream`.  steps_out,
+ * dt_out: optional host outputs.  HJX_ERR_NONFINITE if the result holds
+ * NaN or Inf (it is still written). */
+hjx_status hjx_claw_solve(hjx_claw *h, const void *v0, void *v_out, double t1, void *stream, int64_t *steps_out,
+                          double *dt_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -168,9 +168,8 @@ AxisTables<T> tables(const hjx_problem *p)
     return t;
 }
 
-hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_scheme_desc *s)
+hjx_status validate_grid(const hjx_grid_desc *g)
 {
-    if (!g || !h || !s) return fail(HJX_ERR_INVALID_ARG, "NULL descriptor");
     if (g->dim < 1 || g->dim > HJX_MAX_DIM)
         return fail(HJX_ERR_INVALID_ARG, "grid dim %d outside [1, %d]", g->dim, HJX_MAX_DIM);
     if (g->periodic_mask >> g->dim)
@@ -185,6 +184,14 @@ hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_sch
         if (total >= (int64_t(1) << 31))
             return fail(HJX_ERR_INVALID_ARG, "grid has 2^31 nodes or more");
     }
+    return HJX_OK;
+}
+
+hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_scheme_desc *s)
+{
+    if (!g || !h || !s) return fail(HJX_ERR_INVALID_ARG, "NULL descriptor");
+    hjx_status gst = validate_grid(g);
+    if (gst != HJX_OK) return gst;
     const int np = n_params(h->kind);
     if (np == 0) return fail(HJX_ERR_INVALID_ARG, "unknown Hamiltonian kind %d", h->kind);
     for (int k = 0; k < np; ++k)
@@ -1719,6 +1726,231 @@ hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *con
     hjx_status st = hjx_batch_set_shape(b, win.first, win.second);
     if (st != HJX_OK) return st;
     if (best_ms) *best_ms = best;
+    return ok();
+}
+
+}  // extern "C"
+
+// ==================================================================== conservation laws
+
+struct hjx_claw {
+    hjx_grid_desc grid{};
+    int flux = 0, dtype = 0;
+    double c[kMaxDim] = {0, 0, 0, 0};
+    double cfl = 0.0;
+    double dx[kMaxDim] = {0, 0, 0, 0};
+    int64_t total = 0;
+    size_t elem = 0;
+    int device = 0;
+    void *tmp = nullptr;                  // work array of the grid's size
+    unsigned long long *dmax = nullptr;   // device: max |v| (double bits), then the NaN/Inf flag
+    unsigned long long *hmax = nullptr;   // pinned host copy
+};
+
+namespace {
+
+void claw_release(hjx_claw *h)
+{
+    if (!h) return;
+    if (h->tmp) (void)hipFree(h->tmp);
+    if (h->dmax) (void)hipFree(h->dmax);
+    if (h->hmax) (void)hipHostFree(h->hmax);
+    delete h;
+}
+
+template <typename T>
+ClawArgs<T> claw_args(const hjx_claw *h, const void *v, void *out, double dt)
+{
+    ClawArgs<T> a{};
+    a.v = static_cast<const T *>(v);
+    a.out = static_cast<T *>(out);
+    a.dim = h->grid.dim;
+    int st = 1;
+    for (int d = h->grid.dim - 1; d >= 0; --d) {
+        a.n[d] = (int)h->grid.n[d];
+        a.stride[d] = st;
+        st *= a.n[d];
+    }
+    a.periodic = h->grid.periodic_mask;
+    a.rows = (int)(h->total / h->grid.n[h->grid.dim - 1]);
+    for (int d = 0; d < h->grid.dim; ++d) {
+        a.c[d] = T(h->c[d]);
+        a.half_lam[d] = T(dt / h->dx[d] / 2.0);
+    }
+    a.inv_2n = T(1.0 / (2.0 * h->grid.dim));
+    return a;
+}
+
+hipError_t claw_launch(const hjx_claw *h, const void *v, void *out, double dt, hipStream_t s)
+{
+    if (h->dtype == HJX_F32) return launch_claw_f32(claw_args<float>(h, v, out, dt), h->flux, s);
+    return launch_claw_f64(claw_args<double>(h, v, out, dt), h->flux, s);
+}
+
+// max |v| over the grid (synchronises s)
+hjx_status claw_maxabs(hjx_claw *h, const void *v, hipStream_t s, double *out)
+{
+    if (h->dtype == HJX_F32)
+        HIP_TRY(launch_maxabs_f32(static_cast<const float *>(v), (int)h->total, h->dmax, s));
+    else
+        HIP_TRY(launch_maxabs_f64(static_cast<const double *>(v), (int)h->total, h->dmax, s));
+    HIP_TRY(hipMemcpyAsync(h->hmax, h->dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(out, h->hmax, sizeof(double));
+    return HJX_OK;
+}
+
+// whether v holds NaN or Inf (synchronises s)
+hjx_status claw_nonfinite(hjx_claw *h, const void *v, hipStream_t s, bool *bad)
+{
+    int *flag = reinterpret_cast<int *>(h->dmax + 1);
+    HIP_TRY(launch_zero_f64acc(reinterpret_cast<double *>(h->dmax + 1), 1, s));
+    if (h->dtype == HJX_F32)
+        HIP_TRY(launch_nonfinite_f32(static_cast<const float *>(v), (int)h->total, flag, s));
+    else
+        HIP_TRY(launch_nonfinite_f64(static_cast<const double *>(v), (int)h->total, flag, s));
+    HIP_TRY(hipMemcpyAsync(h->hmax + 1, h->dmax + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int host_flag = 0;
+    std::memcpy(&host_flag, h->hmax + 1, sizeof(int));
+    *bad = host_flag != 0;
+    return HJX_OK;
+}
+
+hjx_status claw_dt(hjx_claw *h, const void *v, hipStream_t s, double *dt)
+{
+    double vmax = 1.0;
+    if (h->flux == HJX_FLUX_BURGERS) {
+        hjx_status st = claw_maxabs(h, v, s, &vmax);
+        if (st != HJX_OK) return st;
+    }
+    double best = INFINITY;
+    for (int d = 0; d < h->grid.dim; ++d) {
+        const double speed = std::fabs(h->c[d]) * vmax;
+        if (speed > 0) best = std::min(best, h->cfl * h->dx[d] / ((double)h->grid.dim * speed));
+    }
+    *dt = best;
+    return HJX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjx_status hjx_claw_create(const hjx_grid_desc *grid, int32_t flux, const double *c, int32_t dtype, double cfl,
+                           hjx_claw **out)
+{
+    if (!out) return fail(HJX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid || !c) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    hjx_status st = validate_grid(grid);
+    if (st != HJX_OK) return st;
+    if (flux != HJX_FLUX_LINEAR && flux != HJX_FLUX_BURGERS) return fail(HJX_ERR_INVALID_ARG, "unknown flux %d", flux);
+    for (int d = 0; d < grid->dim; ++d)
+        if (!std::isfinite(c[d])) return fail(HJX_ERR_INVALID_ARG, "flux coefficient %d is not finite", d);
+    if (!(cfl > 0.0) || !(cfl <= 1.0)) return fail(HJX_ERR_INVALID_ARG, "cfl %g outside (0, 1]", cfl);
+    if (dtype != HJX_F32 && dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+
+    hjx_claw *h = new (std::nothrow) hjx_claw;
+    if (!h) return fail(HJX_ERR_OOM, "host allocation failed");
+    h->grid = *grid;
+    h->flux = flux;
+    h->dtype = dtype;
+    h->cfl = cfl;
+    h->total = 1;
+    for (int d = 0; d < grid->dim; ++d) {
+        h->c[d] = c[d];
+        h->total *= grid->n[d];
+        const double len = grid->gmax[d] - grid->gmin[d];
+        h->dx[d] = ((grid->periodic_mask >> d) & 1u) ? len / (double)grid->n[d] : len / (double)(grid->n[d] - 1);
+    }
+    h->elem = dtype == HJX_F32 ? sizeof(float) : sizeof(double);
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        claw_release(h);
+        return fail(HJX_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    const size_t need = (size_t)h->total * h->elem;
+    size_t cap = 0;
+    if (over_workspace_cap(need, &cap)) {
+        claw_release(h);
+        return fail(HJX_ERR_OOM, "work array of %zu bytes exceeds HJX_MAX_WORKSPACE=%zu", need, cap);
+    }
+    if ((e = hipMalloc(&h->tmp, need)) != hipSuccess || (e = hipMalloc(&h->dmax, 2 * sizeof(unsigned long long))) !=
+                                                                hipSuccess ||
+        (e = hipHostMalloc(&h->hmax, 2 * sizeof(unsigned long long))) != hipSuccess) {
+        claw_release(h);
+        return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "allocation: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return ok();
+}
+
+hjx_status hjx_claw_destroy(hjx_claw *h)
+{
+    claw_release(h);
+    return ok();
+}
+
+hjx_status hjx_claw_dt(hjx_claw *h, const void *v, double *dt_out, void *stream)
+{
+    if (!h || !dt_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (!v && h->flux == HJX_FLUX_BURGERS) return fail(HJX_ERR_INVALID_ARG, "v is NULL (the Burgers flux needs it)");
+    hjx_status st = claw_dt(h, v, static_cast<hipStream_t>(stream), dt_out);
+    return st != HJX_OK ? st : ok();
+}
+
+hjx_status hjx_claw_step(hjx_claw *h, const void *v, void *v_out, double dt, void *stream)
+{
+    if (!h || !v || !v_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (v == v_out) return fail(HJX_ERR_INVALID_ARG, "v_out aliases v");
+    if (!std::isfinite(dt) || dt < 0) return fail(HJX_ERR_INVALID_ARG, "dt %g is not finite and >= 0", dt);
+    HIP_TRY(claw_launch(h, v, v_out, dt, static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+hjx_status hjx_claw_solve(hjx_claw *h, const void *v0, void *v_out, double t1, void *stream, int64_t *steps_out,
+                          double *dt_out)
+{
+    if (!h || !v0 || !v_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (v0 == v_out) return fail(HJX_ERR_INVALID_ARG, "v_out aliases v0");
+    if (!std::isfinite(t1) || t1 < 0) return fail(HJX_ERR_INVALID_ARG, "t1 %g is not finite and >= 0", t1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool bad = false;
+    hjx_status st = claw_nonfinite(h, v0, s, &bad);
+    if (st != HJX_OK) return st;
+    if (bad) return fail(HJX_ERR_NONFINITE, "v0 holds NaN or Inf");
+    double dt = 0.0;
+    if ((st = claw_dt(h, v0, s, &dt)) != HJX_OK) return st;
+
+    // the step sizes first, so that the ping-pong between v_out and the work
+    // array ends in v_out
+    std::vector<double> hs;
+    const double slack = 1e-12 * (std::fabs(t1) > 1.0 ? std::fabs(t1) : 1.0);
+    for (double t = 0.0; t < t1;) {
+        double step = dt;
+        bool last = false;
+        if (t + step >= t1 - slack) {
+            step = t1 - t;
+            last = true;
+        }
+        hs.push_back(step);
+        t = last ? t1 : t + step;
+    }
+    const size_t n = hs.size();
+    if (n == 0) {
+        HIP_TRY(hipMemcpyAsync(v_out, v0, (size_t)h->total * h->elem, hipMemcpyDeviceToDevice, s));
+    }
+    const void *src = v0;
+    for (size_t k = 0; k < n; ++k) {
+        void *dst = ((n - k) & 1) ? v_out : h->tmp;
+        HIP_TRY(claw_launch(h, src, dst, hs[k], s));
+        src = dst;
+    }
+    if ((st = claw_nonfinite(h, v_out, s, &bad)) != HJX_OK) return st;
+    if (steps_out) *steps_out = (int64_t)n;
+    if (dt_out) *dt_out = dt;
+    if (bad) return fail(HJX_ERR_NONFINITE, "the solution holds NaN or Inf");
     return ok();
 }
 

@@ -258,6 +258,32 @@ hipError_t launch_alpha_f64(const AlphaArgs<double> &a, double *alpha_out, hipSt
 hipError_t launch_nonfinite_f32(const float *x, int n, int *flag, hipStream_t s);
 hipError_t launch_nonfinite_f64(const double *x, int n, int *flag, hipStream_t s);
 
+// ---------------------------------------------------------------- conservation laws
+// One Lax-Friedrichs step of v_t + sum_d f_d(v)_{x_d} = 0 (hjx_claw.hip):
+// out = inv_2n sum_d (v_{+d} + v_{-d}) - sum_d half_lam[d] (f_d(v_{+d}) - f_d(v_{-d}))
+// with half_lam[d] = dt / (2 dx_d) and inv_2n = 1 / (2 dim).
+enum : int { kFluxLinear = 0, kFluxBurgers = 1 };
+
+template <typename T>
+struct ClawArgs {
+    const T *v;
+    T *out;
+    int dim;
+    int n[kMaxDim];
+    int stride[kMaxDim];
+    unsigned periodic;  // bit d: axis d periodic (else the edge value continues)
+    int rows;           // nodes / n[dim - 1]
+    T c[kMaxDim];       // f_d(v) = c_d v (linear) or c_d v^2 / 2 (Burgers)
+    T half_lam[kMaxDim];
+    T inv_2n;
+};
+
+hipError_t launch_claw_f32(const ClawArgs<float> &a, int flux, hipStream_t s);
+hipError_t launch_claw_f64(const ClawArgs<double> &a, int flux, hipStream_t s);
+// *out = max |v_i| as the bits of a double (cleared first by the launcher)
+hipError_t launch_maxabs_f32(const float *v, int n, unsigned long long *out, hipStream_t s);
+hipError_t launch_maxabs_f64(const double *v, int n, unsigned long long *out, hipStream_t s);
+
 // plain element copy (used where a stage result must land in another buffer)
 hipError_t launch_copy_f32(const float *src, float *dst, int n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int n, hipStream_t s);

@@ -19,6 +19,7 @@ HJX_F32, HJX_F64 = 0, 1
 DERIV = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
+FLUX = {"linear": 0, "burgers": 1}
 MAX_DIM = 4
 
 
@@ -87,6 +88,13 @@ SIGNATURES = {
                          ctypes.POINTER(Stats)], ctypes.c_int),
     "hjx_batch_tune": ([_P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P,
+                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hjx_claw_create": ([ctypes.POINTER(GridDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                         ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hjx_claw_destroy": ([_P], ctypes.c_int),
+    "hjx_claw_dt": ([_P, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    "hjx_claw_step": ([_P, _P, _P, ctypes.c_double, _P], ctypes.c_int),
+    "hjx_claw_solve": ([_P, _P, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_int64),
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
 }
 
@@ -488,6 +496,84 @@ class Batch:
         p0, tg, po, out = self._args(phi0, target, out)
         ms = hjx_batch_tune(self.handle, p0, tg, po, t1, reps, stream)
         return self.shape, ms
+
+
+# ------------------------------------------------------------------ conservation laws
+
+def hjx_claw_create(grid, flux, c, dtype, cfl):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_double * MAX_DIM)(*[float(x) for x in c][:MAX_DIM])
+    _check(lib().hjx_claw_create(ctypes.byref(grid), int(flux), arr, int(dtype), float(cfl), ctypes.byref(h)))
+    return h
+
+
+def hjx_claw_destroy(handle):
+    _check(lib().hjx_claw_destroy(handle))
+
+
+def hjx_claw_dt(handle, v_ptr, stream=None):
+    dt = ctypes.c_double()
+    _check(lib().hjx_claw_dt(handle, v_ptr, ctypes.byref(dt), _stream(stream)))
+    return dt.value
+
+
+def hjx_claw_step(handle, v_ptr, out_ptr, dt, stream=None):
+    _check(lib().hjx_claw_step(handle, v_ptr, out_ptr, float(dt), _stream(stream)))
+
+
+def hjx_claw_solve(handle, v0_ptr, out_ptr, t1, stream=None):
+    steps, dt = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().hjx_claw_solve(handle, v0_ptr, out_ptr, float(t1), _stream(stream), ctypes.byref(steps),
+                                ctypes.byref(dt)))
+    return steps.value, dt.value
+
+
+class Claw:
+    """A scalar conservation law v_t + sum_d f_d(v)_{x_d} = 0 solved by the
+    Lax-Friedrichs scheme (hjx_claw_*, see include/hjx.h)."""
+
+    def __init__(self, gmin, gmax, n, periodic=(), flux="burgers", c=(1.0,), cfl=0.9, dtype="f64"):
+        self.shape = tuple(int(v) for v in n)
+        self.dim = len(self.shape)
+        self.numel = 1
+        for v in self.shape:
+            self.numel *= v
+        self.dtype = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
+        cc = [float(c[d] if d < len(c) else c[-1]) for d in range(self.dim)]
+        g, _, _ = descriptors(gmin, gmax, n, periodic)
+        self.handle = None
+        self.handle = hjx_claw_create(g, FLUX[flux] if isinstance(flux, str) else int(flux), cc,
+                                      HJX_F32 if self.dtype == torch.float32 else HJX_F64, cfl)
+
+    def close(self):
+        if self.handle is not None:
+            hjx_claw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _t(self, t, name):
+        return _dev(t, self.dtype, self.numel, name)
+
+    def dt(self, v, stream=None):
+        return hjx_claw_dt(self.handle, self._t(v, "v"), stream)
+
+    def step(self, v, dt, out=None, stream=None):
+        if out is None:
+            out = torch.empty_like(v)
+        hjx_claw_step(self.handle, self._t(v, "v"), self._t(out, "v_out"), dt, stream)
+        return out
+
+    def solve(self, v0, t1, out=None, stream=None):
+        """Returns (v(t1), {"steps", "dt"})."""
+        if out is None:
+            out = torch.empty_like(v0)
+        steps, dt = hjx_claw_solve(self.handle, self._t(v0, "v0"), self._t(out, "v_out"), t1, stream)
+        return out, {"steps": steps, "dt": dt}
 
 
 class HjxSolve(torch.autograd.Function):

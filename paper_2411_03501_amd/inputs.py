@@ -82,6 +82,18 @@ ROCKETS = Workload("rockets", (-64.0, -64.0, -math.pi / 2), (64.0, 64.0, math.pi
 
 WORKLOADS = {w.name: w for w in (NORMAL2D, DUBINS3D, DUBINS3D_81, CAR4D, ROCKETS)}
 
+# A scalar conservation law (Sec. IV-D) at a size that fills the GPU:
+# Burgers' equation v_t + (c0 v^2/2)_x + (c1 v^2/2)_y = 0 on the periodic unit
+# square, 4096^2 nodes, c = (1, 0.5), CFL 0.9; params holds c.
+BURGERS2D = Workload("burgers2d", (0.0, 0.0), (1.0, 1.0), (4096, 4096), (0, 1), "burgers", (1.0, 0.5),
+                     "lf", 1, 0.9, 0.0, False, 0.0, "none", "f32")
+
+
+def burgers_initial(w, seed=2411):
+    """Smooth data for the Burgers workload: 1 plus a seeded low-mode
+    Fourier sum of amplitude 0.5 (shocks form as it steepens)."""
+    return 1.0 + 0.5 * smooth_field(w.n, seed)
+
 
 def node_axes(w):
     """Node positions per axis: non-periodic axes include both ends,

@@ -122,3 +122,30 @@ def test_batch_rejects_bad_arguments_before_the_device():
     assert L.hjx_batch_solve(None, None, None, None, None, None, None) == hjx.HJX_ERR_INVALID_ARG
     assert L.hjx_batch_tune(None, None, None, None, None, 1, None, None) == hjx.HJX_ERR_INVALID_ARG
     assert L.hjx_batch_destroy(None) == hjx.HJX_OK
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(flux=5), "unknown flux"),
+    (dict(c=[1.0, math.nan]), "not finite"),
+    (dict(cfl=0.0), "cfl"),
+    (dict(dtype=7), "dtype"),
+    (dict(n=[2, 5]), "n\\[0\\]"),
+])
+def test_claw_rejects_bad_arguments_before_the_device(kw, msg):
+    args = dict(n=[5, 5], flux=hjx.FLUX["burgers"], c=[1.0, 1.0], dtype=hjx.HJX_F64, cfl=0.9)
+    args.update(kw)
+    g, _, _ = hjx.descriptors([0, 0], [1, 1], args["n"])
+    with pytest.raises(hjx.HjxError) as e:
+        hjx.hjx_claw_create(g, args["flux"], args["c"], args["dtype"], args["cfl"])
+    assert e.value.status == hjx.HJX_ERR_INVALID_ARG
+    assert re.search(msg, str(e.value)), str(e.value)
+
+
+def test_claw_null_arguments():
+    L = hjx.lib()
+    out = ctypes.c_void_p()
+    assert L.hjx_claw_create(None, 0, None, 1, 0.9, ctypes.byref(out)) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_claw_step(None, None, None, 0.1, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_claw_solve(None, None, None, 1.0, None, None, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_claw_dt(None, None, None, None) == hjx.HJX_ERR_INVALID_ARG
+    assert L.hjx_claw_destroy(None) == hjx.HJX_OK
