@@ -21,6 +21,8 @@ SCHEME = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 # restricted update (see restricted_rate in hjxo.c)
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
+# Lax-Friedrichs dissipation: alpha_d as the grid maximum (global) or at the node (local)
+DISSIPATION = {"global": 0, "local": 1}
 
 
 class Problem(ctypes.Structure):
@@ -36,11 +38,12 @@ class Problem(ctypes.Structure):
         ("rk", ctypes.c_int),
         ("cfl", ctypes.c_double),
         ("restrict_update", ctypes.c_int),
+        ("dissipation", ctypes.c_int),
     ]
 
 
 def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
-                 cfl=0.75, restrict="none"):
+                 cfl=0.75, restrict="none", dissipation="global"):
     """Build an oracle problem.  `periodic` lists periodic axes."""
     P = Problem()
     P.dim = len(n)
@@ -56,6 +59,7 @@ def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme
     P.rk = int(rk)
     P.cfl = float(cfl)
     P.restrict_update = RESTRICT[restrict] if isinstance(restrict, str) else int(restrict)
+    P.dissipation = DISSIPATION[dissipation] if isinstance(dissipation, str) else int(dissipation)
     return P
 
 

@@ -35,6 +35,12 @@
  *                                  alpha_d the grid-wide maximum of the
  *                                  partial bound (global LF dissipation,
  *                                  Listing 4 'artificialDissipationGLF')
+ *   local LF dissipation ......... alpha_d taken at the node itself (the
+ *                                  partial bound there) instead of its grid
+ *                                  maximum; the CFL step still uses the
+ *                                  maximum.  Not in the paper, which names
+ *                                  only the global form (Listing 4); the
+ *                                  standard local variant of it.
  *   CFL time step ................ Sec. IV-D (lambda max|f'| <= 1) and Sec. V
  *   TVD-RK 1/2/3 ................. Sec. V (odeCFL1/2/3 averaging steps)
  *   min-with-target .............. Sec. VI, variational HJ PDE (tube form)
@@ -86,6 +92,7 @@ typedef double real;
 enum { SCHEME_FIRST = 1, SCHEME_ENO2 = 2, SCHEME_ENO3 = 3, SCHEME_WENO5 = 5 };
 enum { HAM_NORMAL = 0, HAM_DUBINS3_PE = 1, HAM_DUBINS4 = 2, HAM_ROCKETS = 3 };
 enum { RESTRICT_NONE = 0, RESTRICT_NONPOSITIVE = 1, RESTRICT_POSITIVE = 2 };
+enum { DISS_GLOBAL = 0, DISS_LOCAL = 1 };
 
 /* Problem description, laid out for ctypes. */
 typedef struct {
@@ -99,6 +106,7 @@ typedef struct {
     int rk;         /* 1, 2 or 3 */
     double cfl;
     int restrict_update; /* RESTRICT_NONE, RESTRICT_NONPOSITIVE or RESTRICT_POSITIVE */
+    int dissipation;     /* DISS_GLOBAL or DISS_LOCAL */
 } hjxo_problem;
 
 /* ------------------------------------------------------------------ */
@@ -453,7 +461,10 @@ static void lf_rhs(const hjxo_problem *P, const real *hp, const real *phi, const
             pbar[d] = (pm[d][f] + pp[d][f]) / 2.0;
         }
         real hhat = ham_value(P, hp, x, pbar);
-        for (int d = 0; d < P->dim; ++d) hhat = hhat - alpha[d] * (pp[d][f] - pm[d][f]) / 2.0;
+        for (int d = 0; d < P->dim; ++d) {
+            real a = P->dissipation == DISS_LOCAL ? partial_bound(P, hp, x, d) : alpha[d];
+            hhat = hhat - a * (pp[d][f] - pm[d][f]) / 2.0;
+        }
         L[f] = -hhat;
     }
 }
@@ -576,6 +587,7 @@ static int check_problem(const hjxo_problem *P)
         return -1;
     if (P->rk < 1 || P->rk > 3) return -1;
     if (P->restrict_update < RESTRICT_NONE || P->restrict_update > RESTRICT_POSITIVE) return -1;
+    if (P->dissipation != DISS_GLOBAL && P->dissipation != DISS_LOCAL) return -1;
     if (P->ham_kind == HAM_DUBINS3_PE && P->dim != 3) return -1;
     if (P->ham_kind == HAM_DUBINS4 && P->dim != 4) return -1;
     if (P->ham_kind == HAM_ROCKETS && P->dim != 3) return -1;
