@@ -320,21 +320,32 @@ def run_first_order_large(n=4096, steps=2, warmup=1):
             "hbm_frac": gbs / PEAK_HBM_GBS}
 
 
-def run_tube(w, dtype="f32", steps=2, warmup=1, plain_us=None):
-    """The restricted update (tube form: every stage's rate clipped to
-    min(L, 0)) on the headline workload: the same grid, scheme, horizon and
-    target, through the stage kernels compiled with the clip."""
-    wt = w.with_(restrict="nonpositive")
+def run_variant(w, what, dtype="f32", steps=2, warmup=1, plain_us=None, **change):
+    """A scheme variant on the headline workload (the same grid, scheme,
+    horizon and target), through the stage kernels compiled for it."""
+    wt = w.with_(**change)
     elapsed, st, loop_ms = run_gpu(wt, dtype, steps, warmup)
     kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / (st["steps"] * wt.rk)
     ops = alg_ops_per_point(wt.scheme, wt.ham, wt.dim) * wt.points
-    res = {"workload": f"{w.name} {dtype} with the tube form's clip min(L, 0), {st['steps']} RK steps",
+    res = {"workload": f"{w.name} {dtype} with {what}, {st['steps']} RK steps",
            "updates_per_s": wt.points * st["steps"] * steps / elapsed, "stage_kernel_us": kern_s * 1e6,
            "tile": st["tile"], "alu_frac": ops / kern_s / 1e12 / PEAK_VALU_TOPS}
     if plain_us:
         res["stage_us_over_plain"] = kern_s * 1e6 / plain_us
-    log(f"  tube form: {kern_s * 1e6:.2f} us per stage launch")
+    log(f"  {what}: {kern_s * 1e6:.2f} us per stage launch")
     return res
+
+
+def run_tube(w, dtype="f32", steps=2, warmup=1, plain_us=None):
+    """The restricted update (tube form: every stage's rate clipped to
+    min(L, 0)) on the headline workload."""
+    return run_variant(w, "the tube form's clip min(L, 0)", dtype, steps, warmup, plain_us, restrict="nonpositive")
+
+
+def run_local(w, dtype="f32", steps=2, warmup=1, plain_us=None):
+    """Local Lax-Friedrichs dissipation (alpha_d at the node) on the headline
+    workload."""
+    return run_variant(w, "local Lax-Friedrichs dissipation", dtype, steps, warmup, plain_us, dissipation="local")
 
 
 def run_rockets(steps=2, warmup=1):
@@ -496,7 +507,7 @@ def main():
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
     ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube",
-                                       "rockets", "claw"],
+                                       "rockets", "claw", "local"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -517,6 +528,8 @@ def main():
             res = run_small()
         elif args.only == "first_order_large":
             res = run_first_order_large()
+        elif args.only == "local":
+            res = run_local(inputs.WORKLOADS[args.workload], args.dtype)
         elif args.only == "claw":
             res = run_claw()
         elif args.only == "rockets":
@@ -575,6 +588,9 @@ def main():
 
         log(f"tube form: {w.name} {args.dtype} with the clip")
         extra[f"{w.name}_tube_{args.dtype}"] = run_tube(w, args.dtype, plain_us=kern_s * 1e6)
+
+        log(f"local LF: {w.name} {args.dtype}")
+        extra[f"{w.name}_local_lf_{args.dtype}"] = run_local(w, args.dtype, plain_us=kern_s * 1e6)
 
         log("rockets f32: the paper's own workload")
         extra["rockets_f32"] = run_rockets()

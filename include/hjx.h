@@ -130,9 +130,18 @@ typedef struct {
     int64_t n[HJX_MAX_DIM];
 } hjx_grid_desc;
 
+/* Lax-Friedrichs dissipation ('dissFunc', Listing 4):
+ *   HJX_DISS_GLOBAL  alpha_d = the grid maximum of the partial bound
+ *                    (artificialDissipationGLF, Sec. IV-D);
+ *   HJX_DISS_LOCAL   alpha_d = the partial bound at the node itself (the
+ *                    local form, not in the paper).
+ * The CFL step uses the grid maximum either way.  hjx_tape_create and
+ * hjx_batch_create reject HJX_DISS_LOCAL (HJX_ERR_UNSUPPORTED). */
+typedef enum { HJX_DISS_GLOBAL = 0, HJX_DISS_LOCAL = 1 } hjx_dissipation_kind;
+
 typedef struct {
-    int32_t kind; /* hjx_ham_kind */
-    int32_t reserved;
+    int32_t kind;        /* hjx_ham_kind */
+    int32_t dissipation; /* hjx_dissipation_kind */
     double p[8];
 } hjx_ham_desc;
 

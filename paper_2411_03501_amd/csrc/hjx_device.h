@@ -366,18 +366,46 @@ __device__ __forceinline__ T ham_value(const StageArgs<T> &a, const int *j, cons
     }
 }
 
-// What a stage node does besides its stage value: nothing (plain), keep
-// p-, p+ in a.dp_out (the replay of the adjoint), or clip the rate by
-// a.clip (a restricted update; a.clip may be 0 where one kernel serves
-// clipped and unclipped problems).  Unclipped solves never compile the clip.
-enum : int { kNodePlain = 0, kNodeKeep = 1, kNodeClip = 2 };
+// What a stage node does besides its stage value, as bits: keep p-, p+ in
+// a.dp_out (the replay of the adjoint), clip the rate by a.clip (a restricted
+// update; a.clip may be 0 where one kernel serves clipped and unclipped
+// problems), take alpha_d at the node (local Lax-Friedrichs).  Solves that
+// use none of them never compile them.
+enum : int { kNodePlain = 0, kNodeKeep = 1, kNodeClip = 2, kNodeLocal = 4 };
+
+// Bound on |dH/dp_d| over the controls at node j (the local dissipation
+// coefficient; its grid maximum is the global alpha_d).
+template <typename T, int D, int HAM>
+__device__ __forceinline__ T node_bound(const StageArgs<T> &a, const int *j, int d)
+{
+    if constexpr (HAM == kHamNormal) {
+        return vabs(a.hp[0]);
+    } else if constexpr (HAM == kHamDubins3) {
+        const T ve = a.hp[0], vp = a.hp[1], we = a.hp[2], wp = a.hp[3];
+        if (d == 0) return vabs(-ve + vp * a.tab.cosv[2][j[2]]) + we * vabs(a.tab.coord[1][j[1]]);
+        if (d == 1) return vabs(vp * a.tab.sinv[2][j[2]]) + we * vabs(a.tab.coord[0][j[0]]);
+        return we + wp;
+    } else if constexpr (HAM == kHamRockets) {
+        const T ac = a.hp[0], g = a.hp[1], ue = a.hp[2], up = a.hp[3];
+        const T ax = vabs(a.tab.coord[0][j[0]]);
+        if (d == 0) return vabs(ac * a.tab.cosv[2][j[2]]) + ue * ax;
+        if (d == 1) return vabs(ac * a.tab.sinv[2][j[2]] + ac - g) + up * ax;
+        return ue + up;
+    } else {
+        const T v = a.tab.coord[3][j[3]];
+        if (d == 0) return vabs(v * a.tab.cosv[2][j[2]]);
+        if (d == 1) return vabs(v * a.tab.sinv[2][j[2]]);
+        return d == 2 ? a.hp[0] : a.hp[1];
+    }
+}
 
 // LF Hamiltonian (Sec. IV-D) and the stage combination (Sec. V, Sec. VI):
 // L = -(H(x, pbar) - sum_d alpha_d (p+_d - p-_d)/2); the result is L itself
 // (rhs_only) or ca phi_n + cb (phi + dt L), then min with the target.  With
-// CLIP, a restricted update (Sec. VI): L is first clipped to min(L, 0)
-// (a.clip < 0) or max(L, 0) (a.clip > 0).
-template <typename T, int D, int HAM, bool CLIP = false>
+// kNodeClip in MODE, a restricted update (Sec. VI): L is first clipped to
+// min(L, 0) (a.clip < 0) or max(L, 0) (a.clip > 0).  With kNodeLocal, alpha_d
+// is node_bound at the node instead of the grid maximum a.alpha[d].
+template <typename T, int D, int HAM, int MODE = kNodePlain>
 __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, const T *pm, const T *pp, T center,
                                           int idx)
 {
@@ -387,10 +415,14 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
     for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (pm[d] + pp[d]);
     T hhat = ham_value<T, D, HAM>(a, j, pbar);
 #pragma unroll
-    for (int d = 0; d < D; ++d) hhat = fmaT(-a.alpha[d], T(0.5) * (pp[d] - pm[d]), hhat);
+    for (int d = 0; d < D; ++d) {
+        T al = a.alpha[d];
+        if constexpr ((MODE & kNodeLocal) != 0) al = node_bound<T, D, HAM>(a, j, d);
+        hhat = fmaT(-al, T(0.5) * (pp[d] - pm[d]), hhat);
+    }
     T L = -hhat;
     if (a.rhs_only) return L;
-    if constexpr (CLIP) {
+    if constexpr ((MODE & kNodeClip) != 0) {
         if (a.clip < 0) L = L > T(0) ? T(0) : L;
         if (a.clip > 0) L = L < T(0) ? T(0) : L;
     }
@@ -422,7 +454,7 @@ __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
         center = v[3];
         node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
     }
-    if constexpr (MODE == kNodeKeep) {
+    if constexpr ((MODE & kNodeKeep) != 0) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
@@ -430,7 +462,7 @@ __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
         }
     }
     *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
-        stage_result<T, D, HAM, MODE == kNodeClip>(a, j, pm, pp, center, idx);
+        stage_result<T, D, HAM, MODE>(a, j, pm, pp, center, idx);
 }
 
 // The rest of one node of the direct variant once its axis-0 derivatives
@@ -449,7 +481,7 @@ __device__ __forceinline__ void direct_rest(const StageArgs<T> &a, const int *j,
         else gather7(a.phi_in, idx, j[d], a.g.n[d], a.g.stride[d], (a.g.periodic >> d) & 1u, v);
         node_derivs<T, SCHEME>(v, a.inv_dx[d], a.dx[d], pm[d], pp[d]);
     }
-    if constexpr (MODE == kNodeKeep) {
+    if constexpr ((MODE & kNodeKeep) != 0) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
@@ -457,7 +489,7 @@ __device__ __forceinline__ void direct_rest(const StageArgs<T> &a, const int *j,
         }
     }
     *reinterpret_cast<T *>(reinterpret_cast<char *>(a.out) + (unsigned)idx * (unsigned)sizeof(T)) =
-        stage_result<T, D, HAM, MODE == kNodeClip>(a, j, pm, pp, center, idx);
+        stage_result<T, D, HAM, MODE>(a, j, pm, pp, center, idx);
 }
 
 // Two nodes of the direct variant: j and its neighbour one step along axis 0

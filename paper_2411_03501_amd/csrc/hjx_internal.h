@@ -63,6 +63,7 @@ struct StageArgs {
     T dt, ca, cb;
     int rhs_only;
     int clip;  // restricted update: 0 none, -1 L <- min(L, 0), +1 L <- max(L, 0) (not with rhs_only)
+    int local; // local Lax-Friedrichs: alpha_d at the node instead of alpha[d]
     Tile tile;
     unsigned char *mask;  // nullable: 1 where the target was the smaller (replay for the adjoint)
     T *dp_out;            // nullable: p-_d at dp_out + 2d dp_stride, p+_d at dp_out + (2d+1) dp_stride

@@ -41,10 +41,10 @@ using namespace dev;
 //   5. Hamiltonian, LF dissipation, RK combination, min with target, store.
 // Each interval is evaluated by exactly the same arithmetic whichever thread
 // or tile evaluates it, so results do not depend on the launch shape.
-// CLIP: a restricted update (the rate clipped by a.clip before step 5).
+// MODE: kNodePlain, or kNodeClip and kNodeLocal bits (hjx_device.h).
 
 
-template <typename T, int D, int SCHEME, int HAM, bool CLIP>
+template <typename T, int D, int SCHEME, int HAM, int MODE>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 {
     constexpr int AF = D - 1;  // fastest axis: along the lanes
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
                 node_derivs<T, SCHEME>(v, a.inv_dx[0], a.dx[0], pm[0], pp[0]);
             }
             // 5. LF Hamiltonian and the stage combination
-            a.out[idx] = stage_result<T, D, HAM, CLIP>(a, j, pm, pp, center, idx);
+            a.out[idx] = stage_result<T, D, HAM, MODE>(a, j, pm, pp, center, idx);
         }
 
         if constexpr (D >= 3) {  // advance the marched queue
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
     node_derivs<T, kSchemeFirst>(v1, a.inv_dx[1], a.dx[1], pm[1], pp[1]);
     node_derivs<T, kSchemeFirst>(w0, a.inv_dx[0], a.dx[0], pm2[0], pp2[0]);
     node_derivs<T, kSchemeFirst>(w1, a.inv_dx[1], a.dx[1], pm2[1], pp2[1]);
-    if constexpr (MODE == kNodeKeep) {
+    if constexpr ((MODE & kNodeKeep) != 0) {
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
             at32(a.dp_out + (size_t)(2 * d) * (size_t)a.dp_stride, idx) = pm[d];
@@ -401,9 +401,9 @@ __global__ __launch_bounds__(256) void stage_x2_kernel(StageArgs<T> a)
             at32(a.dp_out + (size_t)(2 * d + 1) * (size_t)a.dp_stride, idx + 1) = pp2[d];
         }
     }
-    const T r0 = stage_result<T, 2, HAM, MODE == kNodeClip>(a, j, pm, pp, c.x, idx);
+    const T r0 = stage_result<T, 2, HAM, MODE>(a, j, pm, pp, c.x, idx);
     j[1] = x0 + 1;
-    const T r1 = stage_result<T, 2, HAM, MODE == kNodeClip>(a, j, pm2, pp2, c.y, idx + 1);
+    const T r1 = stage_result<T, 2, HAM, MODE>(a, j, pm2, pp2, c.y, idx + 1);
     T2 r;
     r.x = r0;
     r.y = r1;
@@ -423,8 +423,9 @@ bool x2_applies(const StageArgs<T> &a)
     }
 }
 
-template <typename T, int D, int SCHEME, int HAM>
-hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
+// One stage launch in node mode M (bits of kNodeKeep, kNodeClip, kNodeLocal).
+template <typename T, int D, int SCHEME, int HAM, int M>
+hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
 {
     const Tile t = a.tile;
     const int nf = a.g.n[D - 1], nm = D >= 2 ? a.g.n[D - 2] : 1;
@@ -435,17 +436,11 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
     if (t.variant == kVariantPlaneMarch &&
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
-    // the replay that keeps p-, p+ never clips (the adjoint rejects a
-    // restricted update); unclipped stages run the kernels without the clip
-    if (a.dp_out && a.clip) return hipErrorInvalidValue;
-    const bool clip = !a.rhs_only && a.clip != 0;
-    if (t.variant == kVariantDirect || a.dp_out) {  // only the direct variant keeps p-, p+
+    if (t.variant == kVariantDirect || (M & kNodeKeep) != 0) {  // only the direct variant keeps p-, p+
         if (x2_applies<T, D, SCHEME>(a)) {
             const long threads = (long)a.g.n[0] * (a.g.n[1] / 2);
             const dim3 grid((unsigned)((threads + 255) / 256));
-            if (a.dp_out) hipLaunchKernelGGL((stage_x2_kernel<T, HAM, kNodeKeep>), grid, dim3(256), 0, s, a);
-            else if (clip) hipLaunchKernelGGL((stage_x2_kernel<T, HAM, kNodeClip>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((stage_x2_kernel<T, HAM, kNodePlain>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((stage_x2_kernel<T, HAM, M>), grid, dim3(256), 0, s, a);
             return hipGetLastError();
         }
         // with pairs: half the planes (3-D) or half the rows (2-D)
@@ -453,26 +448,37 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         const int rows = D == 3 && pairs ? (a.g.slow + 1) / 2 : a.g.slow;
         const long cols = D == 2 && pairs ? (long)((a.g.n[0] + 1) / 2) * a.g.n[1] : (long)a.g.plane;
         dim3 grid((unsigned)((cols + 255) / 256), rows < 65535 ? rows : 65535);
-        if constexpr (std::is_same<T, float>::value) {
-            if (a.dp_out)
-                hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, kNodeKeep>), grid, dim3(256), 0, s, a);
-            else if (clip)
-                hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, kNodeClip>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, kNodePlain>), grid, dim3(256), 0, s, a);
-        } else {
-            if (a.dp_out)
-                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, kNodeKeep>), grid, dim3(256), 0, s, a);
-            else if (clip)
-                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, kNodeClip>), grid, dim3(256), 0, s, a);
-            else
-                hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, kNodePlain>), grid, dim3(256), 0, s, a);
-        }
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL((stage_direct_kernel<T, D, SCHEME, HAM, M>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, M>), grid, dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    const size_t lds = stage_lds_bytes(t, sizeof(T));
-    if (clip) hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, true>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
-    else hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, false>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
-    return hipGetLastError();
+    if constexpr ((M & kNodeKeep) == 0) {
+        const size_t lds = stage_lds_bytes(t, sizeof(T));
+        hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, M>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+// The node mode of a stage: the replay that keeps p-, p+ (the adjoint) takes
+// neither the clip nor the local dissipation, which the adjoint rejects; the
+// right-hand side alone is never clipped.  Plain stages run the kernels
+// without either.
+template <typename T, int D, int SCHEME, int HAM>
+hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
+{
+    const int mode = (a.dp_out ? kNodeKeep : 0) | (!a.rhs_only && a.clip != 0 ? kNodeClip : 0) |
+                     (a.local ? kNodeLocal : 0);
+    switch (mode) {
+    case kNodePlain: return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
+    case kNodeKeep: return launch_mode<T, D, SCHEME, HAM, kNodeKeep>(a, s);
+    case kNodeClip: return launch_mode<T, D, SCHEME, HAM, kNodeClip>(a, s);
+    case kNodeLocal: return launch_mode<T, D, SCHEME, HAM, kNodeLocal>(a, s);
+    case kNodeLocal | kNodeClip: return launch_mode<T, D, SCHEME, HAM, kNodeLocal | kNodeClip>(a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int D, int HAM>

@@ -20,6 +20,7 @@ DERIV = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 FLUX = {"linear": 0, "burgers": 1}
+DISSIPATION = {"global": 0, "local": 1}
 MAX_DIM = 4
 
 
@@ -30,7 +31,7 @@ class GridDesc(ctypes.Structure):
 
 
 class HamDesc(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p", ctypes.c_double * 8)]
+    _fields_ = [("kind", ctypes.c_int32), ("dissipation", ctypes.c_int32), ("p", ctypes.c_double * 8)]
 
 
 class SchemeDesc(ctypes.Structure):
@@ -293,7 +294,7 @@ def hjx_batch_tune(batch, phi0_ptrs, target_ptrs, out_ptrs, t1, reps=2, stream=N
 # ------------------------------------------------------------------ handle wrapper
 
 def descriptors(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3, cfl=0.75,
-                dtype="f64", restrict="none"):
+                dtype="f64", restrict="none", dissipation="global"):
     g = GridDesc()
     g.dim = len(n)
     g.periodic_mask = sum(1 << d for d in periodic)
@@ -301,6 +302,7 @@ def descriptors(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme=
         g.gmin[d], g.gmax[d], g.n[d] = float(gmin[d]), float(gmax[d]), int(n[d])
     h = HamDesc()
     h.kind = HAM[ham] if isinstance(ham, str) else int(ham)
+    h.dissipation = DISSIPATION[dissipation] if isinstance(dissipation, str) else int(dissipation)
     for k, v in enumerate(params):
         h.p[k] = float(v)
     s = SchemeDesc()
@@ -316,7 +318,7 @@ class Problem:
     """A problem handle: grid, Hamiltonian and scheme (see include/hjx.h)."""
 
     def __init__(self, gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
-                 cfl=0.75, dtype="f64", restrict="none"):
+                 cfl=0.75, dtype="f64", restrict="none", dissipation="global"):
         self.shape = tuple(int(v) for v in n)
         self.dim = len(self.shape)
         self.numel = 1
@@ -325,12 +327,12 @@ class Problem:
         self.dtype = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
         self.handle = None
         self.handle = hjx_problem_create(*descriptors(gmin, gmax, n, periodic, ham, params, scheme, rk, cfl,
-                                                      dtype, restrict))
+                                                      dtype, restrict, dissipation))
 
     @classmethod
     def from_workload(cls, w, dtype=None):
         return cls(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params, w.scheme, w.rk, w.cfl, dtype or w.dtype,
-                   w.restrict)
+                   w.restrict, w.dissipation)
 
     def close(self):
         if self.handle is not None:

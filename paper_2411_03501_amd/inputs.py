@@ -50,6 +50,7 @@ class Workload:
     steps: int = 0                # batch instances: number of full steps
     extra: dict = field(default_factory=dict)
     restrict: str = "none"        # restricted update: none | nonpositive | positive
+    dissipation: str = "global"   # Lax-Friedrichs alpha: global | local
 
     @property
     def dim(self):

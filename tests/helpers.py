@@ -12,7 +12,8 @@ TOL_F32_REL = 1e-4
 
 def oracle_problem(w, **over):
     kw = dict(gmin=w.gmin, gmax=w.gmax, n=w.n, periodic=w.periodic, ham=w.ham, params=w.params,
-              scheme=w.scheme, rk=w.rk, cfl=w.cfl, restrict=w.restrict)
+              scheme=w.scheme, rk=w.rk, cfl=w.cfl, restrict=w.restrict,
+              dissipation=w.dissipation)
     kw.update(over)
     return O.make_problem(**kw)
 
@@ -20,7 +21,8 @@ def oracle_problem(w, **over):
 def gpu_problem(w, dtype=None, **over):
     from paper_2411_03501_amd import hjx
     kw = dict(gmin=w.gmin, gmax=w.gmax, n=w.n, periodic=w.periodic, ham=w.ham, params=w.params,
-              scheme=w.scheme, rk=w.rk, cfl=w.cfl, dtype=dtype or w.dtype, restrict=w.restrict)
+              scheme=w.scheme, rk=w.rk, cfl=w.cfl, dtype=dtype or w.dtype, restrict=w.restrict,
+              dissipation=w.dissipation)
     kw.update(over)
     return hjx.Problem(**kw)
 

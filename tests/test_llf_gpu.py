@@ -1,0 +1,125 @@
+"""Local Lax-Friedrichs dissipation on the GPU (alpha_d as the partial bound
+at each node; HJX_DISS_LOCAL) through the C ABI, against the oracle element
+by element: every Hamiltonian with a node-dependent bound, every scheme and
+RK order in both precisions, with a target and with the restricted update,
+every launch shape, one full-size step; identity with the global form for
+normal motion; the tape and the batch reject it."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_03501_amd import inputs
+from helpers import assert_close, gpu_problem, oracle_problem, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_03501_amd import hjx  # noqa: E402
+
+TDT = {"f32": torch.float32, "f64": torch.float64}
+
+CASES = {
+    "dubins3d": inputs.DUBINS3D.with_(n=(19, 23, 17), radius=3.0, dissipation="local"),
+    "car4d": inputs.CAR4D.with_(n=(9, 11, 8, 7), radius=1.5, dissipation="local"),
+    "rockets": inputs.ROCKETS.with_(n=(21, 19, 17), radius=20.0, restrict="none", dissipation="local"),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def field(w, seed):
+    scale = 4.0 if w.ham == "rockets" else 0.3
+    return inputs.initial_surface(w) + scale * inputs.smooth_field(w.n, seed)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scheme,rk", [("first", 1), ("eno2", 2), ("eno3", 3), ("weno5", 3)])
+@pytest.mark.parametrize("case", list(CASES))
+def test_local_dissipation_matches_the_oracle(case, scheme, rk, dtype):
+    w = CASES[case].with_(scheme=scheme, rk=rk)
+    say(f"llf {case} {scheme} rk{rk} {dtype}")
+    phi0 = field(w, 7)
+    Po = oracle_problem(w)
+    t1 = 5.5 * O.cfl_dt(Po)
+    target = phi0 + 0.05 if w.with_target else None
+    ref, n_ref, _ = O.solve(Po, phi0, t1, target=target)
+    glob, _, _ = O.solve(oracle_problem(w.with_(dissipation="global")), phi0, t1, target=target)
+    assert np.abs(glob - ref).max() > 1e-6        # the local form changed the answer
+    P = gpu_problem(w, dtype)
+    got, st = P.solve(to_dev(phi0, TDT[dtype]), t1, target=None if target is None else to_dev(target, TDT[dtype]))
+    assert st["steps"] == n_ref == 6
+    assert_close(to_host(got), ref, dtype, w.periodic, f"llf {case} {scheme} rk{rk}")
+    P.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("mode", ["nonpositive", "positive"])
+def test_local_dissipation_with_the_restricted_update(mode, dtype):
+    w = CASES["dubins3d"].with_(scheme="weno5", rk=3, restrict=mode)
+    phi0 = field(w, 9)
+    Po = oracle_problem(w)
+    t1 = 4.5 * O.cfl_dt(Po)
+    ref, n_ref, _ = O.solve(Po, phi0, t1)
+    P = gpu_problem(w, dtype)
+    got, st = P.solve(to_dev(phi0, TDT[dtype]), t1)
+    assert st["steps"] == n_ref
+    assert_close(to_host(got), ref, dtype, w.periodic, f"llf + {mode}")
+    P.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["dubins3d", "car4d"])
+def test_launch_shape_does_not_change_local_results(case, dtype):
+    w = CASES[case].with_(scheme="weno5", rk=3)
+    phi0 = to_dev(field(w, 4), TDT[dtype])
+    P = gpu_problem(w, dtype)
+    t1 = 3.5 * P.dissipation()[1]
+    P.tile = (1, 256, 1, 1)
+    ref, _ = P.solve(phi0, t1)
+    ref = ref.clone()
+    for tile in [(0, 11, 3, 2), (0, w.n[-1], 4, 1)]:
+        P.tile = tile
+        got, _ = P.solve(phi0, t1)
+        assert torch.equal(got, ref), tile
+    P.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_normal_motion_local_equals_global_bit_for_bit(dtype):
+    w = inputs.NORMAL2D.with_(n=(45, 38), scheme="weno5", rk=3, params=(1.7,))
+    phi0 = to_dev(inputs.initial_surface(w) + 0.2 * inputs.smooth_field(w.n, 2), TDT[dtype])
+    a, _ = gpu_problem(w, dtype).solve(phi0, 0.1)
+    b, _ = gpu_problem(w.with_(dissipation="local"), dtype).solve(phi0, 0.1)
+    assert torch.equal(a, b)
+
+
+def test_full_size_dubins3d_local_step():
+    w = inputs.DUBINS3D.with_(dissipation="local")
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+    dt = O.cfl_dt(Po)
+    say("full-size dubins3d local: oracle step")
+    ref = O.step(Po, phi0, dt, target=phi0)
+    P = gpu_problem(w, "f64")
+    got = P.step(to_dev(phi0, torch.float64), dt, target=to_dev(phi0, torch.float64))
+    assert_close(to_host(got), ref, "f64", w.periodic, "101^3 local")
+    P.close()
+
+
+def test_tape_and_batch_reject_the_local_dissipation():
+    P = gpu_problem(CASES["dubins3d"], "f32")
+    with pytest.raises(hjx.HjxError) as e:
+        P.tape(0.01)
+    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "local dissipation" in str(e.value)
+    with pytest.raises(hjx.HjxError) as e:
+        hjx.Batch([P])
+    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "local dissipation" in str(e.value)
+    P.close()
