@@ -21,8 +21,9 @@ SCHEME = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 # restricted update (see restricted_rate in hjxo.c)
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
-# Lax-Friedrichs dissipation: alpha_d as the grid maximum (global) or at the node (local)
-DISSIPATION = {"global": 0, "local": 1}
+# numerical Hamiltonian: Lax-Friedrichs with alpha_d as the grid maximum
+# (global) or at the node (local), or Godunov's (normal motion only)
+DISSIPATION = {"global": 0, "local": 1, "godunov": 2}
 
 
 class Problem(ctypes.Structure):

@@ -41,6 +41,17 @@
  *                                  maximum.  Not in the paper, which names
  *                                  only the global form (Listing 4); the
  *                                  standard local variant of it.
+ *   Godunov normal motion ........ for H = a|p| only, the Godunov numerical
+ *                                  Hamiltonian in place of Lax-Friedrichs:
+ *                                  the extremum of H over the interval
+ *                                  between p- and p+ on each axis (min for
+ *                                  the convex a >= 0, max for a < 0), which
+ *                                  for |p| reduces per axis to
+ *                                  q = max(max(p-, 0), -min(p+, 0)) (a >= 0)
+ *                                  or max(-min(p-, 0), max(p+, 0)) (a < 0)
+ *                                  and Hhat = a sqrt(sum q^2).  Not in the
+ *                                  paper: the monotone scheme its upwind
+ *                                  discussion leads to for this Hamiltonian.
  *   CFL time step ................ Sec. IV-D (lambda max|f'| <= 1) and Sec. V
  *   TVD-RK 1/2/3 ................. Sec. V (odeCFL1/2/3 averaging steps)
  *   min-with-target .............. Sec. VI, variational HJ PDE (tube form)
@@ -92,7 +103,7 @@ typedef double real;
 enum { SCHEME_FIRST = 1, SCHEME_ENO2 = 2, SCHEME_ENO3 = 3, SCHEME_WENO5 = 5 };
 enum { HAM_NORMAL = 0, HAM_DUBINS3_PE = 1, HAM_DUBINS4 = 2, HAM_ROCKETS = 3 };
 enum { RESTRICT_NONE = 0, RESTRICT_NONPOSITIVE = 1, RESTRICT_POSITIVE = 2 };
-enum { DISS_GLOBAL = 0, DISS_LOCAL = 1 };
+enum { DISS_GLOBAL = 0, DISS_LOCAL = 1, DISS_GODUNOV = 2 };
 
 /* Problem description, laid out for ctypes. */
 typedef struct {
@@ -106,7 +117,7 @@ typedef struct {
     int rk;         /* 1, 2 or 3 */
     double cfl;
     int restrict_update; /* RESTRICT_NONE, RESTRICT_NONPOSITIVE or RESTRICT_POSITIVE */
-    int dissipation;     /* DISS_GLOBAL or DISS_LOCAL */
+    int dissipation;     /* DISS_GLOBAL, DISS_LOCAL or DISS_GODUNOV */
 } hjxo_problem;
 
 /* ------------------------------------------------------------------ */
@@ -460,6 +471,22 @@ static void lf_rhs(const hjxo_problem *P, const real *hp, const real *phi, const
             x[d] = coord(P, d, idx[d]);
             pbar[d] = (pm[d][f] + pp[d][f]) / 2.0;
         }
+        if (P->dissipation == DISS_GODUNOV) { /* normal motion only (check_problem) */
+            real s = 0.0;
+            for (int d = 0; d < P->dim; ++d) {
+                real m = pm[d][f], p = pp[d][f], q;
+                if (RE(hp[0]) >= 0) {
+                    real up = RE(m) > 0 ? m : (real)0.0, dn = RE(p) < 0 ? -p : (real)0.0;
+                    q = r_max(up, dn);
+                } else {
+                    real dn = RE(m) < 0 ? -m : (real)0.0, up = RE(p) > 0 ? p : (real)0.0;
+                    q = r_max(dn, up);
+                }
+                s = s + q * q;
+            }
+            L[f] = -(hp[0] * r_sqrt(s));
+            continue;
+        }
         real hhat = ham_value(P, hp, x, pbar);
         for (int d = 0; d < P->dim; ++d) {
             real a = P->dissipation == DISS_LOCAL ? partial_bound(P, hp, x, d) : alpha[d];
@@ -587,7 +614,8 @@ static int check_problem(const hjxo_problem *P)
         return -1;
     if (P->rk < 1 || P->rk > 3) return -1;
     if (P->restrict_update < RESTRICT_NONE || P->restrict_update > RESTRICT_POSITIVE) return -1;
-    if (P->dissipation != DISS_GLOBAL && P->dissipation != DISS_LOCAL) return -1;
+    if (P->dissipation != DISS_GLOBAL && P->dissipation != DISS_LOCAL && P->dissipation != DISS_GODUNOV) return -1;
+    if (P->dissipation == DISS_GODUNOV && P->ham_kind != HAM_NORMAL) return -1;
     if (P->ham_kind == HAM_DUBINS3_PE && P->dim != 3) return -1;
     if (P->ham_kind == HAM_DUBINS4 && P->dim != 4) return -1;
     if (P->ham_kind == HAM_ROCKETS && P->dim != 3) return -1;

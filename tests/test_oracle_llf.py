@@ -102,6 +102,6 @@ def test_local_form_converges_to_the_translation_with_no_more_error():
 
 def test_unknown_dissipation_is_rejected():
     P = _p(inputs.NORMAL2D.with_(n=(5, 5)))
-    P.dissipation = 2
+    P.dissipation = 3
     with pytest.raises(ValueError):
         O.rhs(P, np.zeros((5, 5)))
