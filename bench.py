@@ -300,21 +300,22 @@ def run_batch(reps=2):
             "speedup": single_s / batch_s, "shape": {"item_nodes": shape[0], "blocks": shape[1]}}
 
 
-def run_first_order_large(n=4096, steps=2, warmup=1):
+def run_first_order_large(n=4096, steps=2, warmup=1, dissipation="global"):
     """The HBM-bound path at a size that fills the GPU: normal2d's scheme
     (FP64, first-order upwind + forward Euler, CFL 0.75, no target) on
     n x n nodes to the same horizon.  Algorithmic bytes per launch: phi read
     once and the result written once (the neighbours' re-reads are halo)."""
     from paper_2411_03501_amd import inputs
 
-    w = inputs.NORMAL2D.with_(name=f"normal2d_{n}", n=(n, n))
+    w = inputs.NORMAL2D.with_(name=f"normal2d_{n}", n=(n, n), dissipation=dissipation)
     elapsed, st, loop_ms = run_gpu(w, "f64", steps, warmup)
     launches = st["steps"] * w.rk
     kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / launches
     bytes_launch = stage_bytes_per_point(w.rk, w.with_target, 8) * w.points
     gbs = bytes_launch / kern_s / 1e9
     log(f"  {w.name}: {st['steps']} steps, {kern_s * 1e6:.1f} us per launch, {gbs:.0f} GB/s algorithmic")
-    return {"workload": f"{w.name}: {n}x{n} FP64, first-order upwind + forward Euler, {st['steps']} steps",
+    flux = "Lax-Friedrichs" if dissipation == "global" else f"{dissipation} numerical Hamiltonian"
+    return {"workload": f"{w.name}: {n}x{n} FP64, first-order upwind + forward Euler, {flux}, {st['steps']} steps",
             "updates_per_s": w.points * st["steps"] * steps / elapsed, "stage_kernel_us": kern_s * 1e6,
             "tile": st["tile"], "bytes_per_launch": bytes_launch, "hbm_alg_gbs": gbs,
             "hbm_frac": gbs / PEAK_HBM_GBS}
@@ -507,7 +508,7 @@ def main():
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
     ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube",
-                                       "rockets", "claw", "local"],
+                                       "rockets", "claw", "local", "godunov_large"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -528,6 +529,8 @@ def main():
             res = run_small()
         elif args.only == "first_order_large":
             res = run_first_order_large()
+        elif args.only == "godunov_large":
+            res = run_first_order_large(dissipation="godunov")
         elif args.only == "local":
             res = run_local(inputs.WORKLOADS[args.workload], args.dtype)
         elif args.only == "claw":
@@ -603,6 +606,9 @@ def main():
 
         log("first-order f64 at 4096^2: the HBM-bound path")
         extra["normal2d_4096_f64"] = run_first_order_large()
+
+        log("first-order f64 at 4096^2 with Godunov's numerical Hamiltonian")
+        extra["normal2d_4096_godunov_f64"] = run_first_order_large(dissipation="godunov")
 
         log("batch256 f32: batched vs per-member")
         extra["batch256"] = run_batch()

@@ -130,14 +130,21 @@ typedef struct {
     int64_t n[HJX_MAX_DIM];
 } hjx_grid_desc;
 
-/* Lax-Friedrichs dissipation ('dissFunc', Listing 4):
- *   HJX_DISS_GLOBAL  alpha_d = the grid maximum of the partial bound
- *                    (artificialDissipationGLF, Sec. IV-D);
- *   HJX_DISS_LOCAL   alpha_d = the partial bound at the node itself (the
- *                    local form, not in the paper).
- * The CFL step uses the grid maximum either way.  hjx_tape_create and
- * hjx_batch_create reject HJX_DISS_LOCAL (HJX_ERR_UNSUPPORTED). */
-typedef enum { HJX_DISS_GLOBAL = 0, HJX_DISS_LOCAL = 1 } hjx_dissipation_kind;
+/* Numerical Hamiltonian ('dissFunc', Listing 4):
+ *   HJX_DISS_GLOBAL   Lax-Friedrichs, alpha_d = the grid maximum of the
+ *                     partial bound (artificialDissipationGLF, Sec. IV-D);
+ *   HJX_DISS_LOCAL    Lax-Friedrichs, alpha_d = the partial bound at the node
+ *                     itself (the local form, not in the paper);
+ *   HJX_DISS_GODUNOV  HJX_HAM_NORMAL only: Godunov's, per axis the extremum
+ *                     of a|p| over the interval between p- and p+ (min for
+ *                     a >= 0, max for a < 0), Hhat = a sqrt(sum q_d^2), with
+ *                     q_d = max(max(p-_d, 0), -min(p+_d, 0)) for a >= 0 and
+ *                     max(-min(p-_d, 0), max(p+_d, 0)) for a < 0 (not in the
+ *                     paper).
+ * The CFL step uses the grid maximum of the partial bound in every case.
+ * hjx_tape_create and hjx_batch_create accept HJX_DISS_GLOBAL only
+ * (HJX_ERR_UNSUPPORTED). */
+typedef enum { HJX_DISS_GLOBAL = 0, HJX_DISS_LOCAL = 1, HJX_DISS_GODUNOV = 2 } hjx_dissipation_kind;
 
 typedef struct {
     int32_t kind;        /* hjx_ham_kind */

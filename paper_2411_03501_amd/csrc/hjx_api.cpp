@@ -194,8 +194,10 @@ hjx_status validate(const hjx_grid_desc *g, const hjx_ham_desc *h, const hjx_sch
     if (gst != HJX_OK) return gst;
     const int np = n_params(h->kind);
     if (np == 0) return fail(HJX_ERR_INVALID_ARG, "unknown Hamiltonian kind %d", h->kind);
-    if (h->dissipation != HJX_DISS_GLOBAL && h->dissipation != HJX_DISS_LOCAL)
+    if (h->dissipation != HJX_DISS_GLOBAL && h->dissipation != HJX_DISS_LOCAL && h->dissipation != HJX_DISS_GODUNOV)
         return fail(HJX_ERR_INVALID_ARG, "unknown dissipation %d", h->dissipation);
+    if (h->dissipation == HJX_DISS_GODUNOV && h->kind != HJX_HAM_NORMAL)
+        return fail(HJX_ERR_INVALID_ARG, "the Godunov Hamiltonian is built for NORMAL only");
     for (int k = 0; k < np; ++k)
         if (!std::isfinite(h->p[k])) return fail(HJX_ERR_INVALID_ARG, "Hamiltonian parameter %d is not finite", k);
     if (h->kind == HJX_HAM_DUBINS3_PE) {
@@ -273,7 +275,7 @@ StageArgs<T> stage_args(const hjx_problem *p, const double *alpha)
         a.alpha[d] = d < p->grid.dim ? T(alpha[d]) : T(0);
     }
     for (int k = 0; k < 8; ++k) a.hp[k] = T(p->ham.p[k]);
-    a.local = p->ham.dissipation == HJX_DISS_LOCAL;
+    a.diss = p->ham.dissipation;
     a.clip = p->scheme.restrict_update == HJX_RESTRICT_NONPOSITIVE ? -1
              : p->scheme.restrict_update == HJX_RESTRICT_POSITIVE  ? 1
                                                                    : 0;
@@ -883,7 +885,7 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     if (p->ham.kind == HJX_HAM_ROCKETS)
         return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the ROCKETS Hamiltonian is not implemented");
     if (p->ham.dissipation != HJX_DISS_GLOBAL)
-        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the local dissipation is not implemented");
+        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the local dissipation or Godunov is not implemented");
     hjx_tape *t = new (std::nothrow) hjx_tape;
     if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
     t->p = p;
@@ -1560,7 +1562,7 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
         if (p->ham.kind == HJX_HAM_ROCKETS)
             return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: the batch kernel has no ROCKETS Hamiltonian", i);
         if (p->ham.dissipation != HJX_DISS_GLOBAL)
-            return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: the batch kernel has no local dissipation", i);
+            return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: the batch kernel has no local dissipation or Godunov", i);
     }
     {
         const size_t need = (p0->scheme.dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>)) *

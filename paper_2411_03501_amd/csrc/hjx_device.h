@@ -378,7 +378,7 @@ enum : int { kNodePlain = 0, kNodeKeep = 1, kNodeClip = 2, kNodeLocal = 4 };
 template <typename T, int D, int HAM>
 __device__ __forceinline__ T node_bound(const StageArgs<T> &a, const int *j, int d)
 {
-    if constexpr (HAM == kHamNormal) {
+    if constexpr (HAM == kHamNormal || HAM == kHamNormalGodunov) {
         return vabs(a.hp[0]);
     } else if constexpr (HAM == kHamDubins3) {
         const T ve = a.hp[0], vp = a.hp[1], we = a.hp[2], wp = a.hp[3];
@@ -413,12 +413,32 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
     T pbar[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (pm[d] + pp[d]);
-    T hhat = ham_value<T, D, HAM>(a, j, pbar);
+    T hhat;
+    if constexpr (HAM == kHamNormalGodunov) {
+        // Godunov for a|p|: per axis the extremum of |p| over the interval
+        // between p- and p+ (the minimum for a >= 0, the maximum for a < 0)
+        T s = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        T al = a.alpha[d];
-        if constexpr ((MODE & kNodeLocal) != 0) al = node_bound<T, D, HAM>(a, j, d);
-        hhat = fmaT(-al, T(0.5) * (pp[d] - pm[d]), hhat);
+        for (int d = 0; d < D; ++d) {
+            T q;
+            if (a.hp[0] >= T(0)) {
+                const T up = pm[d] > T(0) ? pm[d] : T(0), dn = pp[d] < T(0) ? -pp[d] : T(0);
+                q = dn > up ? dn : up;
+            } else {
+                const T dn = pm[d] < T(0) ? -pm[d] : T(0), up = pp[d] > T(0) ? pp[d] : T(0);
+                q = up > dn ? up : dn;
+            }
+            s = fmaT(q, q, s);
+        }
+        hhat = a.hp[0] * sqrt(s);
+    } else {
+        hhat = ham_value<T, D, HAM>(a, j, pbar);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            T al = a.alpha[d];
+            if constexpr ((MODE & kNodeLocal) != 0) al = node_bound<T, D, HAM>(a, j, d);
+            hhat = fmaT(-al, T(0.5) * (pp[d] - pm[d]), hhat);
+        }
     }
     T L = -hhat;
     if (a.rhs_only) return L;

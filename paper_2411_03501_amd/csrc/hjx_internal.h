@@ -63,7 +63,7 @@ struct StageArgs {
     T dt, ca, cb;
     int rhs_only;
     int clip;  // restricted update: 0 none, -1 L <- min(L, 0), +1 L <- max(L, 0) (not with rhs_only)
-    int local; // local Lax-Friedrichs: alpha_d at the node instead of alpha[d]
+    int diss;  // 0: Lax-Friedrichs with alpha[d]; 1: with alpha_d at the node; 2: Godunov (normal motion)
     Tile tile;
     unsigned char *mask;  // nullable: 1 where the target was the smaller (replay for the adjoint)
     T *dp_out;            // nullable: p-_d at dp_out + 2d dp_stride, p+_d at dp_out + (2d+1) dp_stride
@@ -244,6 +244,9 @@ inline size_t stage_lds_bytes(const Tile &t, size_t elem)
 
 enum : int { kSchemeFirst = 1, kSchemeEno2 = 2, kSchemeEno3 = 3, kSchemeWeno5 = 5 };
 enum : int { kHamNormal = 0, kHamDubins3 = 1, kHamDubins4 = 2, kHamRockets = 3 };
+// normal motion with Godunov's numerical Hamiltonian instead of Lax-Friedrichs
+// (a template tag of the stage kernels, chosen by StageArgs::diss)
+enum : int { kHamNormalGodunov = 4 };
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_stage_f32(const StageArgs<float> &a, int scheme, int ham, hipStream_t s);

@@ -470,7 +470,12 @@ template <typename T, int D, int SCHEME, int HAM>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
     const int mode = (a.dp_out ? kNodeKeep : 0) | (!a.rhs_only && a.clip != 0 ? kNodeClip : 0) |
-                     (a.local ? kNodeLocal : 0);
+                     (a.diss == 1 ? kNodeLocal : 0);
+    if constexpr (HAM == kHamNormalGodunov) {  // no alpha, so no local form; no adjoint
+        if (mode == kNodePlain) return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
+        if (mode == kNodeClip) return launch_mode<T, D, SCHEME, HAM, kNodeClip>(a, s);
+        return hipErrorInvalidValue;
+    }
     switch (mode) {
     case kNodePlain: return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
     case kNodeKeep: return launch_mode<T, D, SCHEME, HAM, kNodeKeep>(a, s);
@@ -507,6 +512,15 @@ hipError_t launch_stage(const StageArgs<T> &a, int scheme, int ham, hipStream_t 
     if (ham == kHamRockets) {
         if (a.g.dim != 3) return hipErrorInvalidValue;
         return launch_scheme<T, 3, kHamRockets>(a, scheme, s);
+    }
+    if (a.diss == 2) {  // Godunov's numerical Hamiltonian for normal motion
+        switch (a.g.dim) {
+        case 1: return launch_scheme<T, 1, kHamNormalGodunov>(a, scheme, s);
+        case 2: return launch_scheme<T, 2, kHamNormalGodunov>(a, scheme, s);
+        case 3: return launch_scheme<T, 3, kHamNormalGodunov>(a, scheme, s);
+        case 4: return launch_scheme<T, 4, kHamNormalGodunov>(a, scheme, s);
+        }
+        return hipErrorInvalidValue;
     }
     switch (a.g.dim) {
     case 1: return launch_scheme<T, 1, kHamNormal>(a, scheme, s);

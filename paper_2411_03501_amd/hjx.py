@@ -20,7 +20,7 @@ DERIV = {"first": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 FLUX = {"linear": 0, "burgers": 1}
-DISSIPATION = {"global": 0, "local": 1}
+DISSIPATION = {"global": 0, "local": 1, "godunov": 2}
 MAX_DIM = 4
 
 

@@ -69,7 +69,8 @@ def _create(**kw):
     (dict(cfl=0.0), "cfl"),
     (dict(cfl=1.5), "cfl"),
     (dict(restrict=3), "restrict_update"),
-    (dict(dissipation=2), "unknown dissipation"),
+    (dict(dissipation=3), "unknown dissipation"),
+    (dict(gmin=[0] * 3, gmax=[1] * 3, n=[5] * 3, ham="dubins3_pe", params=[1, 1, 1, 1], dissipation=2), "Godunov"),
     (dict(ham="rockets", params=[1, 32, 1, 1]), "ROCKETS needs dim 3"),
     (dict(gmin=[0] * 3, gmax=[1] * 3, n=[5] * 3, ham="rockets", params=[1, 32, -1, 1]), "control bounds"),
     (dict(restrict=-1), "restrict_update"),
