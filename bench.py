@@ -406,6 +406,48 @@ def run_claw(steps=400, warmup=20):
             "bytes_per_step": bytes_step, "hbm_alg_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
 
 
+def run_shapes():
+    """Initial data of the 256-member batch (a sphere or a cylinder per
+    member, 186.9 M nodes, FP32) built on the device by hjx_shape, against
+    the host recipe that the batched benchmark otherwise uses."""
+    import torch
+
+    from paper_2411_03501_amd import hjx, inputs
+
+    ws = inputs.batch256()
+    outs = [torch.empty(w.n, dtype=torch.float32, device="cuda") for w in ws]
+    specs = [dict(gmin=w.gmin, gmax=w.gmax, n=w.n, periodic=w.periodic, radius=w.radius,
+                  axes=None if w.surface == "sphere" else (0, 1)) for w in ws]
+
+    def per_member():
+        for sp, o in zip(specs, outs):
+            hjx.shape(dtype="f32", out=o, **sp)
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    one_ms = timed(per_member)
+    dev_ms = timed(lambda: hjx.shape_batch(specs, dtype="f32", outs=outs))
+    t0 = time.perf_counter()
+    for w in ws[:32]:
+        inputs.initial_surface(w)
+    host_ms = (time.perf_counter() - t0) * 1e3 * len(ws) / 32
+    nodes = sum(w.points for w in ws)
+    log(f"  batch256 initial data: one launch {dev_ms:.2f} ms, a launch per member {one_ms:.2f} ms, "
+        f"host recipe about {host_ms:.0f} ms")
+    return {"workload": f"initial data of batch256: {len(ws)} spheres and cylinders, {nodes / 1e6:.1f} M nodes, FP32",
+            "device_ms": dev_ms, "per_member_launches_ms": one_ms, "host_recipe_ms_est": host_ms,
+            "write_gbs": nodes * 4 / dev_ms / 1e6, "hbm_frac": nodes * 4 / dev_ms / 1e6 / PEAK_HBM_GBS,
+            "host_sample": "the host recipe (float64 numpy) timed on the first 32 members, scaled to 256"}
+
+
 def run_small(reps=20):
     """The launch-bound workload: normal2d (101^2, FP64, first-order upwind +
     forward Euler, 40 steps).  Per solve: hjx_solve (host-driven launches,
@@ -508,7 +550,7 @@ def main():
                     help="variant,tx,ty,march of the stage kernel instead of the autotuner's choice "
                          "(counter runs: the tuner's timings are distorted under counter collection)")
     ap.add_argument("--only", choices=["batch256", "adjoint", "copy", "normal2d", "first_order_large", "tube",
-                                       "rockets", "claw", "local", "godunov_large"],
+                                       "rockets", "claw", "local", "godunov_large", "shapes"],
                     help="run one secondary measurement alone and print its JSON (for profiling); "
                          "copy: a plain 1 GiB device copy, the reference for HBM counter calibration")
     args = ap.parse_args()
@@ -529,6 +571,8 @@ def main():
             res = run_small()
         elif args.only == "first_order_large":
             res = run_first_order_large()
+        elif args.only == "shapes":
+            res = run_shapes()
         elif args.only == "godunov_large":
             res = run_first_order_large(dissipation="godunov")
         elif args.only == "local":
@@ -609,6 +653,9 @@ def main():
 
         log("first-order f64 at 4096^2 with Godunov's numerical Hamiltonian")
         extra["normal2d_4096_godunov_f64"] = run_first_order_large(dissipation="godunov")
+
+        log("batch256 initial data on the device")
+        extra["batch256_initial_data"] = run_shapes()
 
         log("batch256 f32: batched vs per-member")
         extra["batch256"] = run_batch()

@@ -366,6 +366,50 @@ hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *con
                           const double *t1, int32_t reps, void *stream, double *best_ms);
 
 /* ------------------------------------------------------------------
+ * Implicit surfaces and shape operations (Sec. III: implicit surface
+ * representations, Listing 2, and the calculus on implicit functions), built
+ * on the device.  Arrays are device memory of the grid's size (row-major,
+ * last axis fastest) in the given dtype.                                   */
+typedef enum {
+    HJX_SHAPE_BALL = 0,      /* sqrt(sum_{d in mask} (x_d - c_d)^2) - r: the signed distance to a
+                                sphere (every axis in mask) or a cylinder (some axes) */
+    HJX_SHAPE_ELLIPSOID = 1  /* sum_{d in mask} w_d (x_d - c_d)^2 - r: Listing 2's form (not a distance) */
+} hjx_shape_kind;
+
+typedef struct {
+    int32_t kind;            /* hjx_shape_kind */
+    uint32_t axis_mask;      /* bit d: axis d takes part (at least one axis, none beyond dim) */
+    double center[HJX_MAX_DIM];
+    double weights[HJX_MAX_DIM]; /* ELLIPSOID only; finite */
+    double radius;
+} hjx_shape_desc;
+
+/* phi_out[node] = the shape at the node's coordinates (gmin_d + j dx_d, the
+ * grid of hjx_grid_desc), evaluated in double and rounded once to dtype.
+ * Asynchronous on `stream`. */
+hjx_status hjx_shape(const hjx_grid_desc *grid, const hjx_shape_desc *shape, int32_t dtype, void *phi_out,
+                     void *stream);
+
+/* The shapes of 1 <= n <= 65535 grids in one launch (initial data of a batch):
+ * phi_out[k] = shapes[k] on grids[k], as hjx_shape would write it.  grids,
+ * shapes, phi_out: host arrays of n entries; each phi_out[k] a device array
+ * of grids[k]'s size.  Copies the n descriptors to a temporary device array
+ * and synchronises `stream`. */
+hjx_status hjx_shape_batch(int32_t n, const hjx_grid_desc *grids, const hjx_shape_desc *shapes, int32_t dtype,
+                           void *const *phi_out, void *stream);
+
+typedef enum {
+    HJX_OP_UNION = 0,        /* min(a, b) */
+    HJX_OP_INTERSECTION = 1, /* max(a, b) */
+    HJX_OP_COMPLEMENT = 2,   /* -a (b unused, may be NULL) */
+    HJX_OP_SUBTRACTION = 3   /* max(a, -b): the interior of a without that of b */
+} hjx_shape_op_kind;
+
+/* out[i] = op(a[i], b[i]) for 0 <= i < n, elementwise; out may alias a or b.
+ * Asynchronous on `stream`. */
+hjx_status hjx_shape_op(int32_t op, int32_t dtype, const void *a, const void *b, void *out, int64_t n, void *stream);
+
+/* ------------------------------------------------------------------
  * Scalar conservation laws (Sec. IV-D): v_t + sum_d f_d(v)_{x_d} = 0 by the
  * Lax-Friedrichs scheme.  The paper prints it in one dimension,
  *   v_j' = v_j - (lambda/2)(f(v_{j+1}) - f(v_{j-1})) + (v_{j+1} - 2 v_j + v_{j-1})/2,

@@ -1964,3 +1964,105 @@ hjx_status hjx_claw_solve(hjx_claw *h, const void *v0, void *v_out, double t1, v
 }
 
 }  // extern "C"
+
+// ==================================================================== shapes
+
+namespace {
+
+// validate one shape on one grid and fill its kernel arguments
+hjx_status shape_args(const hjx_grid_desc *grid, const hjx_shape_desc *shape, ShapeArgs *out)
+{
+    hjx_status st = validate_grid(grid);
+    if (st != HJX_OK) return st;
+    if (shape->kind != HJX_SHAPE_BALL && shape->kind != HJX_SHAPE_ELLIPSOID)
+        return fail(HJX_ERR_INVALID_ARG, "unknown shape kind %d", shape->kind);
+    if (shape->axis_mask == 0 || (shape->axis_mask >> grid->dim))
+        return fail(HJX_ERR_INVALID_ARG, "axis_mask 0x%x names no axis or an axis >= dim %d", shape->axis_mask,
+                    grid->dim);
+    if (!std::isfinite(shape->radius)) return fail(HJX_ERR_INVALID_ARG, "radius is not finite");
+    ShapeArgs a{};
+    a.dim = grid->dim;
+    a.kind = shape->kind;
+    a.mask = shape->axis_mask;
+    a.total = 1;
+    for (int d = 0; d < grid->dim; ++d) {
+        if (!std::isfinite(shape->center[d]) || (shape->kind == HJX_SHAPE_ELLIPSOID && !std::isfinite(shape->weights[d])))
+            return fail(HJX_ERR_INVALID_ARG, "center or weight %d is not finite", d);
+        a.n[d] = (int)grid->n[d];
+        a.total *= a.n[d];
+        const double len = grid->gmax[d] - grid->gmin[d];
+        a.gmin[d] = grid->gmin[d];
+        a.dx[d] = ((grid->periodic_mask >> d) & 1u) ? len / (double)grid->n[d] : len / (double)(grid->n[d] - 1);
+        a.center[d] = shape->center[d];
+        a.weights[d] = shape->weights[d];
+    }
+    a.radius = shape->radius;
+    a.rows = (int)(a.total / a.n[grid->dim - 1]);
+    *out = a;
+    return HJX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjx_status hjx_shape(const hjx_grid_desc *grid, const hjx_shape_desc *shape, int32_t dtype, void *phi_out,
+                     void *stream)
+{
+    if (!grid || !shape || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != HJX_F32 && dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    ShapeArgs a{};
+    hjx_status st = shape_args(grid, shape, &a);
+    if (st != HJX_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == HJX_F32) HIP_TRY(launch_shape_f32(a, static_cast<float *>(phi_out), s));
+    else HIP_TRY(launch_shape_f64(a, static_cast<double *>(phi_out), s));
+    return ok();
+}
+
+hjx_status hjx_shape_batch(int32_t n, const hjx_grid_desc *grids, const hjx_shape_desc *shapes, int32_t dtype,
+                           void *const *phi_out, void *stream)
+{
+    if (n < 1 || n > 65535 || !grids || !shapes || !phi_out)
+        return fail(HJX_ERR_INVALID_ARG, "need 1 <= n <= 65535 and no NULL array");
+    if (dtype != HJX_F32 && dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    std::vector<ShapeMember> host((size_t)n);
+    long largest = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!phi_out[k]) return fail(HJX_ERR_INVALID_ARG, "phi_out[%d] is NULL", k);
+        hjx_status st = shape_args(&grids[k], &shapes[k], &host[k].a);
+        if (st != HJX_OK) return fail(st, "member %d: %s", k, hjx_last_error());
+        host[k].out = phi_out[k];
+        largest = std::max(largest, host[k].a.total);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ShapeMember *dev = nullptr;
+    HIP_TRY(hipMalloc(&dev, host.size() * sizeof(ShapeMember)));
+    hipError_t e = hipMemcpyAsync(dev, host.data(), host.size() * sizeof(ShapeMember), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = dtype == HJX_F32 ? launch_shape_batch_f32(dev, n, largest, s) : launch_shape_batch_f64(dev, n, largest, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return fail(HJX_ERR_DEVICE, "hjx_shape_batch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+hjx_status hjx_shape_op(int32_t op, int32_t dtype, const void *a, const void *b, void *out, int64_t n, void *stream)
+{
+    if (op < HJX_OP_UNION || op > HJX_OP_SUBTRACTION) return fail(HJX_ERR_INVALID_ARG, "unknown shape op %d", op);
+    if (!a || !out || (op != HJX_OP_COMPLEMENT && !b)) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != HJX_F32 && dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if (n < 0) return fail(HJX_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0) return ok();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (op == HJX_OP_COMPLEMENT) b = a;  // unused by the kernel
+    if (dtype == HJX_F32)
+        HIP_TRY(launch_shape_op_f32(op, static_cast<const float *>(a), static_cast<const float *>(b),
+                                    static_cast<float *>(out), (long)n, s));
+    else
+        HIP_TRY(launch_shape_op_f64(op, static_cast<const double *>(a), static_cast<const double *>(b),
+                                    static_cast<double *>(out), (long)n, s));
+    return ok();
+}
+
+}  // extern "C"

@@ -288,6 +288,36 @@ hipError_t launch_claw_f64(const ClawArgs<double> &a, int flux, hipStream_t s);
 hipError_t launch_maxabs_f32(const float *v, int n, unsigned long long *out, hipStream_t s);
 hipError_t launch_maxabs_f64(const double *v, int n, unsigned long long *out, hipStream_t s);
 
+// ---------------------------------------------------------------- shapes
+// An implicit surface over a grid (hjx_shapes.hip).
+enum : int { kShapeBall = 0, kShapeEllipsoid = 1 };
+enum : int { kOpUnion = 0, kOpIntersection = 1, kOpComplement = 2, kOpSubtraction = 3 };
+
+struct ShapeArgs {
+    int dim, kind;
+    unsigned mask;      // bit d: axis d takes part
+    int n[kMaxDim];
+    int rows;           // nodes / n[dim - 1]
+    long total;
+    double gmin[kMaxDim], dx[kMaxDim];
+    double center[kMaxDim], weights[kMaxDim];
+    double radius;
+};
+
+// One member of a batched construction: its shape and output.
+struct ShapeMember {
+    ShapeArgs a;
+    void *out;
+};
+
+hipError_t launch_shape_f32(const ShapeArgs &a, float *out, hipStream_t s);
+// members: device array of nm (<= 65535) members; largest: the most nodes of one member
+hipError_t launch_shape_batch_f32(const ShapeMember *members, int nm, long largest, hipStream_t s);
+hipError_t launch_shape_batch_f64(const ShapeMember *members, int nm, long largest, hipStream_t s);
+hipError_t launch_shape_f64(const ShapeArgs &a, double *out, hipStream_t s);
+hipError_t launch_shape_op_f32(int op, const float *a, const float *b, float *out, long n, hipStream_t s);
+hipError_t launch_shape_op_f64(int op, const double *a, const double *b, double *out, long n, hipStream_t s);
+
 // plain element copy (used where a stage result must land in another buffer)
 hipError_t launch_copy_f32(const float *src, float *dst, int n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int n, hipStream_t s);

@@ -21,6 +21,8 @@ HAM = {"normal": 0, "dubins3_pe": 1, "dubins4": 2, "rockets": 3}
 RESTRICT = {"none": 0, "nonpositive": 1, "positive": 2}
 FLUX = {"linear": 0, "burgers": 1}
 DISSIPATION = {"global": 0, "local": 1, "godunov": 2}
+SHAPES = {"ball": 0, "ellipsoid": 1}
+SHAPE_OPS = {"union": 0, "intersection": 1, "complement": 2, "subtraction": 3}
 MAX_DIM = 4
 
 
@@ -37,6 +39,11 @@ class HamDesc(ctypes.Structure):
 class SchemeDesc(ctypes.Structure):
     _fields_ = [("deriv", ctypes.c_int32), ("rk", ctypes.c_int32), ("cfl", ctypes.c_double),
                 ("dtype", ctypes.c_int32), ("restrict_update", ctypes.c_int32)]
+
+
+class ShapeDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("axis_mask", ctypes.c_uint32), ("center", ctypes.c_double * 4),
+                ("weights", ctypes.c_double * 4), ("radius", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -90,6 +97,10 @@ SIGNATURES = {
     "hjx_batch_tune": ([_P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P,
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hjx_shape": ([ctypes.POINTER(GridDesc), ctypes.POINTER(ShapeDesc), ctypes.c_int32, _P, _P], ctypes.c_int),
+    "hjx_shape_op": ([ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_int64, _P], ctypes.c_int),
+    "hjx_shape_batch": ([ctypes.c_int32, ctypes.POINTER(GridDesc), ctypes.POINTER(ShapeDesc), ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_void_p), _P], ctypes.c_int),
     "hjx_claw_create": ([ctypes.POINTER(GridDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                          ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hjx_claw_destroy": ([_P], ctypes.c_int),
@@ -498,6 +509,79 @@ class Batch:
         p0, tg, po, out = self._args(phi0, target, out)
         ms = hjx_batch_tune(self.handle, p0, tg, po, t1, reps, stream)
         return self.shape, ms
+
+
+# ------------------------------------------------------------------ shapes
+
+def hjx_shape(grid, desc, dtype, out_ptr, stream=None):
+    _check(lib().hjx_shape(ctypes.byref(grid), ctypes.byref(desc), int(dtype), out_ptr, _stream(stream)))
+
+
+def hjx_shape_op(op, dtype, a_ptr, b_ptr, out_ptr, n, stream=None):
+    _check(lib().hjx_shape_op(int(op), int(dtype), a_ptr, b_ptr, out_ptr, int(n), _stream(stream)))
+
+
+def shape(gmin, gmax, n, kind="ball", axes=None, center=None, radius=1.0, weights=None, periodic=(), dtype="f64",
+          out=None, stream=None):
+    """An implicit surface on the grid (hjx_shape): kind "ball" (sphere over
+    every axis in `axes`, cylinder over some) or "ellipsoid" (Listing 2)."""
+    g, _, _ = descriptors(gmin, gmax, n, periodic)
+    d = _shape_desc(len(n), kind, axes, center, radius, weights)
+    tdt = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
+    if out is None:
+        out = torch.empty(tuple(int(v) for v in n), dtype=tdt, device="cuda")
+    numel = 1
+    for v in n:
+        numel *= int(v)
+    hjx_shape(g, d, HJX_F32 if tdt == torch.float32 else HJX_F64, _dev(out, tdt, numel, "phi_out"), stream)
+    return out
+
+
+def _shape_desc(ndim, kind, axes, center, radius, weights):
+    d = ShapeDesc()
+    d.kind = SHAPES[kind] if isinstance(kind, str) else int(kind)
+    d.axis_mask = sum(1 << a for a in (range(ndim) if axes is None else axes))
+    for k in range(ndim):
+        d.center[k] = float(center[k]) if center is not None else 0.0
+        d.weights[k] = float(weights[k]) if weights is not None else 1.0
+    d.radius = float(radius)
+    return d
+
+
+def shape_batch(specs, dtype="f64", outs=None, stream=None):
+    """Shapes of many grids in one launch (hjx_shape_batch).  specs: dicts
+    with gmin, gmax, n and optional periodic, kind, axes, center, radius,
+    weights (as for shape()).  Returns the list of output tensors."""
+    tdt = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
+    k = len(specs)
+    grids = (GridDesc * k)()
+    descs = (ShapeDesc * k)()
+    if outs is None:
+        outs = [torch.empty(tuple(int(v) for v in sp["n"]), dtype=tdt, device="cuda") for sp in specs]
+    ptrs = (ctypes.c_void_p * k)()
+    for i, sp in enumerate(specs):
+        g, _, _ = descriptors(sp["gmin"], sp["gmax"], sp["n"], sp.get("periodic", ()))
+        grids[i] = g
+        descs[i] = _shape_desc(len(sp["n"]), sp.get("kind", "ball"), sp.get("axes"), sp.get("center"),
+                               sp.get("radius", 1.0), sp.get("weights"))
+        numel = 1
+        for v in sp["n"]:
+            numel *= int(v)
+        ptrs[i] = _dev(outs[i], tdt, numel, f"outs[{i}]")
+    _check(lib().hjx_shape_batch(k, grids, descs, HJX_F32 if tdt == torch.float32 else HJX_F64, ptrs,
+                                 _stream(stream)))
+    return outs
+
+
+def shape_op(op, a, b=None, out=None, stream=None):
+    """Union min(a, b), intersection max(a, b), complement -a or subtraction
+    max(a, -b), elementwise on the device (hjx_shape_op)."""
+    if out is None:
+        out = torch.empty_like(a)
+    dt = HJX_F32 if a.dtype == torch.float32 else HJX_F64
+    hjx_shape_op(SHAPE_OPS[op] if isinstance(op, str) else int(op), dt, _dev(a, a.dtype, a.numel(), "a"),
+                 _dev(b, a.dtype, a.numel(), "b"), _dev(out, a.dtype, a.numel(), "out"), a.numel(), stream)
+    return out
 
 
 # ------------------------------------------------------------------ conservation laws

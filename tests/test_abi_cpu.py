@@ -151,3 +151,16 @@ def test_claw_null_arguments():
     assert L.hjx_claw_solve(None, None, None, 1.0, None, None, None) == hjx.HJX_ERR_INVALID_ARG
     assert L.hjx_claw_dt(None, None, None, None) == hjx.HJX_ERR_INVALID_ARG
     assert L.hjx_claw_destroy(None) == hjx.HJX_OK
+
+
+def test_shape_rejects_bad_arguments_before_the_device():
+    g, _, _ = hjx.descriptors([0, 0], [1, 1], [5, 5])
+    d = hjx.ShapeDesc()
+    d.kind, d.axis_mask, d.radius = 0, 0, 0.5
+    with pytest.raises(hjx.HjxError, match="axis_mask"):
+        hjx.hjx_shape(g, d, hjx.HJX_F64, ctypes.c_void_p(8), stream=0)
+    d.axis_mask, d.radius = 0b11, math.inf
+    with pytest.raises(hjx.HjxError, match="radius"):
+        hjx.hjx_shape(g, d, hjx.HJX_F64, ctypes.c_void_p(8), stream=0)
+    with pytest.raises(hjx.HjxError, match="n = -1"):
+        hjx.hjx_shape_op(0, hjx.HJX_F64, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), -1, stream=0)
