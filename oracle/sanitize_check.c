@@ -4,8 +4,10 @@
  * gcc on the host; nothing else uses it).  The real build of hjxo.c is
  * compiled into this file; the complex-step build is linked beside it.
  * Every Hamiltonian, derivative scheme and RK order takes a few steps on
- * tiny grids (n = 3 to 9, periodic and not), and the complex-step loss runs
- * once; any invalid access or undefined operation aborts the program.
+ * tiny grids (n = 3 to 9, periodic and not), with the restricted updates and
+ * the local, Godunov and global dissipations, and the complex-step loss runs
+ * once; the conservation-law scheme steps every dimension and flux; any
+ * invalid access or undefined operation aborts the program.
  */
 #include "hjxo.c"
 
@@ -15,7 +17,8 @@ long hjxo_cs_solve_loss(const hjxo_problem *P, const double *phi0, const double 
                         int with_target, double t0, double t1, double eps_h, double h, double *loss,
                         double *dloss, double *phi_T_re, double *phi_T_tan);
 
-static int run(int dim, const long *n, unsigned per, int ham, int scheme, int rk)
+static int run_opts(int dim, const long *n, unsigned per, int ham, int scheme, int rk, int restrict_update,
+                    int dissipation)
 {
     hjxo_problem P;
     memset(&P, 0, sizeof P);
@@ -30,6 +33,9 @@ static int run(int dim, const long *n, unsigned per, int ham, int scheme, int rk
     if (ham == 0) P.hp[0] = 1.0;
     if (ham == 1) { P.hp[0] = 1.0; P.hp[1] = 1.2; P.hp[2] = 0.5; P.hp[3] = 0.7; }
     if (ham == 2) { P.hp[0] = 1.0; P.hp[1] = 0.8; }
+    if (ham == 3) { P.hp[0] = 1.0; P.hp[1] = 3.0; P.hp[2] = 0.5; P.hp[3] = 0.7; }
+    P.restrict_update = restrict_update;
+    P.dissipation = dissipation;
     P.scheme = scheme;
     P.rk = rk;
     P.cfl = 0.75;
@@ -51,7 +57,42 @@ static int run(int dim, const long *n, unsigned per, int ham, int scheme, int rk
     if (!bad && hjxo_cs_solve_loss(&P, phi, dphi, dhp, 1, 0.0, t1, 0.3, 1e-20, &L, &dL, NULL, NULL) < 0) bad = 1;
     if (!bad && !(isfinite(L) && isfinite(dL))) bad = 1;
     free(phi); free(tg); free(out); free(dphi);
-    if (bad) fprintf(stderr, "failed: dim %d ham %d scheme %d rk %d\n", dim, ham, scheme, rk);
+    if (bad)
+        fprintf(stderr, "failed: dim %d ham %d scheme %d rk %d restrict %d dissipation %d\n", dim, ham, scheme, rk,
+                restrict_update, dissipation);
+    return bad;
+}
+
+static int run(int dim, const long *n, unsigned per, int ham, int scheme, int rk)
+{
+    return run_opts(dim, n, per, ham, scheme, rk, 0, 0);
+}
+
+/* a few Lax-Friedrichs steps of a conservation law on a tiny grid */
+static int run_claw(int dim, const long *n, unsigned per, int flux)
+{
+    hjxo_claw C;
+    memset(&C, 0, sizeof C);
+    C.dim = dim;
+    for (int d = 0; d < dim; ++d) {
+        C.gmin[d] = -1.0;
+        C.gmax[d] = 1.0 + 0.5 * d;
+        C.n[d] = n[d];
+        C.c[d] = d % 2 ? -0.7 : 1.1;
+    }
+    C.periodic_mask = per;
+    C.flux = flux;
+    C.cfl = 0.9;
+    long total = 1;
+    for (int d = 0; d < dim; ++d) total *= n[d];
+    double *v = malloc(sizeof(double) * total), *out = malloc(sizeof(double) * total);
+    for (long f = 0; f < total; ++f) v[f] = sin(0.9 * f) + 0.2;
+    double dt = 0.0;
+    long steps = hjxo_claw_solve(&C, v, 4.5 * hjxo_claw_dt(&C, v), out, &dt);
+    int bad = steps != 5;
+    for (long f = 0; f < total && !bad; ++f) bad = !isfinite(out[f]);
+    free(v); free(out);
+    if (bad) fprintf(stderr, "failed: claw dim %d flux %d\n", dim, flux);
     return bad;
 }
 
@@ -67,7 +108,20 @@ int main(void)
             bad |= run(2, n2, 0u, 0, schemes[s], rk);
             bad |= run(3, n3, 4u, 1, schemes[s], rk);
             bad |= run(4, n4, 4u, 2, schemes[s], rk);
+            bad |= run(3, n3, 0u, 3, schemes[s], rk);
+            for (int r = 1; r <= 2; ++r) bad |= run_opts(2, n2, 1u, 0, schemes[s], rk, r, 0);
+            bad |= run_opts(3, n3, 4u, 1, schemes[s], rk, 0, 1);
+            bad |= run_opts(3, n3, 0u, 3, schemes[s], rk, 2, 1);
+            bad |= run_opts(2, n2, 2u, 0, schemes[s], rk, 0, 2);
+            bad |= run_opts(1, n1, 0u, 0, schemes[s], rk, 1, 2);
         }
+    for (int flux = 0; flux <= 1; ++flux) {
+        const long c1[1] = {3}, c2[2] = {4, 7}, c3[3] = {3, 5, 4}, c4[4] = {3, 3, 4, 5};
+        bad |= run_claw(1, c1, 1u, flux);
+        bad |= run_claw(2, c2, 0u, flux);
+        bad |= run_claw(3, c3, 5u, flux);
+        bad |= run_claw(4, c4, 15u, flux);
+    }
     for (int s = 0; s < 4; ++s)
         for (long n = 3; n <= 9; ++n)
             for (int per = 0; per <= 1; ++per) {
