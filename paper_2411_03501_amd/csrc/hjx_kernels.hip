@@ -241,13 +241,15 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 // keep enough waves in flight.
 // Whether the direct kernel gives each thread two neighbouring planes of
 // axis 0 (direct_pair) instead of one node: in 2-D and 3-D, for FP64 (fewer
-// quarter-rate reciprocals outweigh the registers) and for first order in
-// either precision (fewer loads per node; few registers anyway).  FP32 WENO
-// and ENO keep one node per thread: pairs cost them occupancy.
+// quarter-rate reciprocals outweigh the registers) and, in FP32, for every
+// scheme but WENO5 (fewer loads and shared axis-0 windows at 60 VGPRs,
+// still 8 waves: ENO2 9.67 -> 8.76 us and ENO3 12.09 -> 11.33 us per stage
+// on dubins3d 101^3).  FP32 WENO5 keeps one node per thread: pairs cost it
+// occupancy.
 template <typename T, int D, int SCHEME>
 constexpr bool direct_pairs()
 {
-    return (D == 2 || D == 3) && (sizeof(T) == 8 || SCHEME == kSchemeFirst);
+    return (D == 2 || D == 3) && (sizeof(T) == 8 || SCHEME != kSchemeWeno5);
 }
 
 // With pairs, 2-D: thread q takes rows 2 (q / n1) and 2 (q / n1) + 1 of
