@@ -40,12 +40,15 @@ class Problem(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("restrict_update", ctypes.c_int),
         ("dissipation", ctypes.c_int),
+        ("decide_f32", ctypes.c_int),
     ]
 
 
 def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme="weno5", rk=3,
-                 cfl=0.75, restrict="none", dissipation="global"):
-    """Build an oracle problem.  `periodic` lists periodic axes."""
+                 cfl=0.75, restrict="none", dissipation="global", decide="f64"):
+    """Build an oracle problem.  `periodic` lists periodic axes.  `decide`
+    is the precision of the ENO stencil choices ("f64", or "f32" for the
+    binary32 choices of eno_choice in hjxo.c); the arithmetic is FP64."""
     P = Problem()
     P.dim = len(n)
     for d in range(len(n)):
@@ -61,6 +64,7 @@ def make_problem(gmin, gmax, n, periodic=(), ham="normal", params=(1.0,), scheme
     P.cfl = float(cfl)
     P.restrict_update = RESTRICT[restrict] if isinstance(restrict, str) else int(restrict)
     P.dissipation = DISSIPATION[dissipation] if isinstance(dissipation, str) else int(dissipation)
+    P.decide_f32 = {"f64": 0, "f32": 1}[decide]
     return P
 
 
@@ -122,6 +126,8 @@ def lib():
         L.hjxo_step.argtypes = [PP, dp, dp, ctypes.c_double]
         L.hjxo_solve.argtypes = [PP, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.hjxo_solve.restype = ctypes.c_long
+        L.hjxo_solve_part.argtypes = [PP, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_long, dp]
+        L.hjxo_solve_part.restype = ctypes.c_long
         L.hjxo_cs_solve_loss.argtypes = [PP, dp, dp, dp, ctypes.c_int, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          dp, dp, dp, dp]
@@ -234,6 +240,26 @@ def solve(P, phi0, t1, t0=0.0, target=None):
     n = _check(lib().hjxo_solve(ctypes.byref(P), _ptr(phi0), _ptr(tgt), float(t0), float(t1),
                                 _ptr(out), ctypes.byref(dt0)), "solve")
     return out, n, dt0.value
+
+
+def solve_in_parts(P, phi0, t1, t0=0.0, target=None, part=100, report=None):
+    """solve() taken `part` steps at a time (the same steps, the same bits),
+    calling report(steps_so_far, t) after each part.  Returns (phi(t1),
+    number of steps)."""
+    phi = _f64(phi0).copy()
+    tgt = None if target is None else _f64(target)
+    t, steps = float(t0), 0
+    reached = ctypes.c_double(t)
+    while t < t1:
+        n = _check(lib().hjxo_solve_part(ctypes.byref(P), _ptr(phi), _ptr(tgt), t, float(t1), int(part),
+                                         ctypes.byref(reached)), "solve_part")
+        steps += n
+        t = reached.value
+        if report:
+            report(steps, t)
+        if n == 0:
+            break
+    return phi, steps
 
 
 def cs_solve_loss(P, phi0, t1, dphi0=None, dparams=None, with_target=True, t0=0.0, eps_h=None,

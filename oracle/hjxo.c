@@ -118,6 +118,7 @@ typedef struct {
     double cfl;
     int restrict_update; /* RESTRICT_NONE, RESTRICT_NONPOSITIVE or RESTRICT_POSITIVE */
     int dissipation;     /* DISS_GLOBAL, DISS_LOCAL or DISS_GODUNOV */
+    int decide_f32;      /* ENO stencil choices taken in binary32 (see eno_choice) */
 } hjxo_problem;
 
 /* ------------------------------------------------------------------ */
@@ -224,17 +225,62 @@ static real D1(const real *e, long j, double dx) { return (e[R + j + 1] - e[R + 
 static real D2(const real *e, long j, double dx) { return (D1(e, j, dx) - D1(e, j - 1, dx)) / (2.0 * dx); }
 static real D3(const real *e, long j, double dx) { return (D2(e, j + 1, dx) - D2(e, j, dx)) / (3.0 * dx); }
 
+/* The ENO choices (Sec. IV-B) turn floating-point comparisons into a
+ * stencil, an integer decision.  A solver that computes in binary32 takes
+ * them in binary32, so the oracle can take them the same way: with 'ef' the
+ * line rounded to binary32 (ghosts extrapolated in binary32, one fused
+ * multiply-add each) and h the binary32 reciprocal of the spacing,
+ *   d1(j) = (E(j+1) - E(j)) h,  d2(j) = (d1(j) - d1(j-1)) (h/2),
+ *   d3(j) = (d2(j+1) - d2(j)) (h * fl32(1/3)),
+ * every operation rounded to binary32.  Only the choice is taken from these
+ * values; the derivative itself is still formed in double from the double
+ * line.  With ef == NULL the choices compare the double D2 and D3 above. */
+static void fill_line_f32(const real *e, long n, int periodic, float *ef)
+{
+    for (long j = 0; j < n; ++j) ef[R + j] = (float)RE(e[R + j]);
+    for (long k = 1; k <= R; ++k) {
+        if (periodic) {
+            ef[R - k] = ef[R + n - k];
+            ef[R + n - 1 + k] = ef[R + k - 1];
+        } else {
+            ef[R - k] = fmaf((float)k, ef[R] - ef[R + 1], ef[R]);
+            ef[R + n - 1 + k] = fmaf((float)k, ef[R + n - 1] - ef[R + n - 2], ef[R + n - 1]);
+        }
+    }
+}
+
+static float d1f(const float *ef, long j, float h) { return (ef[R + j + 1] - ef[R + j]) * h; }
+static float d2f(const float *ef, long j, float h) { return (d1f(ef, j, h) - d1f(ef, j - 1, h)) * (0.5f * h); }
+static float d3f(const float *ef, long j, float h)
+{
+    return (d2f(ef, j + 1, h) - d2f(ef, j, h)) * (h * (float)(1.0 / 3.0));
+}
+
+/* does the smaller-|D^o| rule pick the left candidate (D2 at j vs j+1 for
+ * o = 2, D3 at j vs j+1 for o = 3)?  Ties go left, as printed. */
+static int eno_choice(const real *e, const float *ef, long j, int o, double dx, float h)
+{
+    if (ef) {
+        const float a = o == 2 ? d2f(ef, j, h) : d3f(ef, j, h);
+        const float b = o == 2 ? d2f(ef, j + 1, h) : d3f(ef, j + 1, h);
+        return fabsf(a) <= fabsf(b);
+    }
+    const real a = o == 2 ? D2(e, j, dx) : D3(e, j, dx);
+    const real b = o == 2 ? D2(e, j + 1, dx) : D3(e, j + 1, dx);
+    return RE(r_abs(a)) <= RE(r_abs(b));
+}
+
 /* ENO derivative at node i from the stencil that starts at interval k
  * (k = i-1 for the left-biased value, k = i for the right-biased one),
  * grown to 'order' points + 1 by the smaller-divided-difference rule. */
-static real eno_derivative(const real *e, long i, long k, int order, double dx)
+static real eno_derivative(const real *e, const float *ef, float h, long i, long k, int order, double dx)
 {
     real p = D1(e, k, dx); /* Q1'(x_i) */
     if (order == 1) return p;
 
     real c;
     long kstar;
-    if (RE(r_abs(D2(e, k, dx))) <= RE(r_abs(D2(e, k + 1, dx)))) { /* ties go left */
+    if (eno_choice(e, ef, k, 2, dx, h)) { /* |D2_k| <= |D2_{k+1}|: ties go left */
         c = D2(e, k, dx);
         kstar = k - 1;
     } else {
@@ -245,7 +291,7 @@ static real eno_derivative(const real *e, long i, long k, int order, double dx)
     if (order == 2) return p;
 
     real cstar;
-    if (RE(r_abs(D3(e, kstar, dx))) <= RE(r_abs(D3(e, kstar + 1, dx))))
+    if (eno_choice(e, ef, kstar, 3, dx, h))
         cstar = D3(e, kstar, dx);     /* D^3_{k*+1/2} */
     else
         cstar = D3(e, kstar + 1, dx); /* D^3_{k*+3/2} */
@@ -284,8 +330,9 @@ static real weno5(real v1, real v2, real v3, real v4, real v5)
 
 /* Left (pm) and right (pp) derivative approximations at every node of one
  * extended line. */
-static void derivative_line(int scheme, const real *e, long n, double dx, real *pm, real *pp)
+static void derivative_line(int scheme, const real *e, const float *ef, long n, double dx, real *pm, real *pp)
 {
+    const float h = (float)(1.0 / dx); /* used only with ef */
     for (long i = 0; i < n; ++i) {
         switch (scheme) {
         case SCHEME_FIRST: /* Sec. IV-A: D- and D+ */
@@ -293,12 +340,12 @@ static void derivative_line(int scheme, const real *e, long n, double dx, real *
             pp[i] = (e[R + i + 1] - e[R + i]) / dx;
             break;
         case SCHEME_ENO2:
-            pm[i] = eno_derivative(e, i, i - 1, 2, dx);
-            pp[i] = eno_derivative(e, i, i, 2, dx);
+            pm[i] = eno_derivative(e, ef, h, i, i - 1, 2, dx);
+            pp[i] = eno_derivative(e, ef, h, i, i, 2, dx);
             break;
         case SCHEME_ENO3:
-            pm[i] = eno_derivative(e, i, i - 1, 3, dx);
-            pp[i] = eno_derivative(e, i, i, 3, dx);
+            pm[i] = eno_derivative(e, ef, h, i, i - 1, 3, dx);
+            pp[i] = eno_derivative(e, ef, h, i, i, 3, dx);
             break;
         case SCHEME_WENO5:
             /* left-biased: v_m = D+ phi_{i-4+m}, m = 1..5 */
@@ -322,6 +369,7 @@ static void derivative_axis(const hjxo_problem *P, const real *phi, int d, real 
 #pragma omp parallel
     {
         real *ext = (real *)malloc(sizeof(real) * (size_t)(n + 2 * R));
+        float *extf = P->decide_f32 ? (float *)malloc(sizeof(float) * (size_t)(n + 2 * R)) : NULL;
         real *lm = (real *)malloc(sizeof(real) * (size_t)n);
         real *lp = (real *)malloc(sizeof(real) * (size_t)n);
 #pragma omp for schedule(static)
@@ -329,13 +377,15 @@ static void derivative_axis(const hjxo_problem *P, const real *phi, int d, real 
             long outer = line / s, inner = line % s;
             long start = outer * n * s + inner;
             fill_line(phi, start, s, n, per, ext);
-            derivative_line(P->scheme, ext, n, dx, lm, lp);
+            if (extf) fill_line_f32(ext, n, per, extf);
+            derivative_line(P->scheme, ext, extf, n, dx, lm, lp);
             for (long j = 0; j < n; ++j) {
                 pm[start + j * s] = lm[j];
                 pp[start + j * s] = lp[j];
             }
         }
         free(ext);
+        free(extf);
         free(lm);
         free(lp);
     }
@@ -578,14 +628,17 @@ static void rk_step(const hjxo_problem *P, const real *hp, real *phi, const real
 }
 
 /* time loop from t0 to t1 with the CFL step; the step that would reach
- * (or come within 1e-12 relative of) t1 is clamped to land on t1 */
+ * (or come within 1e-12 relative of) t1 is clamped to land on t1.  With
+ * max_steps >= 0 the loop stops after that many steps and *t_reached (if
+ * not NULL) says where, so that a later call from there continues the same
+ * schedule. */
 static long solve(const hjxo_problem *P, const real *hp, real *phi, const real *target, double t0,
-                  double t1, workspace *w, double *dt_first)
+                  double t1, workspace *w, double *dt_first, long max_steps, double *t_reached)
 {
     real t = t0;
     long steps = 0;
     double slack = 1e-12 * (fabs(t1) > 1.0 ? fabs(t1) : 1.0);
-    while (RE(t) < t1) {
+    while (RE(t) < t1 && (max_steps < 0 || steps < max_steps)) {
         real alpha[MAXD];
         dissipation_alpha(P, hp, alpha);
         real dt = cfl_dt(P, alpha);
@@ -599,6 +652,7 @@ static long solve(const hjxo_problem *P, const real *hp, real *phi, const real *
         ++steps;
         t = last ? (real)t1 : t + dt;
     }
+    if (t_reached) *t_reached = RE(t);
     return steps;
 }
 
@@ -666,7 +720,7 @@ int hjxo_deriv_line(int scheme, const double *phi, long n, int periodic, double 
         return -1;
     double *ext = (double *)malloc(sizeof(double) * (size_t)(n + 2 * R));
     fill_line(phi, 0, 1, n, periodic, ext);
-    derivative_line(scheme, ext, n, dx, pm, pp);
+    derivative_line(scheme, ext, NULL, n, dx, pm, pp);
     free(ext);
     return 0;
 }
@@ -744,7 +798,23 @@ long hjxo_solve(const hjxo_problem *P, const double *phi0, const double *target,
     if (!ws_alloc(P, &w)) { ws_free(&w); return -2; }
     long total = npoints(P);
     if (phi_out != phi0) memcpy(phi_out, phi0, sizeof(double) * (size_t)total);
-    long steps = solve(P, P->hp, phi_out, target, t0, t1, &w, dt_first);
+    long steps = solve(P, P->hp, phi_out, target, t0, t1, &w, dt_first, -1, NULL);
+    ws_free(&w);
+    return steps;
+}
+
+/* At most max_steps >= 1 steps of the solve from t0 towards t1, in place on
+ * phi; *t_reached is where they end.  Calling again from there (t0 =
+ * *t_reached) until it equals t1 takes exactly the steps of one hjxo_solve,
+ * so a long solve can report progress between calls.  Returns the number of
+ * steps taken (< 0 on error). */
+long hjxo_solve_part(const hjxo_problem *P, double *phi, const double *target, double t0, double t1,
+                     long max_steps, double *t_reached)
+{
+    if (check_problem(P) || !(t1 >= t0) || max_steps < 1 || !t_reached) return -1;
+    workspace w;
+    if (!ws_alloc(P, &w)) { ws_free(&w); return -2; }
+    long steps = solve(P, P->hp, phi, target, t0, t1, &w, NULL, max_steps, t_reached);
     ws_free(&w);
     return steps;
 }
@@ -935,7 +1005,7 @@ long hjxo_cs_solve_loss(const hjxo_problem *P, const double *phi0, const double 
         phi[f] = phi0[f] + I * h * (dphi0 ? dphi0[f] : 0.0);
         if (tgt) tgt[f] = phi[f];
     }
-    long steps = solve(P, hp, phi, tgt, t0, t1, &w, NULL);
+    long steps = solve(P, hp, phi, tgt, t0, t1, &w, NULL, -1, NULL);
     real L = sigmoid_volume(P, phi, eps_h);
     *loss = creal(L);
     *dloss = cimag(L) / h;
