@@ -1,11 +1,13 @@
 """Throughput of the level-set hot path on one MI355X.
 
 A bench step is one whole solve of the workload: the dissipation reduction,
-the CFL step and every WENO5 + Lax-Friedrichs + TVD-RK3 step with
-min-with-target to the horizon, on synthetic inputs already resident in HBM.
-Default workload: 3-D pursuit-evasion game (relative Dubins cars,
-v_e = v_p = 5, |w| <= 1), 101^3 nodes over [-6,20]x[-10,10]x[0,2pi), cylinder
-of radius 5 as target, horizon 2.8 (874 RK3 steps).
+the CFL step and every WENO5 + Lax-Friedrichs + TVD-RK3 step to the horizon,
+on synthetic inputs already resident in HBM.  Default workload (the largest
+one GPU holds): the 4-D Dubins car with a speed state (x, y, theta, v),
+|w| <= 1, |a| <= 1, 81^4 = 43,046,721 nodes over [-5,5]^2 x [0,2pi) x [0,2],
+phi0 = a cylinder of radius 1 in (x, y), horizon 1.5 (170 RK3 steps), FP32.
+The 3-D pursuit-evasion game (101^3, 874 steps with min-with-target) runs
+as a secondary leg in FP32 and FP64.
 
 Prints ONE JSON line.  value = grid-point updates/s, a grid-point update
 being one node advanced by one full RK3 step.
@@ -30,16 +32,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def alg_ops_per_point(scheme, ham, dim):
-    """Arithmetic operations per node per stage, counted from the formulas of
-    the method (FMA = 1, reciprocal = 1, |.|/max/min = 1)."""
-    per_dim = {
-        "first": 4,     # two differences, two scalings
-        "weno5": 136,   # six scaled differences + two WENO5 evaluations of 62
-    }[scheme]
-    ham_lf = {"normal": 2 * dim + 2 + 2 * dim, "dubins3_pe": 27, "dubins4": 26}[ham]
-    rk = 4
-    return per_dim * dim + ham_lf + rk
+def alg_ops_per_point(scheme, ham, dim, dtype="f32"):
+    """Algorithmic VALU operations per node per RK stage (FMA = 1).
+
+    WENO5 follows the scope table's estimate of the method's arithmetic,
+    with every interval's WENO5 window shared by the two nodes it serves:
+    per node per RK3 step about 900 operations in 3-D and 1150 in 4-D in
+    FP32, and 100 per axis plus 40 for H, LF and RK per stage in FP64
+    (division and reciprocals take several instructions there).  First
+    order: two differences and two scalings per axis plus H, LF and RK."""
+    if scheme == "weno5":
+        if dtype == "f64":
+            return 100 * dim + 40
+        return {1: 115.0, 2: 190.0, 3: 900.0 / 3, 4: 1150.0 / 3}[dim]
+    ham_lf = {"normal": 2 * dim + 2 + 2 * dim, "dubins3_pe": 27, "dubins4": 26, "rockets": 27}[ham]
+    return 4 * dim + ham_lf + 4
 
 
 def stage_bytes_per_point(rk, with_target, elem):
@@ -184,7 +191,7 @@ def run_adjoint(w, reps=2):
     tape = P.tape(w.t1, ckpt_every=8)
     tape.solve(phi0, target=phi0, out=out)
     loss, g = P.loss_volume(out, eps)
-    tape.adjoint(g)  # warm-up
+    tape.adjoint(g, sum_target=True)  # warm-up
     torch.cuda.synchronize()
     bwd_times = []
     for _ in range(reps):
@@ -192,12 +199,12 @@ def run_adjoint(w, reps=2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         loss, g = P.loss_volume(out, eps)
-        g0, gt, dp = tape.adjoint(g)
+        g0, _, dp = tape.adjoint(g, sum_target=True)   # dL/dphi0 through the initial value and the target
         torch.cuda.synchronize()
         bwd_times.append(time.perf_counter() - t0)
     bwd = min(bwd_times)
     log(f"  adjoint: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms")
-    grad_phi0 = (g0 + gt).double()
+    grad_phi0 = g0.double()
 
     # central differences of FP64 solves with small steps (the loss is only
     # piecewise smooth: a large step crosses changes of the step count, and
@@ -450,9 +457,11 @@ def run_shapes():
 
 def run_small(reps=20):
     """The launch-bound workload: normal2d (101^2, FP64, first-order upwind +
-    forward Euler, 40 steps).  Per solve: hjx_solve (host-driven launches,
-    plus its alpha and non-finite checks) against the same solve as a batch
-    of one member (the horizon captured once in a hipGraph and replayed)."""
+    forward Euler, 40 steps).  Per solve: hjx_solve repeated with the same
+    arguments (its stepping launches captured on the second call and
+    replayed, plus the non-finite checks and one synchronisation), hjx_solve
+    with graphs off (HJX_SOLVE_GRAPH=0: direct launches), and the same solve
+    as a batch of one member (the batch's own horizon graph)."""
     import torch
 
     from paper_2411_03501_amd import hjx, inputs
@@ -461,13 +470,25 @@ def run_small(reps=20):
     P = hjx.Problem.from_workload(w, "f64")
     phi0 = torch.from_numpy(inputs.initial_surface(w)).to("cuda", dtype=torch.float64)
     out = torch.empty_like(phi0)
-    _, st = P.solve(phi0, w.t1, out=out)
+    _, st = P.solve(phi0, w.t1, out=out)   # direct launches
+    P.solve(phi0, w.t1, out=out)           # the same solve again: captured into a graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        P.solve(phi0, w.t1, out=out)
+        P.solve(phi0, w.t1, out=out)       # replays
     torch.cuda.synchronize()
     single = (time.perf_counter() - t0) / reps
+    os.environ["HJX_SOLVE_GRAPH"] = "0"
+    try:
+        P.solve(phi0, w.t1, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.solve(phi0, w.t1, out=out)   # direct launches every time
+        torch.cuda.synchronize()
+        direct = (time.perf_counter() - t0) / reps
+    finally:
+        del os.environ["HJX_SOLVE_GRAPH"]
     B = hjx.Batch([P])
     shape, _ = B.tune([phi0], [w.t1], out=[out], reps=3)
     B.solve([phi0], [w.t1], out=[out])
@@ -483,10 +504,10 @@ def run_small(reps=20):
     P.close()
     n = st["steps"]
     upd = w.points * n
-    log(f"  normal2d: {n} steps, hjx_solve {single * 1e6:.0f} us, batch of one {batched * 1e6:.0f} us "
-        f"(graph {min(graph_ms) * 1e3:.0f} us, shape {shape})")
+    log(f"  normal2d: {n} steps, hjx_solve {single * 1e6:.0f} us (direct launches {direct * 1e6:.0f} us), "
+        f"batch of one {batched * 1e6:.0f} us (graph {min(graph_ms) * 1e3:.0f} us, shape {shape})")
     return {"workload": f"normal2d: 101x101 FP64, first-order + forward Euler, {n} steps",
-            "steps": n, "solve_us": single * 1e6, "graph_solve_us": batched * 1e6,
+            "steps": n, "solve_us": single * 1e6, "solve_direct_us": direct * 1e6, "graph_solve_us": batched * 1e6,
             "graph_replay_us": min(graph_ms) * 1e3, "us_per_step_graph": min(graph_ms) * 1e3 / n,
             "updates_per_s": upd / single, "graph_updates_per_s": upd / batched,
             "graph_shape": {"item_nodes": shape[0], "blocks": shape[1]}}
@@ -509,32 +530,57 @@ def run_copy(nbytes=1 << 30, reps=4):
     return {"bytes_read": nbytes, "bytes_written": nbytes, "reps": reps, "gbs": 2 * nbytes / dt / 1e9}
 
 
-def run_cpu_baseline(w, budget_s=15.0):
-    """The oracle as it stands, on the host's cores, for a bounded number of
-    RK steps of the same workload."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def run_cpu_baseline(w, budget_s=12.0, max_steps=4, single_budget_s=10.0):
+    """The oracle as it stands, on the host's cores: full-grid RK steps of
+    the same workload from phi0, first on min(cores, 16) threads (up to
+    max_steps steps or budget_s seconds), then on one thread (steps until
+    single_budget_s seconds have passed, at least one)."""
     import numpy as np
 
     import oracle as O
     from paper_2411_03501_amd import inputs
 
-    threads = min(os.cpu_count() or 1, 16)
-    O.set_threads(threads)
     Po = O.make_problem(w.gmin, w.gmax, w.n, w.periodic, w.ham, w.params, w.scheme, w.rk, w.cfl)
-    phi = inputs.initial_surface(w)
+    phi0 = inputs.initial_surface(w)
     dt = O.cfl_dt(Po)
-    tgt = phi.copy() if w.with_target else None
-    done = 0
-    t0 = time.perf_counter()
-    while True:
-        phi = O.step(Po, phi, dt, target=tgt)
-        done += 1
-        el = time.perf_counter() - t0
-        log(f"  oracle step {done}: {el:.1f} s")
-        if el > budget_s or done >= 50:
-            break
-    assert np.isfinite(phi).all()
+    tgt = phi0.copy() if w.with_target else None
+
+    def timed(threads, steps_max, budget):
+        O.set_threads(threads)
+        phi, done = phi0, 0
+        t0 = time.perf_counter()
+        while True:
+            phi = O.step(Po, phi, dt, target=tgt)
+            done += 1
+            el = time.perf_counter() - t0
+            log(f"  oracle on {threads} thread(s), step {done}: {el:.1f} s")
+            if el > budget or done >= steps_max:
+                break
+        assert np.isfinite(phi).all()
+        return done, el
+
+    threads = min(os.cpu_count() or 1, 16)
+    done, el = timed(threads, max_steps, budget_s)
+    done1, el1 = timed(1, max_steps, single_budget_s)
     return {"value": w.points * done / el, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} RK3 steps of the full {w.name} grid ({w.points} nodes), FP64"}
+            "sample": f"{done} RK3 steps of the full {w.name} grid ({w.points} nodes) from phi0, FP64, "
+                      f"{threads} threads",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "s_per_rk_step": el / done,
+            "single_thread": {"value": w.points * done1 / el1, "unit": "grid-point updates/s", "cores": 1,
+                              "s_per_rk_step": el1 / done1,
+                              "sample": f"{done1} RK3 step(s) of the full {w.name} grid, FP64, one thread"}}
 
 
 def main():
@@ -542,7 +588,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dubins3d")
+    ap.add_argument("--workload", default="car4d")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
@@ -593,51 +639,42 @@ def main():
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     elapsed, st, loop_ms = run_gpu(w, args.dtype, args.steps, args.warmup, tile)
     rk_steps = st["steps"]
-    elem = 4 if args.dtype == "f32" else 8
     updates = w.points * rk_steps * args.steps
     value = updates / elapsed
-
-    launches = rk_steps * w.rk
-    kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / launches   # mean stage-kernel duration
-    ops = alg_ops_per_point(w.scheme, w.ham, w.dim) * w.points
-    achieved_tops = ops / kern_s / 1e12
-    bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
-    achieved_gbs = bytes_launch / kern_s / 1e9
-    traffic = measured_traffic(w, args.dtype, st["tile"])
-    kernel_name = "stage_direct_kernel" if st["tile"][0] == 1 else "stage_kernel (plane-march)"
-    if w.scheme == "weno5":
-        roof = {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
-                "kernel": kernel_name, "kernel_us": kern_s * 1e6, "tile": st["tile"],
-                "hbm_alg_gbs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS}
-    else:
-        roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic,
-                "kernel": kernel_name, "kernel_us": kern_s * 1e6}
+    roof = roofline(w, args.dtype, st, loop_ms)
 
     extra = {}
     if not args.no_extra:
-        other = "f64" if args.dtype == "f32" else "f32"
-        log(f"secondary: {w.name} {other}")
-        e2, st2, lm2 = run_gpu(w, other, 2, 1)
-        extra[f"{w.name}_{other}"] = {
-            "updates_per_s": w.points * st2["steps"] * 2 / e2,
-            "stage_kernel_us": sum(lm2) / len(lm2) / (st2["steps"] * w.rk) * 1e3}
-        w4 = inputs.CAR4D
-        log(f"secondary: {w4.name} f32")
-        e4, st4, lm4 = run_gpu(w4, "f32", 2, 1)
-        k4 = sum(lm4) / len(lm4) / (st4["steps"] * w4.rk) / 1e3
-        extra["car4d_f32"] = {
-            "updates_per_s": w4.points * st4["steps"] * 2 / e4, "rk_steps": st4["steps"],
-            "stage_kernel_us": k4 * 1e6,
-            "alu_frac": alg_ops_per_point(w4.scheme, w4.ham, w4.dim) * w4.points / k4 / 1e12 / PEAK_VALU_TOPS,
-            "hbm_alg_frac": stage_bytes_per_point(w4.rk, w4.with_target, 4) * w4.points / k4 / 1e9 / PEAK_HBM_GBS}
+        wd = inputs.DUBINS3D
+        for dt_ in ("f32", "f64"):
+            if (wd.name, dt_) == (w.name, args.dtype):
+                continue
+            log(f"secondary: {wd.name} {dt_}")
+            e2, st2, lm2 = run_gpu(wd, dt_, 2, 1)
+            r2 = roofline(wd, dt_, st2, lm2)
+            extra[f"{wd.name}_{dt_}"] = {
+                "workload": describe(wd, st2["steps"]) + f", {dt_.upper()}",
+                "updates_per_s": wd.points * st2["steps"] * 2 / e2, "stage_kernel_us": r2["kernel_us"],
+                "tile": st2["tile"], "alu_frac": r2["frac"] if r2["bound"] == "alu" else None,
+                "traffic": r2["traffic"], "hbm_alg_frac": r2.get("hbm_frac")}
+            if dt_ == "f32":
+                plain32 = r2["kernel_us"]
+        if w.name != "car4d":
+            w4 = inputs.CAR4D
+            log(f"secondary: {w4.name} f32")
+            e4, st4, lm4 = run_gpu(w4, "f32", 2, 1)
+            r4 = roofline(w4, "f32", st4, lm4)
+            extra["car4d_f32"] = {"updates_per_s": w4.points * st4["steps"] * 2 / e4, "rk_steps": st4["steps"],
+                                  "stage_kernel_us": r4["kernel_us"], "alu_frac": r4["frac"],
+                                  "hbm_alg_frac": r4["hbm_frac"]}
+        if w.name == "dubins3d" and args.dtype == "f32":
+            plain32 = roof["kernel_us"]
 
-        log(f"tube form: {w.name} {args.dtype} with the clip")
-        extra[f"{w.name}_tube_{args.dtype}"] = run_tube(w, args.dtype, plain_us=kern_s * 1e6)
+        log(f"tube form: {wd.name} f32 with the clip")
+        extra[f"{wd.name}_tube_f32"] = run_tube(wd, "f32", plain_us=plain32)
 
-        log(f"local LF: {w.name} {args.dtype}")
-        extra[f"{w.name}_local_lf_{args.dtype}"] = run_local(w, args.dtype, plain_us=kern_s * 1e6)
+        log(f"local LF: {wd.name} f32")
+        extra[f"{wd.name}_local_lf_f32"] = run_local(wd, "f32", plain_us=plain32)
 
         log("rockets f32: the paper's own workload")
         extra["rockets_f32"] = run_rockets()
@@ -689,6 +726,30 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def roofline(w, dtype, st, loop_ms):
+    """The stage kernel's roofline record for one workload: its mean launch
+    duration from the event-timed stepping loops (the solve's own stream,
+    divided by the number of stage launches), the algorithmic operations or
+    bytes per launch, and the HBM bytes of the committed counter summary."""
+    elem = 4 if dtype == "f32" else 8
+    kern_s = (sum(loop_ms) / len(loop_ms)) / 1e3 / (st["steps"] * w.rk)
+    ops = alg_ops_per_point(w.scheme, w.ham, w.dim, dtype) * w.points
+    achieved_tops = ops / kern_s / 1e12
+    bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
+    achieved_gbs = bytes_launch / kern_s / 1e9
+    traffic = measured_traffic(w, dtype, st["tile"])
+    kernel_name = "stage_direct_kernel" if st["tile"][0] == 1 else "stage_kernel (plane-march)"
+    if w.scheme == "weno5":
+        return {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
+                "kernel": kernel_name, "kernel_us": kern_s * 1e6, "tile": st["tile"],
+                "ops_per_launch": ops, "bytes_per_launch": bytes_launch,
+                "hbm_alg_gbs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS}
+    return {"bound": "hbm", "achieved": achieved_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved_gbs / PEAK_HBM_GBS, "traffic": traffic,
+            "kernel": kernel_name, "kernel_us": kern_s * 1e6, "tile": st["tile"], "bytes_per_launch": bytes_launch}
 
 
 if __name__ == "__main__":

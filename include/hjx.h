@@ -37,7 +37,8 @@
  *   no derivative store if that would pass the cap); HJX_TUNE_VERBOSE makes
  *   the autotuners print each candidate's time to stderr; HJX_TRACE (not
  *   "0") puts a roctx range around every call and every reverse-sweep
- *   segment (rocprofv3 --marker-trace shows them).
+ *   segment (rocprofv3 --marker-trace shows them); HJX_SOLVE_GRAPH=0 keeps
+ *   hjx_solve from capturing and replaying its launches.
  */
 #ifndef HJX_H
 #define HJX_H
@@ -190,11 +191,23 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
  * make sure no enqueued work still uses it. */
 hjx_status hjx_problem_destroy(hjx_problem *p);
 
+/* Replace the Hamiltonian's parameters (the p[] of hjx_ham_desc, the
+ * dynamics' bounds of Listing 4's schemeData) of an existing problem: params
+ * is a host array of the kind's parameter count (1, 4, 2 or 4 doubles),
+ * checked as hjx_problem_create checks them.  The dissipation bounds are
+ * reduced again at the next call that needs them, and a captured solve is
+ * dropped.  A tape or batch made before the change refuses to run
+ * (HJX_ERR_INVALID_ARG) until the parameters are set back. */
+hjx_status hjx_problem_set_params(hjx_problem *p, const double *params);
+
 /* Dissipation coefficients and CFL step (Sec. IV-D, GLF dissipation of
  * Listing 4): alpha_d = max over all grid nodes of the partial bound,
  * reduced on the device; dt = cfl / sum_d alpha_d/dx_d (+inf when every
  * alpha_d is 0).  alpha_out: host array of at least dim doubles; dt_out:
- * host double.  Synchronises `stream`. */
+ * host double.  alpha depends only on the grid and the parameters, fixed at
+ * create: the first call that needs it (this one, or any call below that
+ * steps) reduces it and synchronises `stream`; later calls reuse it without
+ * touching the device. */
 hjx_status hjx_dissipation(hjx_problem *p, double *alpha_out, double *dt_out, void *stream);
 
 /* Lax-Friedrichs right-hand side L = -Hhat(phi) at every node (Sec. IV,
@@ -235,18 +248,34 @@ hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t 
  * candidate (>= 1).  best_us (host, optional): the winner's mean time per
  * stage launch.  Allocates one temporary array of the problem's size for the
  * duration of the call.  Results do not depend on the choice.  Synchronises
- * `stream`. */
-hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream, double *best_us);
+ * `stream`.
+ * cache_path: a text file of tuned shapes, one line per problem, keyed by the
+ * device (architecture and compute units) and by what the shape can depend
+ * on (dtype, sizes, periodic axes, scheme, RK order, Hamiltonian kind,
+ * dissipation, restricted update).  A line for this problem sets its shape
+ * without timing anything (best_us is the recorded time); otherwise the
+ * tuner runs and appends its result.  NULL: the environment variable
+ * HJX_TUNE_CACHE names the file, if set; "": no cache.  A file that cannot
+ * be read or written is treated as empty. */
+hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *cache_path, void *stream,
+                    double *best_us);
 
 /* Solve from t0 to t1 (Listing 3 odeCFLx(schemeFunc, tspan, y0, ...)):
  * steps of the CFL size dt, the one that would reach t1 (or come within
  * 1e-12 max(1,|t1|) of it) clamped to land on t1.  phi0: initial data;
  * target: device array for min-with-target, or NULL for none (target may be
  * phi0, but not phi_out); phi_out: result (may be phi0 itself).  t1 >= t0.
- * Synchronises
- * `stream`.  stats (optional, host) receives the step record.  Returns
- * HJX_ERR_NONFINITE without stepping if phi0 holds NaN/Inf, and after the
- * solve (phi_out written) if the result does. */
+ * The call enqueues a NaN/Inf check of phi0, the steps and a check of the
+ * result, then synchronises `stream` once.  Returns HJX_ERR_NONFINITE if
+ * phi0 or the result holds NaN/Inf (phi_out is written either way).
+ * stats (optional, host) receives the step record.
+ * When the same solve (the same phi0, target, phi_out, t0 and t1) is asked
+ * for twice in a row, the second call captures the stepping launches into a
+ * hipGraph on a stream of the problem's own and every later identical call
+ * replays it (the same kernels and arguments, so the same bits);
+ * hjx_problem_set_tile, hjx_tune and any different solve drop it.  The
+ * environment variable HJX_SOLVE_GRAPH=0 keeps every solve on direct
+ * launches. */
 hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void *phi_out,
                      double t0, double t1, void *stream, hjx_stats *stats);
 
@@ -303,7 +332,9 @@ hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, con
 /* Reverse sweep after hjx_solve_taped.  dL_dphiT: device array, the
  * gradient of the loss with respect to phi(t1).  dL_dphi0: device array
  * (output).  dL_dtarget: device array (output) or NULL; must be NULL when
- * the solve had no target.  dL_dparams: host array of 8 doubles (output, the
+ * the solve had no target.  dL_dtarget == dL_dphi0 asks for the gradient
+ * of the whole map when phi0 is also the target: that array then receives
+ * dL/dtarget + dL/dphi0.  dL_dparams: host array of 8 doubles (output, the
  * entries past the kind's parameter count are 0) or NULL.  All work runs on
  * `stream`: each segment's replay shares launches with the reverse sweep of
  * the segment after it.  `stream` is synchronised at the end. */

@@ -242,6 +242,18 @@ def solve(P, phi0, t1, t0=0.0, target=None):
     return out, n, dt0.value
 
 
+def solve_part(P, phi, t0, t1, max_steps, target=None):
+    """At most max_steps steps of solve() from t0 towards t1, in place on phi
+    (float64, C-contiguous).  Returns (steps taken, t reached); continuing
+    from there takes exactly the steps of one solve()."""
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous
+    tgt = None if target is None else _f64(target)
+    reached = ctypes.c_double(t0)
+    n = _check(lib().hjxo_solve_part(ctypes.byref(P), _ptr(phi), _ptr(tgt), float(t0), float(t1), int(max_steps),
+                                     ctypes.byref(reached)), "solve_part")
+    return n, reached.value
+
+
 def solve_in_parts(P, phi0, t1, t0=0.0, target=None, part=100, report=None):
     """solve() taken `part` steps at a time (the same steps, the same bits),
     calling report(steps_so_far, t) after each part.  Returns (phi(t1),

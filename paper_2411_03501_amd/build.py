@@ -23,20 +23,53 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, jobs=4):
+OBJDIR = os.path.join(CSRC, "_build")
+
+
+def _deps(path, seen=None):
+    """The file and every file it includes with #include "...", recursively."""
+    import re
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path, encoding="utf-8") as f:
+        for m in re.finditer(r'^\s*#\s*include\s+"([^"]+)"', f.read(), re.M):
+            _deps(os.path.normpath(os.path.join(os.path.dirname(path), m.group(1))), seen)
+    return seen
+
+
+def _stale(obj, src):
+    """An object is stale when it is missing or older than its source or a
+    header the source includes."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(src))
+
+
+def build(verbose=False, force=True):
+    """Compile every source for gfx950 and link libhjx.so.  force=False
+    recompiles only the objects older than their sources or headers (the
+    objects are kept in csrc/_build)."""
+    os.makedirs(OBJDIR, exist_ok=True)
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"]
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        path = os.path.join(CSRC, src)
+        if not force and not _stale(obj, path):
+            continue
+        cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", path, "-o", obj + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((subprocess.Popen(cmd), cmd))
-        objs.append(obj)
-    for p, cmd in procs:
-        if p.wait() != 0:
-            raise RuntimeError("compile failed: " + " ".join(cmd))
+        procs.append((subprocess.Popen(cmd), cmd, obj))
+    failed = [cmd for p, cmd, _ in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError("compile failed: " + " ".join(failed[0]))
+    for _, _, obj in procs:
+        os.replace(obj + ".tmp", obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib",
            "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
@@ -44,10 +77,9 @@ def build(verbose=False, jobs=4):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    for o in objs:
-        os.remove(o)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, force="--changed" not in sys.argv))

@@ -121,10 +121,30 @@ struct hjx_problem {
     size_t table_off[kMaxDim][3] = {};
     void *ws[2] = {nullptr, nullptr};
     double *dalpha = nullptr;  // device: alpha[kMaxDim] + reduction partials
-    int *dflag = nullptr;      // device: non-finite flag
-    double *hbuf = nullptr;    // pinned host: alpha[kMaxDim], flag
+    int *dflag = nullptr;      // device: non-finite flags (input, output)
+    double *hbuf = nullptr;    // pinned host: alpha[kMaxDim], flags
     hipEvent_t ev[2] = {nullptr, nullptr};
     Tile tile{};               // stage-kernel launch shape
+    // alpha depends only on the grid tables and the parameters, both fixed
+    // at create: reduced on the device once, then kept
+    bool alpha_known = false;
+    double alpha[kMaxDim] = {0, 0, 0, 0};
+    // the stepping launches of hjx_solve, captured when the same solve
+    // (arrays, times) is asked for a second time in a row, then replayed
+    struct SolveKey {
+        const void *phi0 = nullptr, *target = nullptr;
+        void *out = nullptr;
+        double t0 = 0.0, t1 = 0.0;
+        bool operator==(const SolveKey &o) const
+        {
+            return phi0 == o.phi0 && target == o.target && out == o.out && t0 == o.t0 && t1 == o.t1;
+        }
+    };
+    SolveKey last_key{};
+    bool have_key = false;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -337,9 +357,14 @@ hipError_t rk_step(const hjx_problem *p, const double *alpha, void *phi, const v
     }
 }
 
-// alpha on the device -> pinned host buffer; synchronises s.
+// alpha_d, the grid maximum of the partial bound: reduced on the device the
+// first time (synchronises s), kept on the host afterwards.
 hjx_status device_alpha(hjx_problem *p, hipStream_t s, double *alpha_host)
 {
+    if (p->alpha_known) {
+        for (int d = 0; d < kMaxDim; ++d) alpha_host[d] = p->alpha[d];
+        return HJX_OK;
+    }
     hipError_t e;
     if (p->scheme.dtype == HJX_F32) {
         AlphaArgs<float> a{};
@@ -363,7 +388,8 @@ hjx_status device_alpha(hjx_problem *p, hipStream_t s, double *alpha_host)
     HIP_TRY(e);
     HIP_TRY(hipMemcpyAsync(p->hbuf, p->dalpha, sizeof(double) * kMaxDim, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int d = 0; d < kMaxDim; ++d) alpha_host[d] = d < p->grid.dim ? p->hbuf[d] : 0.0;
+    for (int d = 0; d < kMaxDim; ++d) p->alpha[d] = alpha_host[d] = d < p->grid.dim ? p->hbuf[d] : 0.0;
+    p->alpha_known = true;
     return HJX_OK;
 }
 
@@ -390,9 +416,133 @@ hjx_status any_nonfinite(hjx_problem *p, const void *x, hipStream_t s, bool *bad
     return HJX_OK;
 }
 
+// launch the non-finite check of x into the flag word flag (0 = input,
+// 1 = output); the flags must have been cleared on the same stream
+hipError_t check_nonfinite(hjx_problem *p, const void *x, int flag, hipStream_t s)
+{
+    if (p->scheme.dtype == HJX_F32)
+        return launch_nonfinite_f32(static_cast<const float *>(x), (int)p->total, p->dflag + flag, s);
+    return launch_nonfinite_f64(static_cast<const double *>(x), (int)p->total, p->dflag + flag, s);
+}
+
+void drop_solve_graph(hjx_problem *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->have_key = false;
+}
+
+// The number of steps of a solve from t0 to t1 with CFL step dt and the
+// size of the last one: steps of dt while they stay short of t1, the one
+// that would reach t1 (or come within 1e-12 max(1, |t1|) of it) clamped to
+// land on t1.
+void schedule(double t0, double t1, double dt, int64_t *steps, double *dt_last)
+{
+    const double slack = 1e-12 * (std::fabs(t1) > 1.0 ? std::fabs(t1) : 1.0);
+    double t = t0, h_last = 0.0;
+    int64_t n = 0;
+    while (t < t1) {
+        double h = dt;
+        bool last = false;
+        if (t + h >= t1 - slack) {
+            h = t1 - t;
+            last = true;
+        }
+        ++n;
+        h_last = h;
+        t = last ? t1 : t + h;
+    }
+    *steps = n;
+    *dt_last = h_last;
+}
+
+// The stepping launches of a solve: `steps` RK steps from phi0 into
+// phi_out, the last of size dt_last, the others dt.  No copy of phi0: the
+// first step reads it where it is.  Forward Euler alternates between
+// phi_out and the workspace so that the last step lands in phi_out; the
+// RK2/RK3 stages of the first step take phi0 as phi^n and write their last
+// stage into phi_out, which later steps advance in place.
+hipError_t enqueue_steps(const hjx_problem *p, const double *alpha, const void *phi0, const void *target,
+                         void *phi_out, int64_t steps, double dt, double dt_last, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (steps == 0) return phi_out == phi0 ? hipSuccess : launch_copy(p, phi0, phi_out, s);
+    if (p->scheme.rk == 1) {
+        if (phi_out == phi0) {  // in place: each step through the workspace and back
+            for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
+                const double h = k + 1 == steps ? dt_last : dt;
+                e = launch_stage(p, alpha, phi_out, nullptr, target, p->ws[0], h, 0.0, 1.0, false, s);
+                if (e == hipSuccess) e = launch_copy(p, p->ws[0], phi_out, s);
+            }
+            return e;
+        }
+        // step k writes phi_out when steps - k is odd, else the workspace
+        const void *cur = phi0;
+        for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
+            const double h = k + 1 == steps ? dt_last : dt;
+            void *nxt = ((steps - k) & 1) ? phi_out : p->ws[0];
+            e = launch_stage(p, alpha, cur, nullptr, target, nxt, h, 0.0, 1.0, false, s);
+            cur = nxt;
+        }
+        return e;
+    }
+    const void *src = phi0;
+    for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
+        const double h = k + 1 == steps ? dt_last : dt;
+        void *a = p->ws[0], *b = p->ws[1];
+        if (p->scheme.rk == 2) {  // odeCFL2: two Euler moves, then the average with phi^n
+            e = launch_stage(p, alpha, src, nullptr, nullptr, a, h, 0.0, 1.0, false, s);
+            if (e == hipSuccess) e = launch_stage(p, alpha, a, src, target, phi_out, h, 0.5, 0.5, false, s);
+        } else {  // odeCFL3: Shu-Osher stages with averages 3/4, 1/4 and 1/3, 2/3
+            e = launch_stage(p, alpha, src, nullptr, nullptr, a, h, 0.0, 1.0, false, s);
+            if (e == hipSuccess) e = launch_stage(p, alpha, a, src, nullptr, b, h, 0.75, 0.25, false, s);
+            if (e == hipSuccess)
+                e = launch_stage(p, alpha, b, src, target, phi_out, h, 1.0 / 3.0, 2.0 / 3.0, false, s);
+        }
+        src = phi_out;
+    }
+    return e;
+}
+
+// the stepping launches captured on the problem's own stream into a graph
+hjx_status capture_steps(hjx_problem *p, const double *alpha, const void *phi0, const void *target, void *phi_out,
+                         int64_t steps, double dt, double dt_last)
+{
+    if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = enqueue_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, p->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(HJX_ERR_DEVICE, "solve graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    p->graph = g;
+    const hipError_t e3 = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+        p->exec = nullptr;
+        return fail(HJX_ERR_DEVICE, "solve graph instantiate: %s", hipGetErrorString(e3));
+    }
+    return HJX_OK;
+}
+
+// whether hjx_solve may capture and replay its launches (HJX_SOLVE_GRAPH=0
+// turns it off: every solve then launches directly)
+bool solve_graphs_on()
+{
+    const char *v = std::getenv("HJX_SOLVE_GRAPH");
+    return !(v && v[0] == '0' && v[1] == 0);
+}
+
 void release(hjx_problem *p)
 {
     if (!p) return;
+    drop_solve_graph(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->tables) (void)hipFree(p->tables);
     for (void *w : p->ws)
         if (w) (void)hipFree(w);
@@ -467,7 +617,7 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
     const size_t field = (size_t)p->total * p->elem;
     const int partials = alpha_blocks((int)p->total);
     size_t cap = 0;
-    const size_t need = bytes + 2 * field + sizeof(double) * kMaxDim * (1 + (size_t)partials) + sizeof(int);
+    const size_t need = bytes + 2 * field + sizeof(double) * kMaxDim * (1 + (size_t)partials) + 2 * sizeof(int);
     if (over_workspace_cap(need, &cap)) {
         release(p);
         return fail(HJX_ERR_OOM, "problem workspace of %zu bytes exceeds HJX_MAX_WORKSPACE=%zu", need, cap);
@@ -476,7 +626,7 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
         (e = hipMemcpy(p->tables, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMalloc(&p->ws[0], field)) != hipSuccess || (e = hipMalloc(&p->ws[1], field)) != hipSuccess ||
         (e = hipMalloc(&p->dalpha, sizeof(double) * kMaxDim * (1 + (size_t)partials))) != hipSuccess ||
-        (e = hipMalloc(&p->dflag, sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&p->dflag, 2 * sizeof(int))) != hipSuccess ||
         (e = hipHostMalloc(&p->hbuf, sizeof(double) * (kMaxDim + 1), hipHostMallocDefault)) != hipSuccess ||
         (e = hipEventCreate(&p->ev[0])) != hipSuccess || (e = hipEventCreate(&p->ev[1])) != hipSuccess) {
         release(p);
@@ -494,9 +644,25 @@ hjx_status hjx_problem_destroy(hjx_problem *p)
     return ok();
 }
 
+hjx_status hjx_problem_set_params(hjx_problem *p, const double *params)
+{
+    if (!p || !params) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
+    hjx_ham_desc h = p->ham;
+    const int np = n_params(h.kind);
+    for (int k = 0; k < 8; ++k) h.p[k] = k < np ? params[k] : 0.0;
+    hjx_status st = validate(&p->grid, &h, &p->scheme);
+    if (st != HJX_OK) return st;
+    if (std::memcmp(h.p, p->ham.p, sizeof h.p) == 0) return ok();
+    p->ham = h;
+    p->alpha_known = false;  // alpha and the captured launches carry the old values
+    drop_solve_graph(p);
+    return ok();
+}
+
 hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int32_t ty, int32_t march)
 {
     if (!p) return fail(HJX_ERR_INVALID_ARG, "NULL problem");
+    drop_solve_graph(p);  // its launches carry the old shape
     const GridGeom g = geometry(p);
     if (variant == HJX_TILE_DIRECT) {
         if (!direct_ok(g, p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the direct variant needs arrays under 4 GiB");
@@ -526,11 +692,95 @@ hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t 
     return ok();
 }
 
-hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream, double *best_us)
+}  // extern "C"
+
+namespace {
+
+// The autotuner's cache: a text file of one line per tuned problem,
+//   hjx-tune 1 <arch> <compute units> <dtype> <dim> <n0>x..x<n3> <periodic>
+//       <deriv> <rk> <ham> <dissipation> <restrict> | <variant> <tx> <ty> <march> <us>
+// the part before '|' naming the device and everything the launch shape
+// can depend on, the part after the shape and its time.  The last line with
+// a problem's key wins; new results are appended.
+std::string tune_key(const hjx_problem *p)
+{
+    hipDeviceProp_t prop{};
+    const bool have = hipGetDeviceProperties(&prop, p->device) == hipSuccess;
+    char buf[512];
+    int o = std::snprintf(buf, sizeof buf, "hjx-tune 1 %s %d %s %d ", have ? prop.gcnArchName : "unknown",
+                          have ? prop.multiProcessorCount : 0, p->scheme.dtype == HJX_F32 ? "f32" : "f64",
+                          p->grid.dim);
+    for (int d = 0; d < p->grid.dim; ++d)
+        o += std::snprintf(buf + o, sizeof buf - o, d ? "x%lld" : "%lld", (long long)p->grid.n[d]);
+    std::snprintf(buf + o, sizeof buf - o, " %u %d %d %d %d %d", p->grid.periodic_mask, p->scheme.deriv,
+                  p->scheme.rk, p->ham.kind, p->ham.dissipation, p->scheme.restrict_update);
+    return buf;
+}
+
+const char *tune_cache_path(const char *given)
+{
+    if (given) return given[0] ? given : nullptr;
+    const char *env = std::getenv("HJX_TUNE_CACHE");
+    return env && env[0] ? env : nullptr;
+}
+
+// the cached shape for key, if the file has one
+bool tune_cache_find(const char *path, const std::string &key, Tile *tile, double *us)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    const std::string prefix = key + " | ";
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, prefix.c_str(), prefix.size()) != 0) continue;
+        int v = 0, tx = 0, ty = 0, m = 0;
+        double t = 0.0;
+        if (std::sscanf(line + prefix.size(), "%d %d %d %d %lf", &v, &tx, &ty, &m, &t) == 5 &&
+            (v == kVariantDirect || v == kVariantPlaneMarch)) {
+            *tile = Tile{tx, ty, m, v};
+            *us = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_add(const char *path, const std::string &key, const Tile &t, double us)
+{
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;  // a cache that cannot be written only costs the next call a retune
+    std::fprintf(f, "%s | %d %d %d %d %.3f\n", key.c_str(), t.variant, t.tx, t.ty, t.march, us);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *cache_path, void *stream,
+                    double *best_us)
 {
     TraceRange trace_("hjx_tune");
     if (!p || !phi) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps %d < 1", reps);
+    const char *cache = tune_cache_path(cache_path);
+    const std::string key = cache ? tune_key(p) : std::string();
+    if (cache) {
+        Tile t{};
+        double us = 0.0;
+        if (tune_cache_find(cache, key, &t, &us)) {
+            const hjx_status st = hjx_problem_set_tile(p, t.variant == kVariantDirect ? HJX_TILE_DIRECT
+                                                                                         : HJX_TILE_PLANE_MARCH,
+                                                       t.tx, t.ty, t.march);
+            if (st == HJX_OK) {
+                if (best_us) *best_us = us;
+                return ok();
+            }
+            // a shape this problem rejects: tune again and append the new one
+        }
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     double alpha[kMaxDim];
     hjx_status st = device_alpha(p, s, alpha);
@@ -600,8 +850,11 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, void *stream,
         }
     }
     HIP_TRY(hipFree(work));
+    drop_solve_graph(p);
     p->tile = best;
-    if (best_us) *best_us = (double)best_ms * 1e3 / reps;
+    const double us = (double)best_ms * 1e3 / reps;
+    if (cache) tune_cache_add(cache, key, best, us);
+    if (best_us) *best_us = us;
     return ok();
 }
 
@@ -654,52 +907,46 @@ hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void 
         return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    bool bad = false;
-    hjx_status st = any_nonfinite(p, phi0, s, &bad);
-    if (st != HJX_OK) return st;
-    if (bad) return fail(HJX_ERR_NONFINITE, "phi0 holds NaN or Inf");
-
     double alpha[kMaxDim];
-    if ((st = device_alpha(p, s, alpha)) != HJX_OK) return st;
+    hjx_status st = device_alpha(p, s, alpha);
+    if (st != HJX_OK) return st;
     const double dt = cfl_dt(p, alpha);
-
-    if (phi_out != phi0) HIP_TRY(launch_copy(p, phi0, phi_out, s));
-    if (stats) HIP_TRY(hipEventRecord(p->ev[0], s));
-
-    // time loop: the step that would reach t1 (within a relative 1e-12) lands on it
-    const double slack = 1e-12 * (std::fabs(t1) > 1.0 ? std::fabs(t1) : 1.0);
-    double t = t0, dt_last = 0.0;
     int64_t steps = 0;
-    void *cur = phi_out;  // forward Euler alternates between phi_out and the workspace
-    while (t < t1) {
-        double h = dt;
-        bool last = false;
-        if (t + h >= t1 - slack) {
-            h = t1 - t;
-            last = true;
-        }
-        if (p->scheme.rk == 1) {
-            void *nxt = cur == phi_out ? p->ws[0] : phi_out;
-            HIP_TRY(launch_stage(p, alpha, cur, nullptr, target, nxt, h, 0.0, 1.0, false, s));
-            cur = nxt;
-        } else {
-            HIP_TRY(rk_step(p, alpha, phi_out, target, h, s));
-        }
-        ++steps;
-        dt_last = h;
-        t = last ? t1 : t + h;
-    }
-    if (cur != phi_out) HIP_TRY(launch_copy(p, cur, phi_out, s));
-    if (stats) HIP_TRY(hipEventRecord(p->ev[1], s));
+    double dt_last = 0.0;
+    schedule(t0, t1, dt, &steps, &dt_last);
 
-    if ((st = any_nonfinite(p, phi_out, s, &bad)) != HJX_OK) return st;
+    // the input check, the stepping launches, the output check, then the
+    // one host synchronisation of the call
+    HIP_TRY(hipMemsetAsync(p->dflag, 0, 2 * sizeof(int), s));
+    HIP_TRY(check_nonfinite(p, phi0, 0, s));
+    if (stats) HIP_TRY(hipEventRecord(p->ev[0], s));
+    const hjx_problem::SolveKey key{phi0, target, phi_out, t0, t1};
+    if (p->exec && p->have_key && key == p->last_key) {
+        HIP_TRY(hipGraphLaunch(p->exec, s));
+    } else if (solve_graphs_on() && steps > 1 && p->have_key && key == p->last_key) {
+        // the same solve a second time in a row: capture it once, replay it from now on
+        if ((st = capture_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last)) != HJX_OK) return st;
+        HIP_TRY(hipGraphLaunch(p->exec, s));
+    } else {
+        drop_solve_graph(p);
+        HIP_TRY(enqueue_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, s));
+        p->last_key = key;
+        p->have_key = true;
+    }
+    if (stats) HIP_TRY(hipEventRecord(p->ev[1], s));
+    HIP_TRY(check_nonfinite(p, phi_out, 1, s));
+    int *hflag = reinterpret_cast<int *>(p->hbuf + kMaxDim);
+    HIP_TRY(hipMemcpyAsync(hflag, p->dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const bool bad_in = hflag[0] != 0, bad_out = hflag[1] != 0;
+
     if (stats) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
         stats->steps = steps;
         stats->dt = dt;
         stats->dt_last = dt_last;
-        stats->t_final = t;
+        stats->t_final = steps > 0 ? t1 : t0;
         for (int d = 0; d < kMaxDim; ++d) stats->alpha[d] = alpha[d];
         stats->elapsed_ms = ms;
         // algorithmic bytes per step: every stage reads its input and writes
@@ -711,7 +958,8 @@ hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void 
         if (target) per_step += 1.0;
         stats->alg_bytes = per_step * f * (double)steps;
     }
-    if (bad) return fail(HJX_ERR_NONFINITE, "the solution holds NaN or Inf");
+    if (bad_in) return fail(HJX_ERR_NONFINITE, "phi0 holds NaN or Inf");
+    if (bad_out) return fail(HJX_ERR_NONFINITE, "the solution holds NaN or Inf");
     return ok();
 }
 
@@ -722,6 +970,7 @@ hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void 
 struct hjx_tape {
     hjx_problem *p = nullptr;
     double t0 = 0, t1 = 0, dt = 0, dt_last = 0, alpha[kMaxDim] = {0, 0, 0, 0};
+    double hp[8] = {};                 // the problem's parameters when the tape was made
     int64_t steps = 0;
     int K = 1, nseg = 0;
     std::vector<void *> ckpt;          // phi at the start of every segment
@@ -808,27 +1057,6 @@ hjx_status tape_alloc_dp(const hjx_problem *p, hjx_tape *t)
     return HJX_OK;
 }
 
-// the steps of a solve from t0 to t1 with CFL step dt (the loop of hjx_solve)
-void schedule(double t0, double t1, double dt, int64_t *steps, double *dt_last)
-{
-    const double slack = 1e-12 * (std::fabs(t1) > 1.0 ? std::fabs(t1) : 1.0);
-    double t = t0, last_h = 0.0;
-    int64_t n = 0;
-    while (t < t1) {
-        double h = dt;
-        bool last = false;
-        if (t + h >= t1 - slack) {
-            h = t1 - t;
-            last = true;
-        }
-        ++n;
-        last_h = h;
-        t = last ? t1 : t + h;
-    }
-    *steps = n;
-    *dt_last = last_h;
-}
-
 // dalpha_d / dtheta_m of the built-in bounds, differentiated at the first
 // node where each maximum is attained (FP64, from the same node formula as
 // the device tables)
@@ -889,6 +1117,7 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     hjx_tape *t = new (std::nothrow) hjx_tape;
     if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
     t->p = p;
+    std::memcpy(t->hp, p->ham.p, sizeof t->hp);
     t->t0 = t0;
     t->t1 = t1;
     t->K = ckpt_every;
@@ -1003,6 +1232,8 @@ hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, con
     TraceRange trace_("hjx_solve_taped");
     if (!p || !tape || !phi0 || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
     if (tape->p != p) return fail(HJX_ERR_INVALID_ARG, "the tape belongs to another problem");
+    if (std::memcmp(tape->hp, p->ham.p, sizeof tape->hp) != 0)
+        return fail(HJX_ERR_INVALID_ARG, "the problem's parameters changed since the tape was made");
     if (target && target == phi_out) return fail(HJX_ERR_INVALID_ARG, "target aliases phi_out");
     hipStream_t s = static_cast<hipStream_t>(stream);
     bool bad = false;
@@ -1218,6 +1449,11 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
     if (t->p != p) return fail(HJX_ERR_INVALID_ARG, "the tape belongs to another problem");
     if (!t->solved) return fail(HJX_ERR_INVALID_ARG, "the tape holds no solve (call hjx_solve_taped first)");
     if (dL_dtarget && !t->target) return fail(HJX_ERR_INVALID_ARG, "dL_dtarget given but the solve had no target");
+    if (std::memcmp(t->hp, p->ham.p, sizeof t->hp) != 0)
+        return fail(HJX_ERR_INVALID_ARG, "the problem's parameters changed since the tape was made");
+    // dL_dtarget == dL_dphi0: the gradient through phi0 when phi0 is also the
+    // target, written as the sum of the two
+    const bool summed = dL_dtarget && dL_dtarget == dL_dphi0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int rk = p->scheme.rk;
     // stage k of the forward step: out = ca phi_n + cb (in_k + h L(in_k))
@@ -1310,7 +1546,19 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
         for (; carried < next.size(); ++carried) HIP_TRY(replay_stage(p, t->alpha, next[carried], s));
     }
     HIP_TRY(flush_contrib(p, t, lbar, s));
-    HIP_TRY(launch_copy(p, lbar, dL_dphi0, s));
+    if (summed) {  // dL/dphi0 = dL/dtarget + lam at t0
+        if (p->scheme.dtype == HJX_F32) {
+            AdjCombineArgs<float> c{};
+            c.c[c.n++] = static_cast<const float *>(lbar);
+            HIP_TRY(launch_combine_f32(static_cast<float *>(dL_dphi0), c, (int)p->total, s));
+        } else {
+            AdjCombineArgs<double> c{};
+            c.c[c.n++] = static_cast<const double *>(lbar);
+            HIP_TRY(launch_combine_f64(static_cast<double *>(dL_dphi0), c, (int)p->total, s));
+        }
+    } else {
+        HIP_TRY(launch_copy(p, lbar, dL_dphi0, s));
+    }
 
     HIP_TRY(launch_acc_reduce(t->acc, t->acc_blocks, t->acc_out, s));
     HIP_TRY(hipMemcpyAsync(t->hacc, t->acc_out, sizeof(double) * kAccCount, hipMemcpyDeviceToHost, s));
@@ -1370,6 +1618,7 @@ struct hjx_batch {
     size_t elem = 0, inst_bytes = 0;
     std::vector<hjx_problem *> probs;
     std::vector<double> alpha;        // n * kMaxDim
+    std::vector<double> hp;           // n * 8: each member's parameters at create
     std::vector<double> dt;           // CFL step of each problem
     void *dinst = nullptr;            // device descriptors (sorted order)
     void *hinst = nullptr;            // pinned host copy
@@ -1583,6 +1832,8 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
     b->inst_bytes = b->dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
     b->probs.assign(problems, problems + n);
     b->alpha.assign((size_t)n * kMaxDim, 0.0);
+    b->hp.assign((size_t)n * 8, 0.0);
+    for (int i = 0; i < n; ++i) std::memcpy(&b->hp[(size_t)i * 8], problems[i]->ham.p, sizeof(double) * 8);
     b->dt.assign(n, 0.0);
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int i = 0; i < n; ++i) {
@@ -1651,6 +1902,8 @@ hjx_status hjx_batch_solve(hjx_batch *b, const void *const *phi0, const void *co
         if (!phi0[i] || !phi_out[i]) return fail(HJX_ERR_INVALID_ARG, "phi0[%d] or phi_out[%d] is NULL", i, i);
         if (target && target[i] && target[i] == phi_out[i])
             return fail(HJX_ERR_INVALID_ARG, "target[%d] aliases phi_out[%d]", i, i);
+        if (std::memcmp(&b->hp[(size_t)i * 8], b->probs[i]->ham.p, sizeof(double) * 8) != 0)
+            return fail(HJX_ERR_INVALID_ARG, "member %d's parameters changed since the batch was made", i);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hjx_status st = batch_schedule(b, t1);

@@ -76,7 +76,8 @@ SIGNATURES = {
     "hjx_step": ([_P, _P, _P, ctypes.c_double, _P], ctypes.c_int),
     "hjx_problem_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "hjx_problem_get_tile": ([_P] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
-    "hjx_tune": ([_P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hjx_tune": ([_P, _P, ctypes.c_int32, ctypes.c_char_p, _P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hjx_problem_set_params": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hjx_solve": ([_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(Stats)], ctypes.c_int),
     "hjx_tape_create": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)],
                         ctypes.c_int),
@@ -185,10 +186,16 @@ def hjx_problem_get_tile(handle):
     return tuple(x.value for x in v)
 
 
-def hjx_tune(handle, phi_ptr, reps=5, stream=None):
+def hjx_tune(handle, phi_ptr, reps=5, stream=None, cache_path=None):
     us = ctypes.c_double()
-    _check(lib().hjx_tune(handle, phi_ptr, int(reps), _stream(stream), ctypes.byref(us)))
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().hjx_tune(handle, phi_ptr, int(reps), cp, _stream(stream), ctypes.byref(us)))
     return us.value
+
+
+def hjx_problem_set_params(handle, params):
+    v = (ctypes.c_double * 8)(*[float(x) for x in params][:8])
+    _check(lib().hjx_problem_set_params(handle, v))
 
 
 def hjx_dissipation(handle, dim, stream=None):
@@ -339,6 +346,7 @@ class Problem:
         self.handle = None
         self.handle = hjx_problem_create(*descriptors(gmin, gmax, n, periodic, ham, params, scheme, rk, cfl,
                                                       dtype, restrict, dissipation))
+        self._params = tuple(float(v) for v in params)
 
     @classmethod
     def from_workload(cls, w, dtype=None):
@@ -371,11 +379,22 @@ class Problem:
             shape = (TILE_PLANE_MARCH,) + tuple(shape)
         hjx_problem_set_tile(self.handle, *shape)
 
-    def tune(self, phi, reps=5, stream=None):
+    def tune(self, phi, reps=5, stream=None, cache=None):
         """Pick the fastest stage-kernel launch shape for this problem; returns
-        (tile, mean launch time in us)."""
-        us = hjx_tune(self.handle, self._t(phi, "phi"), reps, stream)
+        (tile, mean launch time in us).  cache: a tuning-cache file (None: the
+        HJX_TUNE_CACHE environment variable, "": none)."""
+        us = hjx_tune(self.handle, self._t(phi, "phi"), reps, stream, cache)
         return self.tile, us
+
+    @property
+    def params(self):
+        """The Hamiltonian's parameters (a tuple of the kind's count)."""
+        return self._params
+
+    @params.setter
+    def params(self, values):
+        hjx_problem_set_params(self.handle, values)
+        self._params = tuple(float(v) for v in values)
 
     def dissipation(self, stream=None):
         return hjx_dissipation(self.handle, self.dim, stream)
@@ -447,14 +466,18 @@ class Tape:
         self.has_target = target is not None
         return out, st.as_dict()
 
-    def adjoint(self, dL_dphiT, stream=None):
-        """Returns (dL/dphi0, dL/dtarget or None, dL/dparams list of 8)."""
+    def adjoint(self, dL_dphiT, stream=None, sum_target=False):
+        """Returns (dL/dphi0, dL/dtarget or None, dL/dparams list of 8).  With
+        sum_target (the solve's target was phi0 itself) the library writes
+        dL/dphi0 + dL/dtarget into the first array and the second is None."""
         P = self.problem
         g0 = torch.empty_like(dL_dphiT)
-        gt = torch.empty_like(dL_dphiT) if self.has_target else None
+        if sum_target and not self.has_target:
+            raise ValueError("sum_target: the solve had no target")
+        gt = g0 if sum_target else (torch.empty_like(dL_dphiT) if self.has_target else None)
         dp = hjx_adjoint(P.handle, self.handle, P._t(dL_dphiT, "dL_dphiT"), P._t(g0, "dL_dphi0"),
                          P._t(gt, "dL_dtarget"), stream)
-        return g0, gt, dp
+        return g0, (None if sum_target else gt), dp
 
 
 class Batch:
@@ -663,27 +686,49 @@ class Claw:
 
 
 class HjxSolve(torch.autograd.Function):
-    """phi(t1) = solve(phi0) with min-with-target against phi0 itself (the
-    reachable-tube setting) or no target; backward through hjx_adjoint.
-    Usage: HjxSolve.apply(phi0, problem, t1, with_target, ckpt_every).
-    The gradient of the Hamiltonian parameters of the last backward call is
-    left in problem.param_grad."""
+    """phi(t1) = solve(phi0; params) from 0 to t1, with min-with-target
+    against phi0 itself (the reachable-tube setting) or no target, as a
+    differentiable function of phi0 and of the Hamiltonian's parameters.
+
+    Usage: HjxSolve.apply(phi0, params, problem, t1, with_target=True, ckpt_every=8)
+      phi0    tensor of the problem's shape and dtype on the device;
+      params  1-D tensor of the kind's parameter count (any device and
+              float dtype): the problem's parameters are set to it for the
+              solve (hjx_problem_set_params);
+      problem a Problem; returns phi(t1).
+    backward runs hjx_adjoint on the tape of the forward solve (checkpoints
+    every ckpt_every steps) and returns dL/dphi0 (through both the initial
+    value and the target when phi0 is the target; the library adds the two)
+    and dL/dparams (float64 from the library, cast to params' dtype and
+    device).  The tape lives as long as the graph node, so backward may run
+    again with retain_graph; phi0 is saved for backward, so changing it in
+    place before backward raises."""
 
     @staticmethod
-    def forward(ctx, phi0, problem, t1, with_target=True, ckpt_every=8):
+    def forward(ctx, phi0, params, problem, t1, with_target=True, ckpt_every=8):
+        values = [float(v) for v in params.detach().to("cpu", torch.float64).reshape(-1)]
+        problem.params = values
         tape = problem.tape(t1, 0.0, ckpt_every)
-        phi0c = phi0.detach().contiguous()
-        out, _ = tape.solve(phi0c, target=phi0c if with_target else None)
+        x = phi0.detach()
+        if not x.is_contiguous():
+            x = x.contiguous()
+        out, _ = tape.solve(x, target=x if with_target else None)
+        ctx.save_for_backward(x)     # the target the reverse sweep replays
         ctx.tape = tape
-        ctx.phi0 = phi0c  # the target must stay alive until backward
+        ctx.values = values
+        ctx.params_like = (params.dtype, params.device, params.shape)
         ctx.with_target = with_target
         return out
 
     @staticmethod
     def backward(ctx, g):
-        g0, gt, dp = ctx.tape.adjoint(g.contiguous())
-        ctx.tape.problem.param_grad = dp
-        if ctx.with_target:
-            g0 = g0 + gt
-        ctx.tape.close()
-        return g0, None, None, None, None
+        (x,) = ctx.saved_tensors      # raises if phi0 changed in place since forward
+        tape = ctx.tape
+        tape.problem.params = ctx.values  # the parameters the tape was made with
+        g0, _, dp = tape.adjoint(g.contiguous(), sum_target=ctx.with_target)
+        dtype, device, shape = ctx.params_like
+        n = 1
+        for v in shape:
+            n *= v
+        gp = torch.tensor(dp[:n], dtype=torch.float64).to(device=device, dtype=dtype).reshape(shape)
+        return g0, gp, None, None, None, None

@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2411_03501_amd import inputs
-from helpers import gpu_problem, oracle_problem, to_dev, to_host
+from helpers import as_input, gpu_problem, oracle_problem, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -44,9 +44,11 @@ CASES = {
 }
 
 
-def _setup(w):
-    phi0 = inputs.initial_surface(w) + 0.05 * inputs.smooth_field(w.n, 71)
-    Po = oracle_problem(w)
+def _setup(w, dtype="f64"):
+    """Initial data (binary32 for an FP32 solve: the values it receives) and
+    the oracle problem, which takes ENO choices in the solver's precision."""
+    phi0 = as_input(inputs.initial_surface(w) + 0.05 * inputs.smooth_field(w.n, 71), dtype)
+    Po = oracle_problem(w, decide=dtype)
     eps = 1.5 * max(O.grid(Po, 0)[0], O.grid(Po, 1)[0])
     return phi0, Po, eps
 
@@ -63,8 +65,8 @@ def _gpu_grads(w, dtype, phi0, eps, ckpt=3, dL_dphiT=None, mode=None):
         loss, g = P.loss_volume(out, eps)
     else:
         loss, g = None, to_dev(dL_dphiT, TDT[dtype])
-    g0, gt, dp = tape.adjoint(g)
-    total = g0 + gt if gt is not None else g0
+    # with a target (phi0 itself) the library sums dL/dphi0 and dL/dtarget
+    total, _, dp = tape.adjoint(g, sum_target=w.with_target)
     res = (loss, to_host(total), dp, st, to_host(out))
     tape.close()
     P.close()
@@ -75,9 +77,7 @@ def _gpu_grads(w, dtype, phi0, eps, ckpt=3, dL_dphiT=None, mode=None):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_matches_oracle_directional_derivatives(case, dtype):
     w = CASES[case]
-    if dtype == "f32" and w.scheme in ("eno2", "eno3"):
-        pytest.skip("ENO stencil choices on near-ties differ between precisions; FP64 covers ENO")
-    phi0, Po, eps = _setup(w)
+    phi0, Po, eps = _setup(w, dtype)
     say(f"adjoint {case} {dtype} n={w.n}")
     loss, g, dp, st, out = _gpu_grads(w, dtype, phi0, eps)
     # the loss itself
@@ -99,6 +99,71 @@ def test_adjoint_matches_oracle_directional_derivatives(case, dtype):
         _, ref, _ = O.cs_solve_loss(Po, phi0, w.t1, dparams=e, with_target=w.with_target, eps_h=eps)
         assert abs(dp[m] - ref) <= TOL[dtype] * max(abs(ref), 1e-2), (case, dtype, m, dp[m], ref)
     assert all(v == 0.0 for v in dp[len(w.params):])
+
+
+GRAD_W = inputs.DUBINS3D.with_(n=(41, 41, 40))
+GRAD_SEEDS = tuple(range(101, 109))
+
+
+@pytest.fixture(scope="module")
+def oracle_jvps():
+    """The oracle's complex-step directional derivatives of the volume loss
+    after the game's whole horizon (t = 2.8, 350 steps at 41 x 41 x 40, with
+    min-with-target): along 8 seeded smooth directions of phi0 and along each
+    of the 4 parameters (v_e, v_p, wbar_e, wbar_p), from the binary32 initial
+    data both precisions start from."""
+    O.set_threads(min(16, O.max_threads()))
+    w = GRAD_W
+    phi0, Po, eps = _setup(w, "f32")
+    dirs, params = [], []
+    for seed in GRAD_SEEDS:
+        _, ref, steps = O.cs_solve_loss(Po, phi0, w.t1, dphi0=inputs.smooth_field(w.n, seed), with_target=True,
+                                        eps_h=eps)
+        say(f"  oracle JVP along direction {seed}: {ref:.6e} ({steps} steps)")
+        dirs.append(ref)
+    for m in range(4):
+        e = np.zeros(4)
+        e[m] = 1.0
+        _, ref, _ = O.cs_solve_loss(Po, phi0, w.t1, dparams=e, with_target=True, eps_h=eps)
+        say(f"  oracle JVP along parameter {m}: {ref:.6e}")
+        params.append(ref)
+    return phi0, eps, steps, dirs, params
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gradient_workload_against_oracle_jvps(oracle_jvps, dtype):
+    """The gradient workload's setting over its whole horizon (checkpoint
+    every 8 steps) at the largest grid the complex-step oracle takes in
+    minutes: the adjoint's directional derivatives against the oracle's.
+
+    FP64: every one within 1e-3 relative.  FP32: the binary32 forward
+    trajectory itself ends about 1e-3 of the phi range from the oracle's
+    at this horizon (tests/test_oracle_sensitivity.py), so a direction along
+    which the derivative nearly cancels cannot be held to 1e-3 of its own
+    size; there each directional derivative is held to 1e-3 of the largest
+    value its direction could give, |g|_2 |delta|_2, and every parameter
+    derivative (none of which cancels) to 1e-3 relative."""
+    phi0, eps, steps, dirs, params = oracle_jvps
+    w = GRAD_W
+    say(f"gradient workload {dtype} n={w.n} t1={w.t1}")
+    loss, g, dp, st, _ = _gpu_grads(w, dtype, phi0, eps, ckpt=8)
+    assert st["steps"] == steps
+    gn = float(np.sqrt(np.sum(g * g)))
+    bad = []
+    for seed, ref in zip(GRAD_SEEDS, dirs):
+        delta = inputs.smooth_field(w.n, seed)
+        got = float(np.sum(g * delta))
+        scale = abs(ref) if dtype == "f64" else max(abs(ref), gn * float(np.sqrt(np.sum(delta * delta))))
+        say(f"  direction {seed}: adjoint {got:.6e} oracle {ref:.6e} rel {abs(got - ref) / abs(ref):.1e} "
+            f"(of the scale {abs(got - ref) / scale:.1e})")
+        if abs(got - ref) > 1e-3 * scale:
+            bad.append(("direction", seed, got, ref))
+    for m, ref in enumerate(params):
+        say(f"  parameter {m}: adjoint {dp[m]:.6e} oracle {ref:.6e} rel {abs(dp[m] - ref) / abs(ref):.1e}")
+        if abs(dp[m] - ref) > 1e-3 * abs(ref):
+            bad.append(("parameter", m, dp[m], ref))
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "car4_weno5_rk3", "normal2d_first_rk1"])
@@ -150,17 +215,78 @@ def test_stored_and_recomputed_derivatives_give_the_same_bits(case, dtype):
 
 
 def test_autograd_function():
+    """HjxSolve as a torch.autograd.Function of phi0 and of the Hamiltonian's
+    parameters: loss.backward() fills both gradients, and they equal the C
+    call's (dL/dphi0 + dL/dtarget, summed by the library, and dL/dparams);
+    the parameter gradient matches the oracle's complex-step derivative."""
     w = CASES["dubins3_weno5_rk3"]
     phi0, Po, eps = _setup(w)
-    P = gpu_problem(w, "f64")
+    P = gpu_problem(w, "f64", params=(4.0, 4.0, 0.5, 0.5))  # the forward sets the parameters below
     x = to_dev(phi0, torch.float64).requires_grad_(True)
-    out = hjx.HjxSolve.apply(x, P, w.t1, True, 4)
+    params = torch.tensor(w.params, dtype=torch.float64, requires_grad=True)
+    out = hjx.HjxSolve.apply(x, params, P, w.t1, True, 4)
     vol = float(np.prod([O.grid(Po, d)[0] for d in range(w.dim)]))
     loss = vol * torch.sigmoid(-out / eps).sum()
-    loss.backward()
+    loss.backward(retain_graph=True)
     _, g, dp, _, _ = _gpu_grads(w, "f64", phi0, eps)
     assert np.abs(to_host(x.grad) - g).max() <= 1e-12 * np.abs(g).max()
-    assert np.allclose(P.param_grad, dp, rtol=1e-10, atol=1e-12)
+    assert params.grad is not None and params.grad.shape == params.shape
+    assert np.allclose(params.grad.numpy(), dp[:len(w.params)], rtol=1e-10, atol=1e-12)
+    e = np.zeros(len(w.params))
+    e[1] = 1.0
+    _, ref, _ = O.cs_solve_loss(Po, phi0, w.t1, dparams=e, with_target=True, eps_h=eps)
+    assert abs(float(params.grad[1]) - ref) <= 1e-7 * abs(ref)
+    # the library's sum is the sum of the two separate gradients, bit for bit
+    Q = gpu_problem(w, "f64")
+    tape = Q.tape(w.t1, ckpt_every=4)
+    d0 = to_dev(phi0, torch.float64)
+    o, _ = tape.solve(d0, target=d0)
+    _, gl = Q.loss_volume(o, eps)
+    g0, gt, _ = tape.adjoint(gl)
+    summed, none, _ = tape.adjoint(gl, sum_target=True)
+    assert none is None and torch.equal(summed, g0 + gt)
+    tape.close()
+    # the tape outlives backward: a second backward gives the same gradients
+    gx, gp = x.grad.clone(), params.grad.clone()
+    x.grad = None
+    params.grad = None
+    loss.backward()
+    assert torch.equal(x.grad, gx) and torch.equal(params.grad, gp)
+    # phi0 is saved for backward: changing it in place before backward raises
+    out2 = hjx.HjxSolve.apply(x, params, P, w.t1, True, 4)
+    with torch.no_grad():
+        x.add_(0.0)
+    with pytest.raises(RuntimeError):
+        out2.sum().backward()
+
+
+def test_parameters_of_an_existing_problem():
+    """hjx_problem_set_params: a solve after the change equals a solve of a
+    problem created with the new parameters, bit for bit; tapes and batches
+    made before the change refuse to run until the parameters are back."""
+    w = CASES["dubins3_weno5_rk3"]
+    phi0, _, _ = _setup(w)
+    d0 = to_dev(phi0, torch.float64)
+    new = (4.5, 5.5, 0.8, 1.2)
+    P = gpu_problem(w, "f64")
+    tape = P.tape(w.t1, ckpt_every=3)
+    B = hjx.Batch([P])
+    P.params = new
+    a, _ = P.solve(d0, w.t1, target=d0)
+    b, _ = gpu_problem(w, "f64", params=new).solve(d0, w.t1, target=d0)
+    assert torch.equal(a, b)
+    assert P.dissipation() == gpu_problem(w, "f64", params=new).dissipation()
+    with pytest.raises(hjx.HjxError, match="parameters"):
+        tape.solve(d0, target=d0)
+    with pytest.raises(hjx.HjxError, match="parameters"):
+        B.solve([d0], [w.t1], target=[d0])
+    with pytest.raises(hjx.HjxError):        # checked as at create: turn-rate bounds >= 0
+        P.params = (5.0, 5.0, -1.0, 1.0)
+    P.params = w.params
+    out, _ = tape.solve(d0, target=d0)
+    tape.adjoint(torch.ones_like(out))
+    B.close()
+    tape.close()
 
 
 def test_adjoint_argument_rules():

@@ -394,6 +394,48 @@ def test_car4_alpha_closed_form():
     assert math.ceil(1.5 / (0.75 / sum(alpha[d] / full[d] for d in range(4)))) == 170
 
 
+def _dubins3_field(x, y, th, we, wp, ve, vp):
+    """The relative dynamics of the game for controls w_e, w_p (evader's frame)."""
+    return (-ve + vp * math.cos(th) + we * y, vp * math.sin(th) - we * x, wp - we)
+
+
+def test_dubins3_alpha_is_the_largest_speed_over_nodes_and_control_corners():
+    """alpha_d = max over grid nodes and admissible controls of |f_d|: the
+    dynamics are affine in each turn rate, so the corners of the control box
+    attain it; brute force over every node and corner."""
+    n = (7, 8, 9)
+    prm = (2.3, 1.7, 0.6, 1.4)
+    P = O.make_problem([-3, -2, 0], [5, 4, 2 * math.pi], n, periodic=[2], ham="dubins3_pe", params=prm)
+    ax = [O.grid(P, d)[1] for d in range(3)]
+    ve, vp, wbe, wbp = prm
+    best = np.zeros(3)
+    for x in ax[0]:
+        for y in ax[1]:
+            for th in ax[2]:
+                for we in (-wbe, wbe):
+                    for wp in (-wbp, wbp):
+                        best = np.maximum(best, np.abs(_dubins3_field(x, y, th, we, wp, ve, vp)))
+    np.testing.assert_allclose(O.alpha(P), best, rtol=1e-15, atol=0)
+    dxs = [O.grid(P, d)[0] for d in range(3)]
+    assert O.cfl_dt(P) == pytest.approx(0.75 / sum(best[d] / dxs[d] for d in range(3)), rel=1e-15)
+
+
+def test_car4_alpha_is_the_largest_speed_over_nodes_and_control_corners():
+    """The same brute force for the 4-D car: f = (v cos th, v sin th, w, a),
+    every node and every corner of the box |w| <= wbar, |a| <= abar."""
+    n = (4, 5, 9, 7)
+    prm = (0.7, 1.3)
+    P = O.make_problem([-5, -5, 0, -0.5], [5, 5, 2 * math.pi, 2], n, periodic=[2], ham="dubins4", params=prm)
+    ax = [O.grid(P, d)[1] for d in range(4)]
+    best = np.zeros(4)
+    for th in ax[2]:
+        for v in ax[3]:
+            for w_ in (-prm[0], prm[0]):
+                for a_ in (-prm[1], prm[1]):
+                    best = np.maximum(best, np.abs((v * math.cos(th), v * math.sin(th), w_, a_)))
+    np.testing.assert_allclose(O.alpha(P), best, rtol=1e-15, atol=0)
+
+
 # --------------------------------------------------------------------------
 # LF reduces to upwinding for a linear Hamiltonian (Sec. IV-A, IV-D)
 

@@ -9,7 +9,8 @@ import pytest
 
 import oracle as O
 from paper_2411_03501_amd import inputs
-from helpers import assert_close, gpu_problem, near_zero_mask, oracle_problem, to_dev, to_host
+from helpers import (as_input, assert_close, gpu_problem, near_zero_mask, oracle_binary32_state, oracle_problem,
+                     to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -57,12 +58,16 @@ def _field(w, kind, seed):
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_rhs_parity(case, scheme, dtype):
+    """The spatial operator on smooth and on rough (uniform noise) data.  In
+    FP32 the oracle sees the binary32 inputs the GPU sees and takes the ENO
+    stencil choices in binary32 as the kernel does (Sec. IV-B: a choice
+    between candidates closer than binary32 rounding is the precision's to
+    make); every value is still formed in FP64."""
     w = CASES[case].with_(scheme=scheme)
-    kinds = ["smooth", "rough"] if (dtype == "f64" or scheme in ("first", "weno5")) else ["smooth"]
-    for kind in kinds:
+    for kind in ("smooth", "rough"):
         say(f"rhs {case} {scheme} {dtype} {kind} n={w.n}")
-        phi = _field(w, kind, seed=101)
-        ref = O.rhs(oracle_problem(w), phi)
+        phi = as_input(_field(w, kind, seed=101), dtype)
+        ref = O.rhs(oracle_problem(w, decide=dtype), phi)
         P = gpu_problem(w, dtype)
         got = to_host(P.rhs(to_dev(phi, TDT[dtype])))
         torch.cuda.synchronize()
@@ -113,20 +118,30 @@ SOLVES = [
 @pytest.mark.parametrize("name,w,_", SOLVES, ids=[s[0] for s in SOLVES])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_solve_parity(name, w, _, dtype):
-    if dtype == "f32" and w.scheme in ("eno2", "eno3"):
-        pytest.skip("ENO stencil choices on near-ties differ between precisions; FP64 covers ENO")
+    """Whole solves at reduced sizes from the same (in FP32: binary32) initial
+    data, the oracle taking ENO choices in the solver's precision.  FP32:
+    within 1e-4 of the range, or within how far the oracle itself moves when
+    its state is stored in binary32 between steps, whichever is larger (over
+    tens of ENO steps that is the larger: the choices flip with the
+    rounding), and signs beyond two cells."""
     say(f"solve {name} {dtype} n={w.n} t1={w.t1}")
-    phi0 = inputs.initial_surface(w)
-    Po = oracle_problem(w)
-    ref, steps, dt0 = O.solve(Po, phi0, w.t1, target=phi0 if w.with_target else None)
+    phi0 = as_input(inputs.initial_surface(w), dtype)
+    Po = oracle_problem(w, decide=dtype)
+    tgt = phi0 if w.with_target else None
+    ref, steps, dt0 = O.solve(Po, phi0, w.t1, target=tgt)
+    floor = 0.0
+    if dtype == "f32":
+        r32, n32 = oracle_binary32_state(Po, phi0, w.t1, target=tgt)
+        assert n32 == steps
+        floor = float(np.abs(r32 - ref).max())
     P = gpu_problem(w, dtype)
     d0 = to_dev(phi0, TDT[dtype])
     out, st = P.solve(d0, w.t1, target=d0 if w.with_target else None)
     assert st["steps"] == steps
     assert abs(st["dt"] - dt0) <= 1e-12 * dt0 if dtype == "f64" else abs(st["dt"] - dt0) <= 1e-5 * dt0
     assert st["t_final"] == w.t1
-    err = assert_close(to_host(out), ref, dtype, w.periodic, what=f"solve {name}")
-    say(f"  steps {steps} max err {err:.3e}")
+    err = assert_close(to_host(out), ref, dtype, w.periodic, what=f"solve {name}", f32_floor=floor)
+    say(f"  steps {steps} max err {err:.3e} (oracle with a binary32 state: {floor:.3e})")
 
 
 @pytest.mark.parametrize("wname", ["dubins3d", "car4d"])
@@ -300,6 +315,69 @@ def test_results_do_not_depend_on_the_tile(case, scheme):
                 assert torch.equal(d, ref_step), f"step differs for tile {tile} ({dtype})"
 
 
+@pytest.mark.parametrize("case,scheme,rk,with_target", [
+    ("normal2d", "first", 1, False), ("normal2d", "first", 1, True), ("normal3d", "eno2", 2, True),
+    ("dubins3", "weno5", 3, True), ("car4", "weno5", 3, False)])
+def test_solve_graph_replay_gives_the_same_bits(monkeypatch, case, scheme, rk, with_target):
+    """hjx_solve captures its stepping launches on the second identical call
+    and replays them afterwards: every call gives the bits of direct
+    launches (HJX_SOLVE_GRAPH=0), out of place and in place, and the oracle's
+    result; a NaN written into phi0 between replays is still reported."""
+    w = CASES[case].with_(scheme=scheme, rk=rk)
+    phi = inputs.smooth_field(w.n, 17, amplitude=1.5)
+    t1 = 6.5 * O.cfl_dt(oracle_problem(w))
+    P = gpu_problem(w, "f64")
+    d0 = to_dev(phi, torch.float64)
+    tgt = to_dev(phi, torch.float64) if with_target else None
+    out = torch.empty_like(d0)
+    monkeypatch.setenv("HJX_SOLVE_GRAPH", "0")
+    ref, st = P.solve(d0, t1, target=tgt, out=out)
+    ref = ref.clone()
+    assert st["steps"] == 7
+    monkeypatch.delenv("HJX_SOLVE_GRAPH")
+    for k in range(4):   # direct, capture, replay, replay
+        got, st = P.solve(d0, t1, target=tgt, out=out)
+        assert st["steps"] == 7 and torch.equal(got, ref), (case, k)
+    x = torch.empty_like(d0)
+    for k in range(3):   # in place
+        x.copy_(d0)
+        P.solve(x, t1, target=tgt, out=x)
+        assert torch.equal(x, ref), (case, "in place", k)
+    oref, steps, _ = O.solve(oracle_problem(w), phi, t1, target=phi if with_target else None)
+    assert_close(to_host(ref), oref, "f64", w.periodic, what=f"graph solve {case}")
+    d0[0] = float("nan")
+    with pytest.raises(hjx.HjxError) as e:
+        P.solve(d0, t1, target=tgt, out=out)
+    assert e.value.status == hjx.HJX_ERR_NONFINITE
+    P.close()
+
+
+def test_tune_cache_file(tmp_path):
+    """hjx_tune with a cache file: the first problem is tuned and recorded;
+    a second problem of the same kind takes the recorded shape without
+    timing; another size adds a line; lines that do not parse are skipped."""
+    path = tmp_path / "tune.txt"
+    path.write_text("hjx-tune 1 garbage\nnot a cache line\n")
+    w = inputs.DUBINS3D.with_(n=(23, 21, 19))
+    d = to_dev(inputs.initial_surface(w), torch.float32)
+    P = gpu_problem(w, "f32")
+    tile, us = P.tune(d, reps=1, cache=str(path))
+    lines = [l for l in path.read_text().splitlines() if " | " in l]
+    assert len(lines) == 1 and us > 0
+    Q = gpu_problem(w, "f32")
+    Q.tile = (0, 5, 3, 1)
+    tile2, us2 = Q.tune(d, reps=1, cache=str(path))
+    assert tile2 == tile and us2 == pytest.approx(us, rel=1e-3)
+    assert len([l for l in path.read_text().splitlines() if " | " in l]) == 1
+    w2 = w.with_(n=(25, 21, 19))
+    R = gpu_problem(w2, "f32")
+    R.tune(to_dev(inputs.initial_surface(w2), torch.float32), reps=1, cache=str(path))
+    assert len([l for l in path.read_text().splitlines() if " | " in l]) == 2
+    a, _ = P.solve(d, 0.3, target=d)
+    b, _ = gpu_problem(w, "f32").solve(d, 0.3, target=d)
+    assert torch.equal(a, b)
+
+
 def test_tile_validation():
     P = gpu_problem(CASES["dubins3"], "f32")
     for bad in [(0, 4, 1), (17, 16, 1), (8, 8, 0)]:
@@ -339,13 +417,14 @@ def test_full_size_full_horizon_properties(wname, dtype):
     reflection symmetry (x, y, theta) -> (x, -y, -theta) of both games, the
     tube property phi(T) <= phi0, and FP32 against FP64.
 
-    Over these long horizons the scheme amplifies rounding: the exact FP64
-    oracle started from phi0 rounded to FP32-sized relative noise ends
-    1.2e-3 of the phi range away from itself on dubins3d at t = 2.8, and
-    its own reflection asymmetry reaches 1e-7 on a 41x41x40 grid.  So the
-    FP32 path is held to sign agreement beyond two cells of the zero set
-    (exactly) and to 1e-2 of the range in max-abs; the 1e-4 rule is checked
-    on single full-size steps and on whole solves at reduced sizes."""
+    Over these long horizons the scheme amplifies rounding: the FP64 oracle
+    perturbed by binary32-sized noise moves by more than 1e-4 of the phi
+    range, and its own reflection asymmetry passes 1e-10
+    (tests/test_oracle_sensitivity.py).  So the FP32 path is held to sign
+    agreement beyond two cells of the zero set (exactly) and to 1e-2 of the
+    range in max-abs; the 1e-4 rule is checked on single full-size steps
+    and on whole solves at reduced sizes.  dubins3d is also compared with
+    the oracle itself over the whole horizon below."""
     w = inputs.WORKLOADS[wname]
     say(f"full horizon {wname} {dtype} n={w.n} t1={w.t1}")
     phi0 = inputs.initial_surface(w)
@@ -380,6 +459,58 @@ def test_full_size_full_horizon_properties(wname, dtype):
         assert flips == 0
         assert err <= 1e-2 * rng
     say(f"  steps {st['steps']} asymmetry {sym:.3e} tile {P.tile}")
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_full_horizon_against_the_oracle():
+    """dubins3d at its full size, 101^3 nodes, over the whole horizon: 874
+    WENO5 + LF + TVD-RK3 steps to t = 2.8 with min-with-target (Sec. V,
+    Sec. VI), GPU FP64 and FP32 in the benchmark's launch shape against the
+    FP64 oracle, node by node.
+
+    At this horizon the oracle is not a fixed point to 1e-10: rounding-level
+    differences grow through the scheme (tests/test_oracle_sensitivity.py).
+    So the oracle is run twice, from phi0 and from phi0 perturbed by 1e-15
+    relative, and its own movement m is the scale of the FP64 bound:
+      * both paths take the oracle's 874 steps;
+      * FP64: max |gpu - oracle| <= 10 m, and no sign flip beyond two cells;
+      * FP32: max |gpu - oracle| <= 1e-2 of the range, and no sign flip
+        beyond two cells."""
+    w = inputs.DUBINS3D
+    O.set_threads(min(16, O.max_threads()))
+    phi0 = inputs.initial_surface(w)
+    Po = oracle_problem(w)
+
+    def progress(tag):
+        return lambda k, t: say(f"  oracle {tag}: {k} steps, t = {t:.4f}")
+
+    say(f"full horizon vs oracle: dubins3d n={w.n} t1={w.t1}")
+    ref, steps = O.solve_in_parts(Po, phi0, w.t1, target=phi0, part=100, report=progress("phi0"))
+    assert steps == 874
+    pert = phi0 * (1 + 1e-15 * np.random.default_rng(5).uniform(-1, 1, size=phi0.shape))
+    other, _ = O.solve_in_parts(Po, pert, w.t1, target=pert, part=100, report=progress("phi0 (1 + 1e-15 u)"))
+    m = np.abs(other - ref).max()
+    rng = ref.max() - ref.min()
+    far = ~near_zero_mask(ref, w.periodic)
+    say(f"  oracle's own movement under a 1e-15 perturbation: {m:.3e}")
+    for dtype in ("f64", "f32"):
+        P = gpu_problem(w, dtype)
+        d0 = to_dev(phi0, TDT[dtype])
+        P.tune(d0, reps=2)
+        out, st = P.solve(d0, w.t1, target=d0)
+        got = to_host(out)
+        err = np.abs(got - ref).max()
+        flips = int((far & (np.sign(got) != np.sign(ref))).sum())
+        say(f"  {dtype} tile {P.tile}: steps {st['steps']}, max |gpu - oracle| {err:.3e} "
+            f"({err / rng:.1e} of the range), nodes above 1e-10: {(np.abs(got - ref) > 1e-10).mean():.2%}, "
+            f"sign flips beyond two cells {flips}")
+        assert st["steps"] == steps
+        assert flips == 0
+        if dtype == "f64":
+            assert err <= 10 * m, f"FP64 {err:.3e} against the oracle's own movement {m:.3e}"
+        else:
+            assert err <= 1e-2 * rng
+        P.close()
 
 
 def test_self_convergence_under_refinement():
