@@ -429,6 +429,22 @@ hjx_status hjx_shape(const hjx_grid_desc *grid, const hjx_shape_desc *shape, int
 hjx_status hjx_shape_batch(int32_t n, const hjx_grid_desc *grids, const hjx_shape_desc *shapes, int32_t dtype,
                            void *const *phi_out, void *stream);
 
+/* hjx_shape_batch for callers that cannot allocate device memory: code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same construction with the same bits, but the n descriptors are staged
+ * in a fixed array of the library (HJX_SHAPE_NOALLOC_MAX members: a
+ * file-scope device array, one on every GPU the library runs on, held until
+ * the process ends) and in static host storage, so the call allocates
+ * nothing.  1 <= n <= HJX_SHAPE_NOALLOC_MAX, else HJX_ERR_INVALID_ARG.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * descriptors (they are rewritten before each launch; nothing needs to start
+ * at zero).  Calls that overlap on one GPU would race for it, so the library
+ * runs one such call at a time per process, each holding the array until its
+ * kernel has finished (the call synchronises `stream`). */
+#define HJX_SHAPE_NOALLOC_MAX 1024
+hjx_status hjx_shape_batch_noalloc(int32_t n, const hjx_grid_desc *grids, const hjx_shape_desc *shapes,
+                                   int32_t dtype, void *const *phi_out, void *stream);
+
 typedef enum {
     HJX_OP_UNION = 0,        /* min(a, b) */
     HJX_OP_INTERSECTION = 1, /* max(a, b) */

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -2297,6 +2298,37 @@ hjx_status hjx_shape_batch(int32_t n, const hjx_grid_desc *grids, const hjx_shap
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dev);
     if (e != hipSuccess) return fail(HJX_ERR_DEVICE, "hjx_shape_batch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+hjx_status hjx_shape_batch_noalloc(int32_t n, const hjx_grid_desc *grids, const hjx_shape_desc *shapes,
+                                   int32_t dtype, void *const *phi_out, void *stream)
+{
+    static_assert(HJX_SHAPE_NOALLOC_MAX == kShapeNoAllocMax, "the header states the array's size");
+    if (n < 1 || n > HJX_SHAPE_NOALLOC_MAX)
+        return fail(HJX_ERR_INVALID_ARG, "n = %d outside [1, %d], the size of the fixed descriptor array", n,
+                    HJX_SHAPE_NOALLOC_MAX);
+    if (!grids || !shapes || !phi_out) return fail(HJX_ERR_INVALID_ARG, "NULL array");
+    if (dtype != HJX_F32 && dtype != HJX_F64) return fail(HJX_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    // host staging in static storage too: the call allocates nothing anywhere;
+    // one call at a time per process holds it and the device array
+    static std::mutex mu;
+    static ShapeMember host[kShapeNoAllocMax];
+    std::lock_guard<std::mutex> lock(mu);
+    long largest = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!phi_out[k]) return fail(HJX_ERR_INVALID_ARG, "phi_out[%d] is NULL", k);
+        hjx_status st = shape_args(&grids[k], &shapes[k], &host[k].a);
+        if (st != HJX_OK) return fail(st, "member %d: %s", k, hjx_last_error());
+        host[k].out = phi_out[k];
+        largest = std::max(largest, host[k].a.total);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ShapeMember *dev = nullptr;
+    HIP_TRY(shape_noalloc_scratch(&dev));
+    HIP_TRY(hipMemcpyAsync(dev, host, (size_t)n * sizeof(ShapeMember), hipMemcpyHostToDevice, s));
+    HIP_TRY(dtype == HJX_F32 ? launch_shape_batch_f32(dev, n, largest, s) : launch_shape_batch_f64(dev, n, largest, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return ok();
 }
 

@@ -310,6 +310,11 @@ struct ShapeMember {
     void *out;
 };
 
+// hjx_shape_batch_noalloc's descriptor array (a file-scope device array of
+// this many members per GPU) and its device address on the current device
+constexpr int kShapeNoAllocMax = 1024;
+hipError_t shape_noalloc_scratch(ShapeMember **out);
+
 hipError_t launch_shape_f32(const ShapeArgs &a, float *out, hipStream_t s);
 // members: device array of nm (<= 65535) members; largest: the most nodes of one member
 hipError_t launch_shape_batch_f32(const ShapeMember *members, int nm, long largest, hipStream_t s);

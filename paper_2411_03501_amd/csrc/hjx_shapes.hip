@@ -13,6 +13,7 @@
 // complement -a, subtraction max(a, -b).  All kernels stream one value per
 // node: bound by HBM.
 #include <algorithm>
+#include <mutex>
 
 #include "hjx_internal.h"
 
@@ -143,6 +144,32 @@ hipError_t launch_shape_batch_f64(const ShapeMember *members, int nm, long large
     hipLaunchKernelGGL((shape_batch_kernel<double>), batch_grid(nm, largest), dim3(256), 0, s, members, nm);
     return hipGetLastError();
 }
+// The descriptor staging of hjx_shape_batch_noalloc: a file-scope device
+// array of kShapeNoAllocMax members, one copy on every GPU the library runs
+// on, held until the process ends.  On the host its name is only a stand-in:
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) ShapeMember scratch[kShapeNoAllocMax];
+
+hipError_t shape_noalloc_scratch(ShapeMember **out)
+{
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static ShapeMember *addr[kDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<ShapeMember *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 hipError_t launch_shape_op_f32(int op, const float *a, const float *b, float *out, long n, hipStream_t s)
 {
     hipLaunchKernelGGL((shape_op_kernel<float>), dim3(blocks_for(n)), dim3(256), 0, s, op, a, b, out, n);

@@ -102,6 +102,8 @@ SIGNATURES = {
     "hjx_shape_op": ([ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_int64, _P], ctypes.c_int),
     "hjx_shape_batch": ([ctypes.c_int32, ctypes.POINTER(GridDesc), ctypes.POINTER(ShapeDesc), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_void_p), _P], ctypes.c_int),
+    "hjx_shape_batch_noalloc": ([ctypes.c_int32, ctypes.POINTER(GridDesc), ctypes.POINTER(ShapeDesc), ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_void_p), _P], ctypes.c_int),
     "hjx_claw_create": ([ctypes.POINTER(GridDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                          ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hjx_claw_destroy": ([_P], ctypes.c_int),
@@ -571,10 +573,15 @@ def _shape_desc(ndim, kind, axes, center, radius, weights):
     return d
 
 
-def shape_batch(specs, dtype="f64", outs=None, stream=None):
+SHAPE_NOALLOC_MAX = 1024
+
+
+def shape_batch(specs, dtype="f64", outs=None, stream=None, noalloc=False):
     """Shapes of many grids in one launch (hjx_shape_batch).  specs: dicts
     with gmin, gmax, n and optional periodic, kind, axes, center, radius,
-    weights (as for shape()).  Returns the list of output tensors."""
+    weights (as for shape()).  Returns the list of output tensors.
+    noalloc: through hjx_shape_batch_noalloc (at most SHAPE_NOALLOC_MAX
+    members; the library allocates nothing)."""
     tdt = torch.float32 if dtype in ("f32", torch.float32) else torch.float64
     k = len(specs)
     grids = (GridDesc * k)()
@@ -591,8 +598,8 @@ def shape_batch(specs, dtype="f64", outs=None, stream=None):
         for v in sp["n"]:
             numel *= int(v)
         ptrs[i] = _dev(outs[i], tdt, numel, f"outs[{i}]")
-    _check(lib().hjx_shape_batch(k, grids, descs, HJX_F32 if tdt == torch.float32 else HJX_F64, ptrs,
-                                 _stream(stream)))
+    fn = lib().hjx_shape_batch_noalloc if noalloc else lib().hjx_shape_batch
+    _check(fn(k, grids, descs, HJX_F32 if tdt == torch.float32 else HJX_F64, ptrs, _stream(stream)))
     return outs
 
 
