@@ -68,7 +68,8 @@ def describe(w, rk_steps):
 
 
 # the sources that define the stage kernels (their per-node arithmetic and launch)
-KERNEL_SOURCES = ["paper_2411_03501_amd/csrc/hjx_device.h", "paper_2411_03501_amd/csrc/hjx_kernels.hip"]
+KERNEL_SOURCES = ["paper_2411_03501_amd/csrc/hjx_device.h", "paper_2411_03501_amd/csrc/hjx_tile.h",
+                  "paper_2411_03501_amd/csrc/hjx_kernels.hip"]
 
 
 def strip_comments(src):
@@ -740,7 +741,10 @@ def roofline(w, dtype, st, loop_ms):
     bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
     achieved_gbs = bytes_launch / kern_s / 1e9
     traffic = measured_traffic(w, dtype, st["tile"])
-    kernel_name = "stage_direct_kernel" if st["tile"][0] == 1 else "stage_kernel (plane-march)"
+    if st["tile"][0] == 1:
+        kernel_name = "stage_direct_kernel"
+    else:
+        kernel_name = "stage_tile_kernel" if w.dim >= 3 else "stage_kernel (plane-march)"
     if w.scheme == "weno5":
         return {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
                 "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,

@@ -30,7 +30,9 @@
  *   describes it.  Arguments are validated before anything is enqueued.
  * Threads: a problem handle may be used by one thread at a time; distinct
  *   handles are independent.
- * Limits: 1 <= dim <= 4; 3 <= n[d]; total nodes < 2^31.
+ * Limits: 1 <= dim <= 4; 3 <= n[d]; total nodes < 2^31; in 1-D and 2-D an
+ *   array under 4 GiB, in 3-D a plane of the two fastest axes and in 4-D
+ *   seven of them under 4 GiB (HJX_ERR_UNSUPPORTED at create otherwise).
  * Environment: HJX_MAX_WORKSPACE (bytes), read at every create call, caps
  *   the device workspace one hjx_problem_create, hjx_tape_create or
  *   hjx_batch_create may allocate (HJX_ERR_OOM beyond it; a tape then keeps
@@ -227,8 +229,11 @@ hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, vo
  *   HJX_TILE_PLANE_MARCH: a block covers tx nodes of the fastest axis by ty
  *     nodes of the second-fastest (ty = 1 when dim = 1), stages that plane
  *     tile with its halo in LDS, evaluates each stencil interval once and
- *     marches over `march` nodes of the third axis (ignored when dim < 3);
- *     1 <= tx*ty <= 256;
+ *     marches over `march` nodes of another axis (ignored when dim < 3).
+ *     1-D and 2-D: blocks of tx x ty threads, 1 <= tx*ty <= 256.  3-D and
+ *     4-D: blocks of 512 threads over 1 <= tx*ty <= 512 nodes, the
+ *     intervals of the tile dealt evenly over them, the march along axis 0,
+ *     and axis 1 of a 4-D grid gathered node by node;
  *   HJX_TILE_DIRECT: one thread per node, stencils gathered through the
  *     caches (tx, ty, march ignored); arrays must be under 4 GiB, else
  *     HJX_ERR_UNSUPPORTED.
@@ -240,8 +245,9 @@ hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t 
                                 int32_t *march);
 
 /* Autotuner: times the stage kernel on this problem for a set of candidate
- * launch shapes (row widths that split the fastest axis evenly, 64..256
- * threads per block, march lengths 1..32) and keeps the fastest with
+ * launch shapes (row widths that split the fastest axis evenly, tiles of
+ * 64..256 nodes in 1-D and 2-D and of 512 in 3-D and 4-D, march lengths
+ * 1..32, and the direct variant) and keeps the fastest with
  * hjx_problem_set_tile.  Each candidate is timed on whole RK steps taken
  * from a copy of phi with phi as the target, as in a solve.  phi: device
  * array of the problem's size and dtype, read only.  reps: timed steps per

@@ -259,6 +259,20 @@ bool direct_ok(const GridGeom &g, size_t elem)
     return total * elem < (uint64_t(1) << 32);
 }
 
+// nodes one plane-march block may hold: 512 in 3-D and 4-D (the tile kernel,
+// 512 threads, one node each), 256 in 1-D and 2-D (a thread per node)
+int tile_max_nodes(const GridGeom &g) { return g.dim >= 3 ? 512 : 256; }
+
+// In 3-D and 4-D the tile kernel addresses a plane of the two fastest axes
+// through 32-bit offsets; in 1-D and 2-D every kernel addresses the whole
+// array so.
+bool tile_ok(const GridGeom &g, size_t elem)
+{
+    if (g.dim <= 2) return direct_ok(g, elem);
+    const uint64_t planes = g.dim == 4 ? 7 : 1;  // 4-D: the seven planes of the gathered axis' stencil
+    return planes * (uint64_t)g.n[g.dim - 1] * (uint64_t)g.n[g.dim - 2] * elem < (uint64_t(1) << 32);
+}
+
 Tile default_tile(const GridGeom &g, size_t elem)
 {
     Tile t{};
@@ -270,16 +284,11 @@ Tile default_tile(const GridGeom &g, size_t elem)
     t.variant = large || !direct_ok(g, elem) ? kVariantPlaneMarch : kVariantDirect;
     const int width = large ? 128 : 16;
     const int pieces = (nf + width - 1) / width;
+    const int maxn = tile_max_nodes(g);
     t.tx = std::min((nf + pieces - 1) / pieces, 256);
-    t.ty = g.dim >= 2 ? std::max(1, std::min(256 / t.tx, nm)) : 1;
+    t.ty = g.dim >= 2 ? std::max(1, std::min(maxn / t.tx, nm)) : 1;
     t.march = 1;
-    if (g.dim >= 3) {
-        const int nk = g.n[g.dim - 3];
-        const long outer = g.dim == 4 ? g.n[0] : 1;
-        int m = std::min(large ? 8 : 2, nk);
-        while ((long)((nk + m - 1) / m) * outer > 65535) m *= 2;
-        t.march = m;
-    }
+    if (g.dim >= 3) t.march = std::min(large ? 8 : 2, g.n[0]);  // the tile kernel marches axis 0
     return t;
 }
 
@@ -585,6 +594,12 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
         p->dx[d] = ((grid->periodic_mask >> d) & 1u) ? len / (double)grid->n[d] : len / (double)(grid->n[d] - 1);
     }
     p->elem = scheme->dtype == HJX_F32 ? sizeof(float) : sizeof(double);
+    if (!tile_ok(geometry(p), p->elem)) {
+        release(p);
+        return fail(HJX_ERR_UNSUPPORTED, grid->dim <= 2   ? "a 1-D or 2-D grid's arrays must be under 4 GiB"
+                                         : grid->dim == 3 ? "a plane of the two fastest axes must be under 4 GiB"
+                                                          : "seven planes of the two fastest axes must be under 4 GiB");
+    }
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
@@ -671,13 +686,17 @@ hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int
         return ok();
     }
     if (variant != HJX_TILE_PLANE_MARCH) return fail(HJX_ERR_INVALID_ARG, "unknown tile variant %d", variant);
-    if (tx < 1 || ty < 1 || (int64_t)tx * ty > 256)
-        return fail(HJX_ERR_INVALID_ARG, "tile %d x %d: need 1 <= tx*ty <= 256", tx, ty);
+    const int maxn = tile_max_nodes(g);
+    if (tx < 1 || ty < 1 || (int64_t)tx * ty > maxn)
+        return fail(HJX_ERR_INVALID_ARG, "tile %d x %d: need 1 <= tx*ty <= %d", tx, ty, maxn);
     if (g.dim == 1 && ty != 1) return fail(HJX_ERR_INVALID_ARG, "a 1-D grid needs ty = 1");
     if (march < 1) return fail(HJX_ERR_INVALID_ARG, "march %d < 1", march);
     if (g.dim >= 3) {
-        const int64_t gy = (int64_t)((g.n[g.dim - 3] + march - 1) / march) * (g.dim == 4 ? g.n[0] : 1);
-        if (gy > 65535) return fail(HJX_ERR_INVALID_ARG, "march %d leaves %lld block rows (> 65535)", march, (long long)gy);
+        const int64_t blocks = (int64_t)((g.n[g.dim - 1] + tx - 1) / tx) * ((g.n[g.dim - 2] + ty - 1) / ty) *
+                               ((g.n[0] + march - 1) / march) * (g.dim == 4 ? g.n[1] : 1);
+        if (blocks > (int64_t(1) << 30))
+            return fail(HJX_ERR_INVALID_ARG, "tile %d x %d march %d: %lld blocks (> 2^30)", tx, ty, march,
+                        (long long)blocks);
     }
     p->tile = Tile{tx, ty, g.dim >= 3 ? march : 1, kVariantPlaneMarch};
     return ok();
@@ -790,20 +809,25 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
     const double h = std::isfinite(dt) ? dt : 1.0;
     const GridGeom g = geometry(p);
     const int nf = g.n[g.dim - 1], nm = g.dim >= 2 ? g.n[g.dim - 2] : 1;
-    const int nk = g.dim >= 3 ? g.n[g.dim - 3] : 1;
+    const int nk = g.dim >= 3 ? g.n[0] : 1;  // the tile kernel marches axis 0
     const int outer = g.dim == 4 ? g.n[0] : 1;
 
     std::vector<Tile> cands;
+    const int maxn = tile_max_nodes(g);
     for (int pieces = 1; pieces <= 8; ++pieces) {
         const int tx = (nf + pieces - 1) / pieces;
         if (tx > 256 || (pieces > 1 && tx < 8)) continue;
-        for (int threads : {64, 128, 192, 256}) {
-            int ty = g.dim >= 2 ? std::max(1, std::min(threads / tx, nm)) : 1;
-            if (tx * ty > 256) continue;
+        // the tile kernel (3-D, 4-D) idles a thread per node short of 512:
+        // only full tiles are worth timing there
+        for (int nodes : {64, 128, 192, 256, 384, 512}) {
+            if (nodes > maxn) break;
+            if (g.dim >= 3 && nodes < 512) continue;
+            int ty = g.dim >= 2 ? std::max(1, std::min(nodes / tx, nm)) : 1;
+            if (tx * ty > maxn) continue;
             for (int m : {1, 2, 4, 8, 16, 32}) {
                 if (g.dim < 3 && m > 1) break;
                 if (m > nk && m > 1) break;
-                if ((long)((nk + m - 1) / m) * outer > 65535) continue;
+                if (g.dim <= 2 && (long)((nk + m - 1) / m) * outer > 65535) continue;
                 const Tile t{tx, ty, m, kVariantPlaneMarch};
                 bool seen = false;
                 for (const Tile &c : cands) seen |= c.tx == t.tx && c.ty == t.ty && c.march == t.march;

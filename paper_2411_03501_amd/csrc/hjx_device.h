@@ -60,6 +60,10 @@ __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
 template <typename T>
 __device__ __forceinline__ T vabs(T a) { return a < T(0) ? -a : a; }
 
+// the larger of |a| and |b| in one instruction (abs is a source modifier)
+__device__ __forceinline__ float absmax(float a, float b) { return __builtin_fmaxf(__builtin_fabsf(a), __builtin_fabsf(b)); }
+__device__ __forceinline__ double absmax(double a, double b) { return __builtin_fmax(__builtin_fabs(a), __builtin_fabs(b)); }
+
 // ---------------------------------------------------------------- derivatives
 
 template <typename T>
@@ -195,7 +199,11 @@ __device__ __forceinline__ void weno5_q(T u0, T u1, T u2, T u3, T u4, T &q0, T &
     const T s0 = fmaT(k1312 * A0, A0, k14 * B0 * B0);
     const T s1 = fmaT(k1312 * A1, A1, k14 * B1 * B1);
     const T s2 = fmaT(k1312 * A2, A2, k14 * B2 * B2);
-    const T m = vmax(vmax(vmax(u0 * u0, u1 * u1), vmax(u2 * u2, u3 * u3)), u4 * u4);
+    // max_k u_k^2 as (max_k |u_k|)^2: squaring is monotone in |u| and so is
+    // its rounding, so the two are the same bits; four one-instruction
+    // maxima on |u| replace five squares and four compare-and-selects
+    const T am = absmax(absmax(absmax(u0, u1), absmax(u2, u3)), u4);
+    const T m = am * am;
     const T eps = fmaT(T(1e-6), m, Arith<T>::kEpsFloor);
     const T r0 = Arith<T>::rcp(s0 + eps), r1 = Arith<T>::rcp(s1 + eps), r2 = Arith<T>::rcp(s2 + eps);
     q0 = r0 * r0;
@@ -405,9 +413,12 @@ __device__ __forceinline__ T node_bound(const StageArgs<T> &a, const int *j, int
 // kNodeClip in MODE, a restricted update (Sec. VI): L is first clipped to
 // min(L, 0) (a.clip < 0) or max(L, 0) (a.clip > 0).  With kNodeLocal, alpha_d
 // is node_bound at the node instead of the grid maximum a.alpha[d].
+// phi_n, target and mask are read (written) at idx: those of `a`, or the same
+// arrays rebased to where idx counts from (stage_result_at).
 template <typename T, int D, int HAM, int MODE = kNodePlain>
-__device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, const T *pm, const T *pp, T center,
-                                          int idx)
+__device__ __forceinline__ T stage_result_at(const StageArgs<T> &a, const T *phi_n, const T *target,
+                                             unsigned char *mask, const int *j, const T *pm, const T *pp, T center,
+                                             int idx)
 {
 #pragma clang fp contract(off)
     T pbar[D];
@@ -447,13 +458,20 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
         if (a.clip > 0) L = L < T(0) ? T(0) : L;
     }
     T res = a.cb * fmaT(a.dt, L, center);
-    if (a.ca != T(0)) res = fmaT(a.ca, ld32(a.phi_n, idx), res);
-    if (a.target) {
-        const T tg = ld32(a.target, idx);
-        if (a.mask) a.mask[idx] = tg < res;
+    if (a.ca != T(0)) res = fmaT(a.ca, ld32(phi_n, idx), res);
+    if (target) {
+        const T tg = ld32(target, idx);
+        if (mask) mask[idx] = tg < res;
         res = tg < res ? tg : res;
     }
     return res;
+}
+
+template <typename T, int D, int HAM, int MODE = kNodePlain>
+__device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, const T *pm, const T *pp, T center,
+                                          int idx)
+{
+    return stage_result_at<T, D, HAM, MODE>(a, a.phi_n, a.target, a.mask, j, pm, pp, center, idx);
 }
 
 // One node of the direct variant: gather every axis through the caches,

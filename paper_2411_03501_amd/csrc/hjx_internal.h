@@ -32,8 +32,9 @@ struct GridGeom {
 
 // Launch shape of the stage kernel.  A block covers tx nodes of the fastest
 // axis by ty nodes of the second-fastest ("plane tile", staged in LDS with its
-// halo) and marches over `march` consecutive nodes of the third-fastest axis
-// (dim >= 3).  tx * ty <= 256.
+// halo) and, in 3-D and 4-D, marches over `march` consecutive nodes of axis 0.
+// tx * ty <= 256 in 1-D and 2-D; in 3-D and 4-D the tile kernel runs 512
+// threads over tx * ty <= 512 nodes.
 struct Tile {
     int tx, ty, march;
     int variant;  // kVariantPlaneMarch or kVariantDirect
@@ -240,6 +241,22 @@ struct AlphaArgs {
 inline size_t stage_lds_bytes(const Tile &t, size_t elem)
 {
     return elem * ((size_t)(t.ty + 6) * (t.tx + 6) + (size_t)t.ty * (t.tx + 1) + (size_t)(t.ty + 1) * t.tx);
+}
+
+// The tile kernel of 3-D and 4-D grids: the decomposition of its blocks
+// (tiles along the fastest axis and the second, chunks of the marched axis 0,
+// and in 4-D the nodes of the gathered axis 1, which varies fastest) and its
+// LDS: the staged tile with its halo and four one-sided values per node.
+constexpr int kTileNodes = 512;  // nodes of one tile of the 3-D and 4-D tile kernel, at most
+
+struct TileLaunch {
+    int tiles_f, tiles_m, chunks, outer;
+    int blocks;  // tiles_f * tiles_m * chunks * outer (the grid is padded to a multiple of 8)
+};
+
+inline size_t tile_lds_bytes(const Tile &t, size_t elem)
+{
+    return elem * ((size_t)(t.ty + 6) * (t.tx + 6) + 4 * (size_t)t.tx * t.ty);
 }
 
 enum : int { kSchemeFirst = 1, kSchemeEno2 = 2, kSchemeEno3 = 3, kSchemeWeno5 = 5 };

@@ -12,6 +12,7 @@
 // lanes of a wave, so every row load is coalesced; see the stage kernel for
 // the tiling.
 #include "hjx_device.h"
+#include "hjx_tile.h"
 
 #include <cstdint>
 #include <type_traits>
@@ -20,6 +21,9 @@ namespace hjx {
 namespace {
 
 using namespace dev;
+
+// threads per block of the tile kernel (one node each at 512)
+constexpr int kTileThreads = 512;
 
 // ---------------------------------------------------------------- stage kernel
 //
@@ -435,7 +439,7 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
     int gy = 1;
     if (D >= 3) gy = (a.g.n[D - 3] + t.march - 1) / t.march;
     if (D == 4) gy *= a.g.n[0];
-    if (t.variant == kVariantPlaneMarch &&
+    if (D <= 2 && t.variant == kVariantPlaneMarch &&
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
     if (t.variant == kVariantDirect || (M & kNodeKeep) != 0) {  // only the direct variant keeps p-, p+
@@ -457,9 +461,25 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
         return hipGetLastError();
     }
     if constexpr ((M & kNodeKeep) == 0) {
-        const size_t lds = stage_lds_bytes(t, sizeof(T));
-        hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, M>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
-        return hipGetLastError();
+        if constexpr (D >= 3) {  // the tile kernel: 256 threads, up to 512 nodes of the plane tile
+            if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 512 || t.march < 1) return hipErrorInvalidConfiguration;
+            TileLaunch tl{};
+            tl.tiles_f = (nf + t.tx - 1) / t.tx;
+            tl.tiles_m = (nm + t.ty - 1) / t.ty;
+            tl.chunks = (a.g.n[0] + t.march - 1) / t.march;  // the marched axis is axis 0
+            tl.outer = D == 4 ? a.g.n[1] : 1;                  // the gathered axis of a 4-D grid
+            const long blocks = (long)tl.tiles_f * tl.tiles_m * tl.chunks * tl.outer;
+            if (blocks > (1l << 30)) return hipErrorInvalidConfiguration;
+            tl.blocks = (int)blocks;
+            const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);
+            hipLaunchKernelGGL((stage_tile_kernel<T, D, SCHEME, HAM, M, kTileThreads>), dim3(grid),
+                               dim3(kTileThreads), tile_lds_bytes(t, sizeof(T)), s, a, tl);
+            return hipGetLastError();
+        } else {
+            const size_t lds = stage_lds_bytes(t, sizeof(T));
+            hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, M>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);
+            return hipGetLastError();
+        }
     }
     return hipErrorInvalidValue;
 }

@@ -379,11 +379,18 @@ def test_tune_cache_file(tmp_path):
 
 
 def test_tile_validation():
+    """Plane tiles: up to 512 nodes in 3-D and 4-D (the tile kernel's 256
+    threads take two nodes each), up to 256 threads in 1-D and 2-D."""
     P = gpu_problem(CASES["dubins3"], "f32")
-    for bad in [(0, 4, 1), (17, 16, 1), (8, 8, 0)]:
+    for bad in [(0, 4, 1), (23, 23, 1), (8, 8, 0)]:
         with pytest.raises(hjx.HjxError) as e:
             P.tile = bad
         assert e.value.status == hjx.HJX_ERR_INVALID_ARG
+    P.tile = (32, 16, 2)
+    assert P.tile == (hjx.TILE_PLANE_MARCH, 32, 16, 2)
+    P2 = gpu_problem(CASES["normal2d"], "f32")
+    with pytest.raises(hjx.HjxError):
+        P2.tile = (17, 16, 1)
     P1 = gpu_problem(CASES["normal1d"], "f32")
     with pytest.raises(hjx.HjxError):
         P1.tile = (8, 2, 1)
