@@ -224,7 +224,7 @@ hjx_status hjx_rhs(hjx_problem *p, const void *phi, void *L_out, void *stream);
 hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, void *stream);
 
 /* Launch shape of the stage kernel (no counterpart in the paper, whose
- * stages are whole-array expressions).  Two variants compute the same
+ * stages are whole-array expressions).  The variants compute the same
  * arithmetic, so results are bit-for-bit the same for every shape:
  *   HJX_TILE_PLANE_MARCH: a block covers tx nodes of the fastest axis by ty
  *     nodes of the second-fastest (ty = 1 when dim = 1), stages that plane
@@ -237,9 +237,22 @@ hjx_status hjx_step(hjx_problem *p, void *phi, const void *target, double dt, vo
  *   HJX_TILE_DIRECT: one thread per node, stencils gathered through the
  *     caches (tx, ty, march ignored); arrays must be under 4 GiB, else
  *     HJX_ERR_UNSUPPORTED.
- * hjx_problem_create picks a default; hjx_tune may replace it. */
+ *   HJX_TILE_STEPS (1-D and 2-D grids under 4 GiB, else
+ *     HJX_ERR_UNSUPPORTED): hjx_solve takes `march` whole RK steps per
+ *     launch.  A block of 256 threads owns a tx x ty output tile (tx along
+ *     the fastest axis, ty along axis 0; ty = 1 in 1-D) and evaluates every
+ *     stage of those steps in LDS over the tile and a halo of
+ *     H = march * rk * radius nodes (radius 1 first order, 2 ENO2, 3 ENO3 and
+ *     WENO5), which the neighbouring blocks evaluate as well.  Needs
+ *     H <= n_d on a periodic axis and (2 buffers, 3 for RK3) x (tx + 2H) x
+ *     (ty + 2H) values (a region never longer than a non-periodic axis) in
+ *     64 KiB, else HJX_ERR_INVALID_ARG.  Everything other than hjx_solve's
+ *     stepping (hjx_step, hjx_rhs, the tape) takes the direct variant.
+ * hjx_problem_create picks a default (the steps variant for 1-D and 2-D
+ * grids of at most 65536 nodes); hjx_tune may replace it. */
 #define HJX_TILE_PLANE_MARCH 0
 #define HJX_TILE_DIRECT 1
+#define HJX_TILE_STEPS 2
 hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int32_t ty, int32_t march);
 hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t *tx, int32_t *ty,
                                 int32_t *march);
@@ -247,9 +260,11 @@ hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t 
 /* Autotuner: times the stage kernel on this problem for a set of candidate
  * launch shapes (row widths that split the fastest axis evenly, tiles of
  * 64..256 nodes in 1-D and 2-D and of 512 in 3-D and 4-D, march lengths
- * 1..32, and the direct variant) and keeps the fastest with
- * hjx_problem_set_tile.  Each candidate is timed on whole RK steps taken
- * from a copy of phi with phi as the target, as in a solve.  phi: device
+ * 1..32, the direct variant, and in 1-D and 2-D steps tiles of 64..1024
+ * nodes with 1..8 steps per launch) and keeps the fastest with
+ * hjx_problem_set_tile.  Each candidate is timed on `reps` whole RK steps
+ * from phi into a temporary array with phi as the target, launched as
+ * hjx_solve launches them.  phi: device
  * array of the problem's size and dtype, read only.  reps: timed steps per
  * candidate (>= 1).  best_us (host, optional): the winner's mean time per
  * stage launch.  Allocates one temporary array of the problem's size for the

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhjx.so")
-SOURCES = ["hjx_kernels.hip", "hjx_adjoint.hip", "hjx_batch.hip", "hjx_claw.hip", "hjx_shapes.hip", "hjx_api.cpp"]
+SOURCES = ["hjx_kernels.hip", "hjx_steps.hip", "hjx_adjoint.hip", "hjx_batch.hip", "hjx_claw.hip", "hjx_shapes.hip", "hjx_api.cpp"]
 ARCH = os.environ.get("HJX_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

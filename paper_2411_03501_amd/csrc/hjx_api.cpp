@@ -273,8 +273,36 @@ bool tile_ok(const GridGeom &g, size_t elem)
     return planes * (uint64_t)g.n[g.dim - 1] * (uint64_t)g.n[g.dim - 2] * elem < (uint64_t(1) << 32);
 }
 
-Tile default_tile(const GridGeom &g, size_t elem)
+// The steps variant's shape check: a 1-D or 2-D grid under 4 GiB, k = march
+// whole steps with a halo H = k * rk * radius no deeper than a periodic axis,
+// at most 2^20 values per LDS buffer and kStepsLdsMax bytes of LDS.  *area
+// receives the values per buffer.
+bool steps_shape(const GridGeom &g, size_t elem, int deriv, int rk, const Tile &t, long *area)
 {
+    if (g.dim > 2 || !direct_ok(g, elem) || t.tx < 1 || t.ty < 1 || t.march < 1 || (g.dim == 1 && t.ty != 1))
+        return false;
+    const int nx = g.n[g.dim - 1], ny = g.dim == 2 ? g.n[0] : 1;
+    const bool perx = (g.periodic >> (g.dim - 1)) & 1u, pery = g.dim == 2 && (g.periodic & 1u);
+    const long H = (long)t.march * rk * scheme_radius(deriv);
+    if ((perx && H > nx) || (pery && H > ny)) return false;
+    const long a = steps_area(t.tx, t.ty, H, nx, ny, perx, pery, g.dim == 2);
+    if (a >= (1l << 20) || (size_t)steps_buffers(rk) * (size_t)a * elem > kStepsLdsMax) return false;
+    if (area) *area = a;
+    return true;
+}
+
+Tile default_tile(const GridGeom &g, size_t elem, int deriv, int rk)
+{
+    // small 1-D and 2-D grids: a few whole steps per launch (8 x 8 tiles,
+    // about four stage radii of halo; the fastest shape the tuner finds for
+    // the 101^2 first-order case, 1.5 us per step against 2.3 us with 16 x 16)
+    long nodes = 1;
+    for (int d = 0; d < g.dim; ++d) nodes *= g.n[d];
+    if (g.dim <= 2 && nodes <= (1l << 16)) {
+        const Tile st{g.dim == 1 ? 256 : 8, g.dim == 1 ? 1 : 8, std::max(1, 4 / (rk * scheme_radius(deriv))),
+                      kVariantSteps};
+        if (steps_shape(g, elem, deriv, rk, st, nullptr)) return st;
+    }
     Tile t{};
     const int nf = g.n[g.dim - 1];
     const int nm = g.dim >= 2 ? g.n[g.dim - 2] : 1;
@@ -338,6 +366,39 @@ hipError_t launch_stage(const hjx_problem *p, const double *alpha, const void *i
     a.cb = cb;
     a.rhs_only = rhs_only;
     return launch_stage_f64(a, p->scheme.deriv, p->ham.kind, s);
+}
+
+// k whole RK steps of the steps variant from in into out (different arrays),
+// each of size dt but the last, of dt_last; the target after every step.
+hipError_t launch_steps(const hjx_problem *p, const double *alpha, const void *in, const void *target, void *out,
+                        int k, double dt, double dt_last, hipStream_t s)
+{
+    const GridGeom g = geometry(p);
+    long area = 0;
+    if (!steps_shape(g, p->elem, p->scheme.deriv, p->scheme.rk, p->tile, &area)) return hipErrorInvalidConfiguration;
+    StepsLaunch l{};
+    l.k = k;
+    l.rk = p->scheme.rk;
+    l.dt = dt;
+    l.dt_last = dt_last;
+    l.tx = p->tile.tx;
+    l.ty = p->tile.ty;
+    l.tiles_x = (g.n[g.dim - 1] + l.tx - 1) / l.tx;
+    l.area_max = (int)area;
+    // (area is for the tile's own number of steps; a launch of fewer has a
+    // shallower halo and fits in it)
+    if (p->scheme.dtype == HJX_F32) {
+        StageArgs<float> a = stage_args<float>(p, alpha);
+        a.phi_in = static_cast<const float *>(in);
+        a.target = static_cast<const float *>(target);
+        a.out = static_cast<float *>(out);
+        return launch_steps_f32(a, l, p->scheme.deriv, p->ham.kind, s);
+    }
+    StageArgs<double> a = stage_args<double>(p, alpha);
+    a.phi_in = static_cast<const double *>(in);
+    a.target = static_cast<const double *>(target);
+    a.out = static_cast<double *>(out);
+    return launch_steps_f64(a, l, p->scheme.deriv, p->ham.kind, s);
 }
 
 hipError_t launch_copy(const hjx_problem *p, const void *src, void *dst, hipStream_t s)
@@ -479,6 +540,24 @@ hipError_t enqueue_steps(const hjx_problem *p, const double *alpha, const void *
 {
     hipError_t e = hipSuccess;
     if (steps == 0) return phi_out == phi0 ? hipSuccess : launch_copy(p, phi0, phi_out, s);
+    if (p->tile.variant == kVariantSteps) {
+        // k steps per launch; launches alternate between the two workspaces
+        // and the last lands in phi_out (through ws[0] and a copy when a
+        // single launch would read and write phi_out)
+        const int k = p->tile.march;
+        const int64_t launches = (steps + k - 1) / k;
+        const void *src = phi0;
+        for (int64_t i = 0; i < launches && e == hipSuccess; ++i) {
+            const bool final = i + 1 == launches;
+            const int ki = (int)std::min<int64_t>(k, steps - i * k);
+            void *dst = final ? phi_out : p->ws[i & 1];
+            if (dst == src) dst = p->ws[0];
+            e = launch_steps(p, alpha, src, target, dst, ki, dt, final ? dt_last : dt, s);
+            if (e == hipSuccess && final && dst != phi_out) e = launch_copy(p, dst, phi_out, s);
+            src = dst;
+        }
+        return e;
+    }
     if (p->scheme.rk == 1) {
         if (phi_out == phi0) {  // in place: each step through the workspace and back
             for (int64_t k = 0; k < steps && e == hipSuccess; ++k) {
@@ -649,7 +728,7 @@ hjx_status hjx_problem_create(const hjx_grid_desc *grid, const hjx_ham_desc *ham
         return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "problem allocation: %s",
                     hipGetErrorString(e));
     }
-    p->tile = default_tile(geometry(p), p->elem);
+    p->tile = default_tile(geometry(p), p->elem, p->scheme.deriv, p->scheme.rk);
     *out = p;
     return ok();
 }
@@ -685,6 +764,18 @@ hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int
         p->tile = Tile{256, 1, 1, kVariantDirect};
         return ok();
     }
+    if (variant == HJX_TILE_STEPS) {
+        if (g.dim > 2) return fail(HJX_ERR_UNSUPPORTED, "the steps variant takes 1-D and 2-D grids");
+        if (!direct_ok(g, p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the steps variant needs arrays under 4 GiB");
+        const Tile t{tx, ty, march, kVariantSteps};
+        if (!steps_shape(g, p->elem, p->scheme.deriv, p->scheme.rk, t, nullptr))
+            return fail(HJX_ERR_INVALID_ARG,
+                        "steps tile %d x %d, %d steps: needs tx, ty, steps >= 1 (ty = 1 in 1-D), a halo of "
+                        "steps * rk * radius nodes no deeper than a periodic axis and at most %zu bytes of LDS",
+                        tx, ty, march, kStepsLdsMax);
+        p->tile = t;
+        return ok();
+    }
     if (variant != HJX_TILE_PLANE_MARCH) return fail(HJX_ERR_INVALID_ARG, "unknown tile variant %d", variant);
     const int maxn = tile_max_nodes(g);
     if (tx < 1 || ty < 1 || (int64_t)tx * ty > maxn)
@@ -705,7 +796,9 @@ hjx_status hjx_problem_set_tile(hjx_problem *p, int32_t variant, int32_t tx, int
 hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t *tx, int32_t *ty, int32_t *march)
 {
     if (!p || !variant || !tx || !ty || !march) return fail(HJX_ERR_INVALID_ARG, "NULL argument");
-    *variant = p->tile.variant == kVariantDirect ? HJX_TILE_DIRECT : HJX_TILE_PLANE_MARCH;
+    *variant = p->tile.variant == kVariantDirect ? HJX_TILE_DIRECT
+               : p->tile.variant == kVariantSteps  ? HJX_TILE_STEPS
+                                                   : HJX_TILE_PLANE_MARCH;
     *tx = p->tile.tx;
     *ty = p->tile.ty;
     *march = p->tile.march;
@@ -757,7 +850,7 @@ bool tune_cache_find(const char *path, const std::string &key, Tile *tile, doubl
         int v = 0, tx = 0, ty = 0, m = 0;
         double t = 0.0;
         if (std::sscanf(line + prefix.size(), "%d %d %d %d %lf", &v, &tx, &ty, &m, &t) == 5 &&
-            (v == kVariantDirect || v == kVariantPlaneMarch)) {
+            (v == kVariantDirect || v == kVariantPlaneMarch || v == kVariantSteps)) {
             *tile = Tile{tx, ty, m, v};
             *us = t;
             found = true;
@@ -791,9 +884,10 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
         Tile t{};
         double us = 0.0;
         if (tune_cache_find(cache, key, &t, &us)) {
-            const hjx_status st = hjx_problem_set_tile(p, t.variant == kVariantDirect ? HJX_TILE_DIRECT
-                                                                                         : HJX_TILE_PLANE_MARCH,
-                                                       t.tx, t.ty, t.march);
+            const int v = t.variant == kVariantDirect ? HJX_TILE_DIRECT
+                          : t.variant == kVariantSteps  ? HJX_TILE_STEPS
+                                                        : HJX_TILE_PLANE_MARCH;
+            const hjx_status st = hjx_problem_set_tile(p, v, t.tx, t.ty, t.march);
             if (st == HJX_OK) {
                 if (best_us) *best_us = us;
                 return ok();
@@ -836,22 +930,30 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
         }
     }
     if (direct_ok(g, p->elem)) cands.push_back(Tile{256, 1, 1, kVariantDirect});
+    if (g.dim <= 2) {  // the steps variant: tiles of 64..1024 nodes, 1..8 steps per launch
+        const int shapes[][2] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}, {64, 1}, {256, 1}, {1024, 1}};
+        for (const auto &sh : shapes) {
+            if ((g.dim == 1) != (sh[1] == 1)) continue;
+            for (int k : {1, 2, 4, 8}) {
+                const Tile t{sh[0], sh[1], k, kVariantSteps};
+                if (steps_shape(g, p->elem, p->scheme.deriv, p->scheme.rk, t, nullptr)) cands.push_back(t);
+            }
+        }
+    }
     const char *env = std::getenv("HJX_TUNE_VERBOSE");
     const bool verbose = env && env[0] && env[0] != '0';
     const Tile keep = p->tile;
     Tile best = keep;
     float best_ms = INFINITY;
-    // time whole RK steps (all stages, phi itself as the target) on a copy of
-    // phi, as a solve runs them
+    // time whole RK steps (all stages, phi itself as the target) from phi
+    // into a temporary array, launched as a solve launches them
     void *work = nullptr;
     HIP_TRY(hipMalloc(&work, (size_t)p->total * p->elem));
     auto timed = [&](float *ms) -> hipError_t {
         hipError_t e;
-        if ((e = launch_copy(p, phi, work, s)) != hipSuccess) return e;
-        if ((e = rk_step(p, alpha, work, phi, h, s)) != hipSuccess) return e;  // untimed
+        if ((e = enqueue_steps(p, alpha, phi, phi, work, reps, h, h, s)) != hipSuccess) return e;  // untimed
         if ((e = hipEventRecord(p->ev[0], s)) != hipSuccess) return e;
-        for (int r = 0; r < reps; ++r)
-            if ((e = rk_step(p, alpha, work, phi, h, s)) != hipSuccess) return e;
+        if ((e = enqueue_steps(p, alpha, phi, phi, work, reps, h, h, s)) != hipSuccess) return e;
         if ((e = hipEventRecord(p->ev[1], s)) != hipSuccess) return e;
         if ((e = hipEventSynchronize(p->ev[1])) != hipSuccess) return e;
         return hipEventElapsedTime(ms, p->ev[0], p->ev[1]);
@@ -868,7 +970,8 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
         ms /= (float)p->scheme.rk;  // per stage launch
         if (verbose)
             fprintf(stderr, "hjx_tune: %s tile %3d x %3d march %2d: %9.2f us\n",
-                    t.variant == kVariantDirect ? "direct" : "plane ", t.tx, t.ty, t.march, (double)ms * 1e3 / reps);
+                    t.variant == kVariantDirect ? "direct" : (t.variant == kVariantSteps ? "steps " : "plane "), t.tx,
+                    t.ty, t.march, (double)ms * 1e3 / reps);
         if (ms < best_ms) {
             best_ms = ms;
             best = t;

@@ -415,10 +415,10 @@ __device__ __forceinline__ T node_bound(const StageArgs<T> &a, const int *j, int
 // is node_bound at the node instead of the grid maximum a.alpha[d].
 // phi_n, target and mask are read (written) at idx: those of `a`, or the same
 // arrays rebased to where idx counts from (stage_result_at).
+//
+// stage_rate: L alone (clipped under kNodeClip unless a.rhs_only).
 template <typename T, int D, int HAM, int MODE = kNodePlain>
-__device__ __forceinline__ T stage_result_at(const StageArgs<T> &a, const T *phi_n, const T *target,
-                                             unsigned char *mask, const int *j, const T *pm, const T *pp, T center,
-                                             int idx)
+__device__ __forceinline__ T stage_rate(const StageArgs<T> &a, const int *j, const T *pm, const T *pp)
 {
 #pragma clang fp contract(off)
     T pbar[D];
@@ -457,6 +457,17 @@ __device__ __forceinline__ T stage_result_at(const StageArgs<T> &a, const T *phi
         if (a.clip < 0) L = L > T(0) ? T(0) : L;
         if (a.clip > 0) L = L < T(0) ? T(0) : L;
     }
+    return L;
+}
+
+template <typename T, int D, int HAM, int MODE = kNodePlain>
+__device__ __forceinline__ T stage_result_at(const StageArgs<T> &a, const T *phi_n, const T *target,
+                                             unsigned char *mask, const int *j, const T *pm, const T *pp, T center,
+                                             int idx)
+{
+#pragma clang fp contract(off)
+    const T L = stage_rate<T, D, HAM, MODE>(a, j, pm, pp);
+    if (a.rhs_only) return L;
     T res = a.cb * fmaT(a.dt, L, center);
     if (a.ca != T(0)) res = fmaT(a.ca, ld32(phi_n, idx), res);
     if (target) {

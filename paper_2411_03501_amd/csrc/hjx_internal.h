@@ -34,17 +34,20 @@ struct GridGeom {
 // axis by ty nodes of the second-fastest ("plane tile", staged in LDS with its
 // halo) and, in 3-D and 4-D, marches over `march` consecutive nodes of axis 0.
 // tx * ty <= 256 in 1-D and 2-D; in 3-D and 4-D the tile kernel runs 512
-// threads over tx * ty <= 512 nodes.
+// threads over tx * ty <= 512 nodes.  The steps variant (1-D, 2-D) takes
+// `march` whole RK steps of a tx x ty output tile per launch.
 struct Tile {
     int tx, ty, march;
-    int variant;  // kVariantPlaneMarch or kVariantDirect
+    int variant;  // kVariantPlaneMarch, kVariantDirect or kVariantSteps
 };
 
 // Stage-kernel variants (the same arithmetic, bit for bit):
 //   plane-march: the tiling above, each interval evaluated once and shared;
 //   direct: one thread per node, gathering its stencils through the caches
-//           and evaluating both halves at the node (no LDS, no barriers).
-enum : int { kVariantPlaneMarch = 0, kVariantDirect = 1 };
+//           and evaluating both halves at the node (no LDS, no barriers);
+//   steps: several whole RK steps per launch (below); single stages of such
+//          a problem take the direct variant.
+enum : int { kVariantPlaneMarch = 0, kVariantDirect = 1, kVariantSteps = 2 };
 
 // One fused stage: out = ca * phi_n + cb * (phi_in + dt * L(phi_in)),
 // then out = min(out, target) if target != nullptr; with rhs_only the
@@ -260,6 +263,42 @@ inline size_t tile_lds_bytes(const Tile &t, size_t elem)
 }
 
 enum : int { kSchemeFirst = 1, kSchemeEno2 = 2, kSchemeEno3 = 3, kSchemeWeno5 = 5 };
+
+// Nodes each side of a node that one stage of the scheme reads along an axis.
+constexpr int scheme_radius(int scheme) { return scheme == kSchemeFirst ? 1 : (scheme == kSchemeEno2 ? 2 : 3); }
+
+// Several whole RK steps of a 1-D or 2-D grid in one launch (the steps
+// variant).  Each block owns a tx x ty tile of the output (ty along axis 0,
+// tx along the fastest axis; ty = 1 in 1-D) and loads it into LDS with a halo
+// of H = k * rk * radius nodes on every side that is not a non-periodic end
+// of the grid; every stage is then evaluated on the whole region that still
+// holds valid values, which shrinks by the radius on those sides, so after k
+// steps the tile itself is exact.  The halo work is done again by the
+// neighbouring blocks: it buys k - 1 fewer dependent launches per k steps,
+// which is what small grids are bound by.
+struct StepsLaunch {
+    int k, rk;           // whole steps in this launch, RK order
+    double dt, dt_last;  // size of every step of the launch but its last, and of its last
+    int tx, ty;          // output tile
+    int tiles_x;         // tiles along the fastest axis (blocks: tiles_x * tiles along axis 0)
+    int area_max;        // LDS values per buffer (the largest region of any block)
+};
+
+// LDS buffers of the steps variant: the stage input and phi^n, plus a third
+// for the middle stage of RK3.
+constexpr int steps_buffers(int rk) { return rk == 3 ? 3 : 2; }
+
+// The largest region of one block (values per LDS buffer) for tile (tx, ty)
+// and halo H on a grid of n_x x n_y (n_y = 1 in 1-D): a region never spans
+// more than a non-periodic axis holds.
+inline long steps_area(long tx, long ty, long H, long nx, long ny, bool per_x, bool per_y, bool two_d)
+{
+    long wx = (tx < nx ? tx : nx) + 2 * H, wy = two_d ? (ty < ny ? ty : ny) + 2 * H : 1;
+    if (!per_x && wx > nx) wx = nx;
+    if (two_d && !per_y && wy > ny) wy = ny;
+    return wx * wy;
+}
+constexpr size_t kStepsLdsMax = 64 * 1024;  // bytes of LDS per block, so that two blocks share a CU
 enum : int { kHamNormal = 0, kHamDubins3 = 1, kHamDubins4 = 2, kHamRockets = 3 };
 // normal motion with Godunov's numerical Hamiltonian instead of Lax-Friedrichs
 // (a template tag of the stage kernels, chosen by StageArgs::diss)
@@ -268,6 +307,10 @@ enum : int { kHamNormalGodunov = 4 };
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_stage_f32(const StageArgs<float> &a, int scheme, int ham, hipStream_t s);
 hipError_t launch_stage_f64(const StageArgs<double> &a, int scheme, int ham, hipStream_t s);
+// l.k whole RK steps from a.phi_in into a.out (different arrays), with
+// a.target (nullable) taken after the last stage of every step (hjx_steps.hip)
+hipError_t launch_steps_f32(const StageArgs<float> &a, const StepsLaunch &l, int scheme, int ham, hipStream_t s);
+hipError_t launch_steps_f64(const StageArgs<double> &a, const StepsLaunch &l, int scheme, int ham, hipStream_t s);
 
 // alpha[d] = max over nodes (written to alpha_out[0..dim-1] on the device);
 // partial must hold alpha_blocks() * kMaxDim doubles.

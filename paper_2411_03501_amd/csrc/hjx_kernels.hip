@@ -442,7 +442,9 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
     if (D <= 2 && t.variant == kVariantPlaneMarch &&
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
-    if (t.variant == kVariantDirect || (M & kNodeKeep) != 0) {  // only the direct variant keeps p-, p+
+    // only the direct variant keeps p-, p+; single stages of a problem whose
+    // solves take the steps variant run direct
+    if (t.variant == kVariantDirect || t.variant == kVariantSteps || (M & kNodeKeep) != 0) {
         if (x2_applies<T, D, SCHEME>(a)) {
             const long threads = (long)a.g.n[0] * (a.g.n[1] / 2);
             const dim3 grid((unsigned)((threads + 255) / 256));

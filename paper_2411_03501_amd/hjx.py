@@ -174,7 +174,7 @@ def hjx_problem_destroy(handle):
     _check(lib().hjx_problem_destroy(handle))
 
 
-TILE_PLANE_MARCH, TILE_DIRECT = 0, 1
+TILE_PLANE_MARCH, TILE_DIRECT, TILE_STEPS = 0, 1, 2
 
 
 def hjx_problem_set_tile(handle, variant, tx, ty, march):
@@ -371,7 +371,8 @@ class Problem:
 
     @property
     def tile(self):
-        """(variant, tx, ty, march); variant 0 = plane-march, 1 = direct."""
+        """(variant, tx, ty, march); variant 0 = plane-march, 1 = direct, 2 = steps
+        (march whole RK steps per launch)."""
         return hjx_problem_get_tile(self.handle)
 
     @tile.setter
