@@ -10,6 +10,35 @@
 namespace hjx {
 namespace dev {
 
+// ---------------------------------------------------------------- raw buffer access
+//
+// A raw buffer resource (stride 0) over `bytes` bytes from p: the base and the
+// range sit in scalar registers and every load takes a 32-bit vector byte
+// offset plus a 32-bit scalar byte offset, so a load costs no vector
+// address arithmetic.  A load at or beyond the range reads zero instead of
+// faulting.  The fourth word is the gfx9 family's
+// raw-access format (32-bit data).
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, size_t bytes)
+{
+    const unsigned n = bytes < 0xFFFFFFFFull ? (unsigned)bytes : 0xFFFFFFFFu;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, kBufWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned vbyte, unsigned sbyte);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned vbyte, unsigned sbyte)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vbyte, sbyte, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned vbyte, unsigned sbyte)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vbyte, sbyte, 0));
+}
+
 // ---------------------------------------------------------------- tile kernel (3-D and 4-D)
 //
 // NT threads own a tile of TX x TY nodes of the plane of the two fastest
@@ -37,11 +66,18 @@ namespace dev {
 // Blocks are renumbered so that each XCD takes a contiguous run of them with
 // axis 1 varying fastest (4-D): the planes a node's axis-1 stencil reads are
 // then read by neighbouring blocks of the same XCD, through its L2.
+// FP32: at least six waves per SIMD (at most 80 vector registers); left to
+// itself the compiler takes 81 for the 4-D WENO5 kernel, which allows five.
+template <typename T>
+constexpr int tile_min_waves() { return sizeof(T) == 4 ? 6 : 1; }
+
 template <typename T, int D, int SCHEME, int HAM, int MODE, int NT>
-__global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tile_min_waves<T>())))
+void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
 {
     constexpr int NPT = kTileNodes / NT;  // nodes per thread
     static_assert(D == 3 || D == 4, "the tile kernel marches axis 0 of a 3-D or 4-D grid");
+    static_assert((MODE & kNodeKeep) == 0, "kept p-, p+ (and the target mask) come from the direct variant");
     constexpr int AF = D - 1, AM = D - 2, AK = 0, AG = 1;  // AG: the gathered axis of a 4-D grid
     extern __shared__ unsigned char smem_raw[];
     const int TX = a.tile.tx, TY = a.tile.ty, LW = TX + 6;
@@ -74,6 +110,11 @@ __global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaun
     const int txv = min(TX, nf - jf0), tyv = min(TY, nm - jm0);  // the tile's nodes inside the grid
     const int k0 = kc * a.tile.march, k1 = min(k0 + a.tile.march, nk);
     const size_t slab = D == 4 ? (size_t)jd * (size_t)a.g.stride[AG] : 0;
+    // 4-D: the seven planes of the gathered axis all inside the grid (the
+    // same for the whole block; seven planes are under 4 GiB)
+    const bool y_inside = D == 4 && jd >= 3 && jd + 3 < a.g.n[AG];
+    // bytes of one plane of the tile's two axes: what one buffer range covers
+    const size_t pbytes = (size_t)(D == 4 ? a.g.stride[AG] : a.g.stride[AK]) * sizeof(T);
     const T *__restrict__ phi = a.phi_in + slab;
 
     // phi at plane kk (a ghost plane beyond a non-periodic end is
@@ -121,6 +162,13 @@ __global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaun
     const float rtxv = 1.0f / (float)txv, rtx1 = 1.0f / (float)(txv + 1);
     const int items_f = tyv * (txv + 1), items_m = (tyv + 1) * txv;
 
+    // The plane loop, instantiated twice: for blocks whose gathered-axis
+    // stencil lies inside the grid (every block in 3-D; YIN) and for the
+    // others.  The ghost rules of the second need block constants (the
+    // planes to extrapolate from) that would otherwise stay live, spilled,
+    // through every interior block's loop.
+    auto planes = [&](auto yin_tag) {
+    constexpr bool YIN = decltype(yin_tag)::value;
     for (int k = k0; k < k1; ++k) {
         const T *base = phi + (size_t)k * sk;
         // 1. halo: three rows above and below the tile (inside its columns)
@@ -193,7 +241,6 @@ __global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaun
         const size_t po = slab + (size_t)k * sk;
         const T *phin_p = a.phi_n ? a.phi_n + po : nullptr;
         const T *tgt_p = a.target ? a.target + po : nullptr;
-        unsigned char *mask_p = a.mask ? a.mask + po : nullptr;
         T *outp = a.out + po;
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
@@ -217,6 +264,12 @@ __global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaun
                 const int ng = a.g.n[AG], sg = a.g.stride[AG];
                 const T *pk = a.phi_in + (size_t)k * sk;
                 T v[7];
+                if constexpr (YIN) {  // one buffer over the seven planes
+                    const __amdgpu_buffer_rsrc_t ry = buf_rsrc(pk + (size_t)(jd - 3) * (size_t)sg, 7 * pbytes);
+#pragma unroll
+                    for (int m = 0; m < 7; ++m)
+                        v[m] = buf_ld<T>(ry, (unsigned)off[i] * sizeof(T), (unsigned)(m * sg) * sizeof(T));
+                } else
 #pragma unroll
                 for (int m = 0; m < 7; ++m) {  // yy is the same for the whole block
                     const int yy = jd + m - 3;
@@ -239,7 +292,7 @@ __global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaun
             pm[AM] = PMm[n];
             pp[AM] = PPm[n];
             at32(outp, off[i]) =
-                stage_result_at<T, D, HAM, MODE>(a, phin_p, tgt_p, mask_p, j, pm, pp, q[i][3], off[i]);
+                stage_result_at<T, D, HAM, MODE>(a, phin_p, tgt_p, nullptr, j, pm, pp, q[i][3], off[i]);
             // a further node's loads and arithmetic after this node's store:
             // two nodes' temporaries are never live together
             asm volatile("" ::: "memory");
@@ -255,6 +308,11 @@ __global__ __launch_bounds__(NT) void stage_tile_kernel(StageArgs<T> a, TileLaun
             }
         }
     }
+    };
+    if (D == 3 || y_inside)
+        planes(std::true_type{});
+    else
+        planes(std::false_type{});
 }
 
 }  // namespace dev
