@@ -316,7 +316,10 @@ Tile default_tile(const GridGeom &g, size_t elem, int deriv, int rk)
     t.tx = std::min((nf + pieces - 1) / pieces, 256);
     t.ty = g.dim >= 2 ? std::max(1, std::min(maxn / t.tx, nm)) : 1;
     t.march = 1;
-    if (g.dim >= 3) t.march = std::min(large ? 8 : 2, g.n[0]);  // the tile kernel marches axis 0
+    if (g.dim >= 3) {  // the tile kernel marches axis 0: chunks of about 8 (large) or 2 planes, evenly
+        const int want = large ? 8 : 2, chunks = std::max(1, (g.n[0] + want / 2) / want);
+        t.march = (g.n[0] + chunks - 1) / chunks;
+    }
     return t;
 }
 
@@ -918,9 +921,19 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
             if (g.dim >= 3 && nodes < 512) continue;
             int ty = g.dim >= 2 ? std::max(1, std::min(nodes / tx, nm)) : 1;
             if (tx * ty > maxn) continue;
-            for (int m : {1, 2, 4, 8, 16, 32}) {
+            // march lengths: powers of two, and those that split axis 0 into
+            // chunks of equal length (a last chunk of one plane pays a whole
+            // block's set-up for it)
+            std::vector<int> marches{1, 2, 4, 8, 16, 32};
+            if (g.dim >= 3)
+                for (int c = 1; c <= 64; ++c) {
+                    const int m = (nk + c - 1) / c;
+                    if (m <= 32 && nk % m == 0 && std::find(marches.begin(), marches.end(), m) == marches.end())
+                        marches.push_back(m);
+                }
+            for (int m : marches) {
                 if (g.dim < 3 && m > 1) break;
-                if (m > nk && m > 1) break;
+                if (m > nk && m > 1) continue;
                 if (g.dim <= 2 && (long)((nk + m - 1) / m) * outer > 65535) continue;
                 const Tile t{tx, ty, m, kVariantPlaneMarch};
                 bool seen = false;

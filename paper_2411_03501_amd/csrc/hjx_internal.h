@@ -255,7 +255,16 @@ constexpr int kTileNodes = 512;  // nodes of one tile of the 3-D and 4-D tile ke
 struct TileLaunch {
     int tiles_f, tiles_m, chunks, outer;
     int blocks;  // tiles_f * tiles_m * chunks * outer (the grid is padded to a multiple of 8)
+    int y_first; // 4-D interior launch: axis-1 node of its first line (3)
 };
+
+// The 4-D tile kernel's lines of the gathered axis 1: every line (a 3-D grid,
+// or a 4-D grid with too few lines for an interior), the lines whose
+// seven-plane stencil lies inside the grid, or the six lines within three of
+// its ends.  The two kinds are separate launches with separate register
+// allocations: the ghost rules of the end lines need block constants that
+// would otherwise stay live, spilled, through every interior block.
+enum : int { kTileLinesAll = 0, kTileLinesInterior = 1, kTileLinesEnds = 2 };
 
 inline size_t tile_lds_bytes(const Tile &t, size_t elem)
 {

@@ -469,14 +469,30 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
             tl.tiles_f = (nf + t.tx - 1) / t.tx;
             tl.tiles_m = (nm + t.ty - 1) / t.ty;
             tl.chunks = (a.g.n[0] + t.march - 1) / t.march;  // the marched axis is axis 0
-            tl.outer = D == 4 ? a.g.n[1] : 1;                  // the gathered axis of a 4-D grid
-            const long blocks = (long)tl.tiles_f * tl.tiles_m * tl.chunks * tl.outer;
-            if (blocks > (1l << 30)) return hipErrorInvalidConfiguration;
-            tl.blocks = (int)blocks;
-            const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);
-            hipLaunchKernelGGL((stage_tile_kernel<T, D, SCHEME, HAM, M, kTileThreads>), dim3(grid),
-                               dim3(kTileThreads), tile_lds_bytes(t, sizeof(T)), s, a, tl);
-            return hipGetLastError();
+            const size_t lds = tile_lds_bytes(t, sizeof(T));
+            // one launch over `lines` lines of the gathered axis (4-D), from y_first
+            auto go = [&](auto kind, int lines, int y_first) -> hipError_t {
+                constexpr int LINES = decltype(kind)::value;
+                tl.outer = lines;
+                tl.y_first = y_first;
+                const long blocks = (long)tl.tiles_f * tl.tiles_m * tl.chunks * tl.outer;
+                if (blocks > (1l << 30)) return hipErrorInvalidConfiguration;
+                tl.blocks = (int)blocks;
+                const unsigned grid = (unsigned)((blocks + 7) / 8 * 8);
+                hipLaunchKernelGGL((stage_tile_kernel<T, D, SCHEME, HAM, M, kTileThreads, LINES>), dim3(grid),
+                                   dim3(kTileThreads), lds, s, a, tl);
+                return hipGetLastError();
+            };
+            using AllT = std::integral_constant<int, kTileLinesAll>;
+            if constexpr (D == 3) {
+                return go(AllT{}, 1, 0);
+            } else {
+                const int ng = a.g.n[1];
+                if (ng < 7) return go(AllT{}, ng, 0);  // no line has its stencil inside
+                const hipError_t e = go(std::integral_constant<int, kTileLinesInterior>{}, ng - 6, 3);
+                if (e != hipSuccess) return e;
+                return go(std::integral_constant<int, kTileLinesEnds>{}, 6, 0);
+            }
         } else {
             const size_t lds = stage_lds_bytes(t, sizeof(T));
             hipLaunchKernelGGL((stage_kernel<T, D, SCHEME, HAM, M>), dim3(tiles, gy), dim3(t.tx, t.ty), lds, s, a);

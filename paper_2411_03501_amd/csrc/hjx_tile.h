@@ -71,7 +71,7 @@ __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsig
 template <typename T>
 constexpr int tile_min_waves() { return sizeof(T) == 4 ? 6 : 1; }
 
-template <typename T, int D, int SCHEME, int HAM, int MODE, int NT>
+template <typename T, int D, int SCHEME, int HAM, int MODE, int NT, int LINES>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tile_min_waves<T>())))
 void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
 {
@@ -95,6 +95,8 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
     if constexpr (D == 4) {
         jd = rest % tl.outer;
         rest /= tl.outer;
+        if constexpr (LINES == kTileLinesInterior) jd += tl.y_first;
+        if constexpr (LINES == kTileLinesEnds) jd = jd < 3 ? jd : a.g.n[AG] - 6 + jd;
     }
     const int tf = rest % tl.tiles_f;
     rest /= tl.tiles_f;
@@ -110,9 +112,7 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
     const int txv = min(TX, nf - jf0), tyv = min(TY, nm - jm0);  // the tile's nodes inside the grid
     const int k0 = kc * a.tile.march, k1 = min(k0 + a.tile.march, nk);
     const size_t slab = D == 4 ? (size_t)jd * (size_t)a.g.stride[AG] : 0;
-    // 4-D: the seven planes of the gathered axis all inside the grid (the
-    // same for the whole block; seven planes are under 4 GiB)
-    const bool y_inside = D == 4 && jd >= 3 && jd + 3 < a.g.n[AG];
+
     // bytes of one plane of the tile's two axes: what one buffer range covers
     const size_t pbytes = (size_t)(D == 4 ? a.g.stride[AG] : a.g.stride[AK]) * sizeof(T);
     const T *__restrict__ phi = a.phi_in + slab;
@@ -131,7 +131,8 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
 
     // the thread's nodes: n = t + NT i of the tile, row n / TX, column n % TX
     const int t = (int)threadIdx.x;
-    const float rtx = 1.0f / (float)TX;
+    // index reciprocals: one-ulp rcp keeps the floors below exact (indices < 2^20)
+    const float rtx = __builtin_amdgcn_rcpf((float)TX);
     bool valid[NPT];
     int rr[NPT], cc[NPT], off[NPT];
 #pragma unroll
@@ -159,16 +160,13 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
     }
 
     const int band = 6 * txv, side = 6 * tyv;
-    const float rtxv = 1.0f / (float)txv, rtx1 = 1.0f / (float)(txv + 1);
+    const float rtxv = __builtin_amdgcn_rcpf((float)txv), rtx1 = __builtin_amdgcn_rcpf((float)(txv + 1));
     const int items_f = tyv * (txv + 1), items_m = (tyv + 1) * txv;
 
-    // The plane loop, instantiated twice: for blocks whose gathered-axis
-    // stencil lies inside the grid (every block in 3-D; YIN) and for the
-    // others.  The ghost rules of the second need block constants (the
-    // planes to extrapolate from) that would otherwise stay live, spilled,
-    // through every interior block's loop.
-    auto planes = [&](auto yin_tag) {
-    constexpr bool YIN = decltype(yin_tag)::value;
+    // the gathered axis of a 4-D grid: all seven planes inside the grid for
+    // every block of an interior launch (one buffer over them), ghost rules
+    // otherwise
+    constexpr bool YIN = D == 3 || LINES == kTileLinesInterior;
     for (int k = k0; k < k1; ++k) {
         const T *base = phi + (size_t)k * sk;
         // 1. halo: three rows above and below the tile (inside its columns)
@@ -308,11 +306,6 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
             }
         }
     }
-    };
-    if (D == 3 || y_inside)
-        planes(std::true_type{});
-    else
-        planes(std::false_type{});
 }
 
 }  // namespace dev
