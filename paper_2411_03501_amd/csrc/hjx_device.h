@@ -211,6 +211,37 @@ __device__ __forceinline__ void weno5_q(T u0, T u1, T u2, T u3, T u4, T &q0, T &
     q2 = r2 * r2;
 }
 
+// FP64: q_k up to a common factor, without reciprocals.  With t_k = S_k + eps,
+// the normalised weights d_k t_k^-2 / sum_j d_j t_j^-2 equal
+// d_k P_k / sum_j d_j P_j, P_k being the product of the other two t_j^2;
+// weno5_fwd and weno5_rev normalise, so q_k = P_k serves.  The t_k are first
+// scaled by the power of two of eps (exact): S_k <= (13/12 16 + 16) max u^2
+// < 34 max u^2 and eps >= 1e-6 max u^2 put them in [1/2, 3.4e7), so every P_k
+// lies in [1/16, 1.4e30).  Three quarter-rate reciprocals, each refined by
+// two Newton steps, become six multiplications.
+template <>
+__device__ __forceinline__ void weno5_q<double>(double u0, double u1, double u2, double u3, double u4, double &q0,
+                                                double &q1, double &q2)
+{
+#pragma clang fp contract(off)
+    const double k1312 = 13.0 / 12.0, k14 = 0.25;
+    const double A0 = fmaT(-2.0, u1, u0 + u2), B0 = fmaT(-4.0, u1, fmaT(3.0, u2, u0));
+    const double A1 = fmaT(-2.0, u2, u1 + u3), B1 = u1 - u3;
+    const double A2 = fmaT(-2.0, u3, u2 + u4), B2 = fmaT(-4.0, u3, fmaT(3.0, u2, u4));
+    const double s0 = fmaT(k1312 * A0, A0, k14 * B0 * B0);
+    const double s1 = fmaT(k1312 * A1, A1, k14 * B1 * B1);
+    const double s2 = fmaT(k1312 * A2, A2, k14 * B2 * B2);
+    const double am = absmax(absmax(absmax(u0, u1), absmax(u2, u3)), u4);
+    const double eps = fmaT(1e-6, am * am, Arith<double>::kEpsFloor);
+    const int e = __builtin_amdgcn_frexp_exp(eps);
+    const double t0 = __builtin_amdgcn_ldexp(s0 + eps, -e), t1 = __builtin_amdgcn_ldexp(s1 + eps, -e),
+                 t2 = __builtin_amdgcn_ldexp(s2 + eps, -e);
+    const double p12 = t1 * t2, p02 = t0 * t2, p01 = t0 * t1;
+    q0 = p12 * p12;
+    q1 = p02 * p02;
+    q2 = p01 * p01;
+}
+
 template <typename T>
 __device__ __forceinline__ T weno5_fwd(T u0, T u1, T u2, T u3, T u4, T q0, T q1, T q2)
 {
