@@ -532,7 +532,16 @@ def run_copy(nbytes=1 << 30, reps=4):
 
 
 def cpu_model():
-    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    """The host CPU's model name: lscpu's "Model name", else /proc/cpuinfo's
+    "model name", else None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
