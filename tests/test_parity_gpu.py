@@ -41,6 +41,9 @@ CASES = {
     "normal2d": _w("normal2d", [-1, -2], [1, 1], [13, 29], params=(0.9,)),
     "normal3d": _w("normal3d", [-1, -1, 0], [1, 2, 1], [11, 17, 23], periodic=(1,), params=(1.1,)),
     "normal4d": _w("normal4d", [0, 0, 0, 0], [1, 1, 1, 1], [7, 9, 11, 13], periodic=(0, 3), params=(0.6,)),
+    # axis 1 periodic with more than six lines: the 4-D tile kernel's interior
+    # lines (one buffer over seven planes) and its end lines (wrapped) both run
+    "normal4d_per1": _w("normal4d_per1", [0, 0, 0, 0], [1, 1, 1, 1], [6, 11, 9, 10], periodic=(1,), params=(0.8,)),
     "dubins3": _w("dubins3", [-6, -10, 0], [20, 10, 2 * math.pi], [11, 13, 17], periodic=(2,), ham="dubins3_pe",
                   params=(5, 4, 1, 0.7)),
     "car4": _w("car4", [-5, -5, 0, 0], [5, 5, 2 * math.pi, 2], [7, 9, 10, 11], periodic=(2,), ham="dubins4",
@@ -89,7 +92,7 @@ def test_dissipation_parity(case, dtype):
     assert abs(dt - dt_ref) <= tol * 4 * dt_ref
 
 
-@pytest.mark.parametrize("case", ["normal2d", "normal3d", "dubins3", "car4"])
+@pytest.mark.parametrize("case", ["normal2d", "normal3d", "normal4d_per1", "dubins3", "car4"])
 @pytest.mark.parametrize("rk", [1, 2, 3])
 @pytest.mark.parametrize("with_target", [False, True])
 def test_step_parity_f64(case, rk, with_target):
@@ -286,7 +289,7 @@ def test_repeat_runs_are_bitwise_identical():
 TILES = [(8, 8, 1), (16, 4, 3), (13, 7, 2), (32, 8, 5), (64, 4, 16), (5, 3, 1), (1, 1, 1)]
 
 
-@pytest.mark.parametrize("case", ["normal1d", "normal2d", "normal3d", "normal4d", "dubins3", "car4"])
+@pytest.mark.parametrize("case", ["normal1d", "normal2d", "normal3d", "normal4d", "normal4d_per1", "dubins3", "car4"])
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_results_do_not_depend_on_the_tile(case, scheme):
     """Every interval is evaluated by the same arithmetic whatever the launch
