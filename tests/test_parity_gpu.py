@@ -318,6 +318,41 @@ def test_results_do_not_depend_on_the_tile(case, scheme):
                 assert torch.equal(d, ref_step), f"step differs for tile {tile} ({dtype})"
 
 
+def test_tile_kernel_two_launches_under_graphs_and_threads():
+    """A 4-D stage of the tile kernel is two launches, the interior lines of
+    axis 1 and its end lines.  Direct launches, the captured graph and its
+    replays, in place, and a solve from a second thread all give the direct
+    variant's bits."""
+    import threading
+    w = CASES["car4"].with_(n=(9, 11, 10, 12))  # 11 lines of axis 1: interior and end launches
+    phi = inputs.smooth_field(w.n, 19, amplitude=1.5)
+    P = gpu_problem(w, "f32")
+    t1 = 6.5 * P.dissipation()[1]
+    d0 = to_dev(phi, torch.float32)
+    P.tile = (hjx.TILE_DIRECT, 256, 1, 1)
+    ref, st = P.solve(d0, t1)
+    ref = ref.clone()
+    assert st["steps"] == 7
+    P.tile = (hjx.TILE_PLANE_MARCH, 12, 10, 3)
+    out = torch.empty_like(d0)
+    for k in range(4):  # direct launches, capture, replays
+        got, _ = P.solve(d0, t1, out=out)
+        assert torch.equal(got, ref), k
+    x = d0.clone()
+    P.solve(x, t1, out=x)
+    assert torch.equal(x, ref), "in place"
+    res = {}
+
+    def other_thread():
+        res["out"] = P.solve(d0, t1, out=torch.empty_like(d0))[0].clone()
+        torch.cuda.synchronize()
+
+    th = threading.Thread(target=other_thread)
+    th.start()
+    th.join()
+    assert torch.equal(res["out"], ref), "second thread"
+
+
 @pytest.mark.parametrize("case,scheme,rk,with_target", [
     ("normal2d", "first", 1, False), ("normal2d", "first", 1, True), ("normal3d", "eno2", 2, True),
     ("dubins3", "weno5", 3, True), ("car4", "weno5", 3, False)])
