@@ -261,10 +261,12 @@ struct TileLaunch {
 // The 4-D tile kernel's lines of the gathered axis 1: every line (a 3-D grid,
 // or a 4-D grid with too few lines for an interior), the lines whose
 // seven-plane stencil lies inside the grid, or the six lines within three of
-// its ends.  The two kinds are separate launches with separate register
-// allocations: the ghost rules of the end lines need block constants that
-// would otherwise stay live, spilled, through every interior block.
-enum : int { kTileLinesAll = 0, kTileLinesInterior = 1, kTileLinesEnds = 2 };
+// its ends, non-periodic (ghost planes extrapolated from planes the line
+// loads anyway) or periodic (wrapped).  The kinds are separate launches with
+// separate register allocations: the ghost rules of the end lines need block
+// constants that would otherwise stay live, spilled, through every interior
+// block.
+enum : int { kTileLinesAll = 0, kTileLinesInterior = 1, kTileLinesEnds = 2, kTileLinesEndsWrap = 3 };
 
 inline size_t tile_lds_bytes(const Tile &t, size_t elem)
 {

@@ -491,6 +491,7 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
                 if (ng < 7) return go(AllT{}, ng, 0);  // no line has its stencil inside
                 const hipError_t e = go(std::integral_constant<int, kTileLinesInterior>{}, ng - 6, 3);
                 if (e != hipSuccess) return e;
+                if ((a.g.periodic >> 1) & 1u) return go(std::integral_constant<int, kTileLinesEndsWrap>{}, 6, 0);
                 return go(std::integral_constant<int, kTileLinesEnds>{}, 6, 0);
             }
         } else {

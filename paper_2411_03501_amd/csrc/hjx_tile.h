@@ -66,6 +66,28 @@ __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsig
 // Blocks are renumbered so that each XCD takes a contiguous run of them with
 // axis 1 varying fastest (4-D): the planes a node's axis-1 stencil reads are
 // then read by neighbouring blocks of the same XCD, through its L2.
+// The seven planes of the gathered axis for one of the six end lines of a
+// non-periodic axis 1 (CASE 0..2: lines 0..2; 3..5: lines n-3..n-1): the
+// planes inside the grid through one buffer, then each ghost plane by
+// gather7's linear extrapolation from the two end planes, which are among
+// those just loaded (the same arithmetic, so the same bits).
+template <typename T, int CASE>
+__device__ __forceinline__ void end_line_planes(const T *pk, int jd, int sg, size_t pbytes, int off, T (&v)[7])
+{
+    constexpr bool low = CASE < 3;
+    constexpr int first = low ? 3 - CASE : 0, last = low ? 6 : 5 - (CASE - 3);  // planes inside the grid
+    const __amdgpu_buffer_rsrc_t r =
+        buf_rsrc(pk + (ptrdiff_t)(jd - 3 + first) * (ptrdiff_t)sg, (size_t)(last - first + 1) * pbytes);
+#pragma unroll
+    for (int m = first; m <= last; ++m)
+        v[m] = buf_ld<T>(r, (unsigned)off * sizeof(T), (unsigned)((m - first) * sg) * sizeof(T));
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        if (m < first) v[m] = fmaT(T(first - m), v[first] - v[first + 1], v[first]);
+        if (m > last) v[m] = fmaT(T(m - last), v[last] - v[last - 1], v[last]);
+    }
+}
+
 // FP32: at least six waves per SIMD (at most 80 vector registers); left to
 // itself the compiler takes 81 for the 4-D WENO5 kernel, which allows five.
 template <typename T>
@@ -96,7 +118,7 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
         jd = rest % tl.outer;
         rest /= tl.outer;
         if constexpr (LINES == kTileLinesInterior) jd += tl.y_first;
-        if constexpr (LINES == kTileLinesEnds) jd = jd < 3 ? jd : a.g.n[AG] - 6 + jd;
+        if constexpr (LINES == kTileLinesEnds || LINES == kTileLinesEndsWrap) jd = jd < 3 ? jd : a.g.n[AG] - 6 + jd;
     }
     const int tf = rest % tl.tiles_f;
     rest /= tl.tiles_f;
@@ -267,6 +289,16 @@ void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
 #pragma unroll
                     for (int m = 0; m < 7; ++m)
                         v[m] = buf_ld<T>(ry, (unsigned)off[i] * sizeof(T), (unsigned)(m * sg) * sizeof(T));
+                } else if constexpr (LINES == kTileLinesEnds) {  // block-uniform: which end line
+                    const int line = jd < 3 ? jd : jd - (ng - 6);
+                    switch (line) {
+                    case 0: end_line_planes<T, 0>(pk, jd, sg, pbytes, off[i], v); break;
+                    case 1: end_line_planes<T, 1>(pk, jd, sg, pbytes, off[i], v); break;
+                    case 2: end_line_planes<T, 2>(pk, jd, sg, pbytes, off[i], v); break;
+                    case 3: end_line_planes<T, 3>(pk, jd, sg, pbytes, off[i], v); break;
+                    case 4: end_line_planes<T, 4>(pk, jd, sg, pbytes, off[i], v); break;
+                    default: end_line_planes<T, 5>(pk, jd, sg, pbytes, off[i], v); break;
+                    }
                 } else
 #pragma unroll
                 for (int m = 0; m < 7; ++m) {  // yy is the same for the whole block
