@@ -142,7 +142,7 @@ def run_gpu(w, dtype, steps, warmup, tile=None):
     target = phi0 if w.with_target else None
     out = torch.empty_like(phi0)
     if tile is None:
-        tile, us = P.tune(phi0, reps=3)   # launch-shape autotuner (outside the timed region)
+        tile, us = P.tune(phi0, reps=8)   # launch-shape autotuner (outside the timed region)
         log(f"  tuned tile {tile}: {us:.2f} us per stage launch")
     else:
         P.tile = tile

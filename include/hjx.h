@@ -262,9 +262,9 @@ hjx_status hjx_problem_get_tile(const hjx_problem *p, int32_t *variant, int32_t 
  * 64..256 nodes in 1-D and 2-D and of 512 in 3-D and 4-D, march lengths
  * 1..32, the direct variant, and in 1-D and 2-D steps tiles of 64..1024
  * nodes with 1..8 steps per launch) and keeps the fastest with
- * hjx_problem_set_tile.  Each candidate is timed on `reps` whole RK steps
- * from phi into a temporary array, without a target, launched as hjx_solve
- * launches them.  phi: device
+ * hjx_problem_set_tile.  Each candidate is timed twice on `reps` whole RK
+ * steps from phi into a temporary array, without a target, launched as
+ * hjx_solve launches them; the faster timing counts.  phi: device
  * array of the problem's size and dtype, read only.  reps: timed steps per
  * candidate (>= 1).  best_us (host, optional): the winner's mean time per
  * stage launch.  Allocates one temporary array of the problem's size for the
