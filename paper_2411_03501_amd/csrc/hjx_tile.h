@@ -41,31 +41,6 @@ __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsig
 
 // ---------------------------------------------------------------- tile kernel (3-D and 4-D)
 //
-// NT threads own a tile of TX x TY nodes of the plane of the two fastest
-// axes (AF along the lanes, AM across; TX * TY <= 512, so at most 512 / NT
-// nodes per thread) and march over `march` consecutive nodes of the slowest axis
-// AK = 0.  In 4-D axis 1 is gathered node by node from seven planes that lie
-// one plane of AM x AF apart, close enough to share one L2.  Per marched
-// plane:
-//   1. the tile's halo, three nodes beyond it on both plane axes, is staged
-//      in LDS (ghosts filled; the tile's corners are never read and never
-//      staged), and every thread writes its own nodes from its marched queue;
-//   2. every interval of the tile along AF (TY rows of TX + 1) and along AM
-//      (TY + 1 rows of TX) is evaluated exactly once, the items dealt evenly
-//      over the NT threads, and its two one-sided values go to LDS;
-//   3. each thread finishes its nodes: the marched axis from a register
-//      queue of seven values (the interval right of the node, its left half
-//      kept for the next plane), axis 1 in 4-D (both sides at the node), then
-//      the plane axes' values from LDS, the Hamiltonian, the stage
-//      combination, the store.
-// Each interval goes through the same interval() arithmetic as in every
-// other variant, so the bits do not depend on the launch shape.  Addresses
-// are 32-bit offsets inside one plane (seven planes for the gathered axis)
-// from a 64-bit base that is the same for the whole block (the host checks
-// that they fit in 4 GiB).
-// Blocks are renumbered so that each XCD takes a contiguous run of them with
-// axis 1 varying fastest (4-D): the planes a node's axis-1 stencil reads are
-// then read by neighbouring blocks of the same XCD, through its L2.
 // The seven planes of the gathered axis for one of the six end lines of a
 // non-periodic axis 1 (CASE 0..2: lines 0..2; 3..5: lines n-3..n-1): the
 // planes inside the grid through one buffer, then each ghost plane by
@@ -93,6 +68,36 @@ __device__ __forceinline__ void end_line_planes(const T *pk, int jd, int sg, siz
 template <typename T>
 constexpr int tile_min_waves() { return sizeof(T) == 4 ? 6 : 1; }
 
+// NT threads own a tile of TX x TY nodes of the plane of the two fastest
+// axes (AF along the lanes, AM across; TX * TY <= 512, so at most 512 / NT
+// nodes per thread) and march over `march` consecutive nodes of the slowest axis
+// AK = 0.  In 4-D axis 1 is gathered node by node from seven planes that lie
+// one plane of AM x AF apart, close enough to share one L2.  Per marched
+// plane:
+//   1. the tile's halo, three nodes beyond it on both plane axes, is staged
+//      in LDS (ghosts filled; the tile's corners are never read and never
+//      staged), and every thread writes its own nodes from its marched queue;
+//   2. every interval of the tile along AF (TY rows of TX + 1) and along AM
+//      (TY + 1 rows of TX) is evaluated exactly once, the items dealt evenly
+//      over the NT threads, and its two one-sided values go to LDS;
+//   3. each thread finishes its nodes: the marched axis from a register
+//      queue of seven values (the interval right of the node, its left half
+//      kept for the next plane), axis 1 in 4-D (both sides at the node), then
+//      the plane axes' values from LDS, the Hamiltonian, the stage
+//      combination, the store.
+// Each interval goes through the same interval() arithmetic as in every
+// other variant, so the bits do not depend on the launch shape.  Addresses
+// are 32-bit offsets inside one plane (seven planes for the gathered axis)
+// from a 64-bit base that is the same for the whole block (the host checks
+// that they fit in 4 GiB).
+// Blocks are renumbered so that each XCD takes a contiguous run of them with
+// axis 1 varying fastest (4-D): the planes a node's axis-1 stencil reads are
+// then read by neighbouring blocks of the same XCD, through its L2.
+// In 4-D a stage is two launches (LINES): the lines of axis 1 whose seven
+// planes all lie inside the grid, which read them through one buffer
+// resource, and the six end lines, whose ghost planes are extrapolated
+// (end_line_planes) or wrapped; a grid with fewer than seven lines takes one
+// launch over all of them.
 template <typename T, int D, int SCHEME, int HAM, int MODE, int NT, int LINES>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tile_min_waves<T>())))
 void stage_tile_kernel(StageArgs<T> a, TileLaunch tl)
