@@ -287,7 +287,8 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
  * target: device array for min-with-target, or NULL for none (target may be
  * phi0, but not phi_out); phi_out: result (may be phi0 itself).  t1 >= t0.
  * The call enqueues a NaN/Inf check of phi0, the steps and a check of the
- * result, then synchronises `stream` once.  Returns HJX_ERR_NONFINITE if
+ * result (under HJX_TILE_STEPS the first and the last stepping launch make
+ * the two checks themselves), then synchronises `stream` once.  Returns HJX_ERR_NONFINITE if
  * phi0 or the result holds NaN/Inf (phi_out is written either way).
  * stats (optional, host) receives the step record.
  * When the same solve (the same phi0, target, phi_out, t0 and t1) is asked

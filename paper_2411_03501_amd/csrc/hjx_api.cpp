@@ -374,7 +374,7 @@ hipError_t launch_stage(const hjx_problem *p, const double *alpha, const void *i
 // k whole RK steps of the steps variant from in into out (different arrays),
 // each of size dt but the last, of dt_last; the target after every step.
 hipError_t launch_steps(const hjx_problem *p, const double *alpha, const void *in, const void *target, void *out,
-                        int k, double dt, double dt_last, hipStream_t s)
+                        int k, double dt, double dt_last, hipStream_t s, int *flag_in, int *flag_out)
 {
     const GridGeom g = geometry(p);
     long area = 0;
@@ -388,6 +388,8 @@ hipError_t launch_steps(const hjx_problem *p, const double *alpha, const void *i
     l.ty = p->tile.ty;
     l.tiles_x = (g.n[g.dim - 1] + l.tx - 1) / l.tx;
     l.area_max = (int)area;
+    l.flag_in = flag_in;
+    l.flag_out = flag_out;
     // (area is for the tile's own number of steps; a launch of fewer has a
     // shallower halo and fits in it)
     if (p->scheme.dtype == HJX_F32) {
@@ -539,14 +541,16 @@ void schedule(double t0, double t1, double dt, int64_t *steps, double *dt_last)
 // RK2/RK3 stages of the first step take phi0 as phi^n and write their last
 // stage into phi_out, which later steps advance in place.
 hipError_t enqueue_steps(const hjx_problem *p, const double *alpha, const void *phi0, const void *target,
-                         void *phi_out, int64_t steps, double dt, double dt_last, hipStream_t s)
+                         void *phi_out, int64_t steps, double dt, double dt_last, hipStream_t s, int *flags)
 {
     hipError_t e = hipSuccess;
     if (steps == 0) return phi_out == phi0 ? hipSuccess : launch_copy(p, phi0, phi_out, s);
     if (p->tile.variant == kVariantSteps) {
         // k steps per launch; launches alternate between the two workspaces
         // and the last lands in phi_out (through ws[0] and a copy when a
-        // single launch would read and write phi_out)
+        // single launch would read and write phi_out).  With flags, the first
+        // launch checks phi0 into flags[0] and the last its result into
+        // flags[1] (the non-finite checks of hjx_solve).
         const int k = p->tile.march;
         const int64_t launches = (steps + k - 1) / k;
         const void *src = phi0;
@@ -555,7 +559,8 @@ hipError_t enqueue_steps(const hjx_problem *p, const double *alpha, const void *
             const int ki = (int)std::min<int64_t>(k, steps - i * k);
             void *dst = final ? phi_out : p->ws[i & 1];
             if (dst == src) dst = p->ws[0];
-            e = launch_steps(p, alpha, src, target, dst, ki, dt, final ? dt_last : dt, s);
+            e = launch_steps(p, alpha, src, target, dst, ki, dt, final ? dt_last : dt, s,
+                             flags && i == 0 ? flags : nullptr, flags && final ? flags + 1 : nullptr);
             if (e == hipSuccess && final && dst != phi_out) e = launch_copy(p, dst, phi_out, s);
             src = dst;
         }
@@ -600,11 +605,11 @@ hipError_t enqueue_steps(const hjx_problem *p, const double *alpha, const void *
 
 // the stepping launches captured on the problem's own stream into a graph
 hjx_status capture_steps(hjx_problem *p, const double *alpha, const void *phi0, const void *target, void *phi_out,
-                         int64_t steps, double dt, double dt_last)
+                         int64_t steps, double dt, double dt_last, int *flags)
 {
     if (!p->cap) HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = enqueue_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, p->cap);
+    const hipError_t e = enqueue_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, p->cap, flags);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(p->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -966,9 +971,9 @@ hjx_status hjx_tune(hjx_problem *p, const void *phi, int32_t reps, const char *c
     HIP_TRY(hipMalloc(&work, (size_t)p->total * p->elem));
     auto timed = [&](float *ms) -> hipError_t {
         hipError_t e;
-        if ((e = enqueue_steps(p, alpha, phi, nullptr, work, reps, h, h, s)) != hipSuccess) return e;  // untimed
+        if ((e = enqueue_steps(p, alpha, phi, nullptr, work, reps, h, h, s, nullptr)) != hipSuccess) return e;  // untimed
         if ((e = hipEventRecord(p->ev[0], s)) != hipSuccess) return e;
-        if ((e = enqueue_steps(p, alpha, phi, nullptr, work, reps, h, h, s)) != hipSuccess) return e;
+        if ((e = enqueue_steps(p, alpha, phi, nullptr, work, reps, h, h, s, nullptr)) != hipSuccess) return e;
         if ((e = hipEventRecord(p->ev[1], s)) != hipSuccess) return e;
         if ((e = hipEventSynchronize(p->ev[1])) != hipSuccess) return e;
         return hipEventElapsedTime(ms, p->ev[0], p->ev[1]);
@@ -1063,25 +1068,28 @@ hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void 
     schedule(t0, t1, dt, &steps, &dt_last);
 
     // the input check, the stepping launches, the output check, then the
-    // one host synchronisation of the call
+    // one host synchronisation of the call (the steps variant checks inside
+    // its first and last launches: two launches fewer)
+    const bool fused = p->tile.variant == kVariantSteps && steps > 0;
+    int *flags = fused ? p->dflag : nullptr;
     HIP_TRY(hipMemsetAsync(p->dflag, 0, 2 * sizeof(int), s));
-    HIP_TRY(check_nonfinite(p, phi0, 0, s));
+    if (!fused) HIP_TRY(check_nonfinite(p, phi0, 0, s));
     if (stats) HIP_TRY(hipEventRecord(p->ev[0], s));
     const hjx_problem::SolveKey key{phi0, target, phi_out, t0, t1};
     if (p->exec && p->have_key && key == p->last_key) {
         HIP_TRY(hipGraphLaunch(p->exec, s));
     } else if (solve_graphs_on() && steps > 1 && p->have_key && key == p->last_key) {
         // the same solve a second time in a row: capture it once, replay it from now on
-        if ((st = capture_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last)) != HJX_OK) return st;
+        if ((st = capture_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, flags)) != HJX_OK) return st;
         HIP_TRY(hipGraphLaunch(p->exec, s));
     } else {
         drop_solve_graph(p);
-        HIP_TRY(enqueue_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, s));
+        HIP_TRY(enqueue_steps(p, alpha, phi0, target, phi_out, steps, dt, dt_last, s, flags));
         p->last_key = key;
         p->have_key = true;
     }
     if (stats) HIP_TRY(hipEventRecord(p->ev[1], s));
-    HIP_TRY(check_nonfinite(p, phi_out, 1, s));
+    if (!fused) HIP_TRY(check_nonfinite(p, phi_out, 1, s));
     int *hflag = reinterpret_cast<int *>(p->hbuf + kMaxDim);
     HIP_TRY(hipMemcpyAsync(hflag, p->dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

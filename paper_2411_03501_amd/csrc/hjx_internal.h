@@ -293,6 +293,8 @@ struct StepsLaunch {
     int tx, ty;          // output tile
     int tiles_x;         // tiles along the fastest axis (blocks: tiles_x * tiles along axis 0)
     int area_max;        // LDS values per buffer (the largest region of any block)
+    int *flag_in;        // nullable: set to 1 if a value loaded from the input is NaN or Inf
+    int *flag_out;       // nullable: set to 1 if a value stored is NaN or Inf
 };
 
 // LDS buffers of the steps variant: the stage input and phi^n, plus a third

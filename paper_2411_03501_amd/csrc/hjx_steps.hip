@@ -91,13 +91,19 @@ __global__ __launch_bounds__(kStepsThreads) void steps_kernel(StageArgs<T> a, St
     T *Xb = P + l.area_max;
     T *const Yb = Xb + l.area_max;  // RK3 only
 
-    // the region from the stage input, periodic axes wrapped
+    // the region from the stage input, periodic axes wrapped (every node of
+    // the input lies in some block's region, so with flag_in the launch also
+    // checks the whole input for NaN and Inf)
     const float rw = 1.0f / (float)w;
+    bool bad = false;
     for (int q = threadIdx.x; q < w * h; q += kStepsThreads) {
         const int py = D == 2 ? row_of(q, rw) : 0, px = q - py * w;
         const int gx = wrap1(rx0 + px, nx), gy = D == 2 ? wrap1(ry0 + py, ny) : 0;
-        P[q] = ld32(a.phi_in, gy * nx + gx);
+        const T v = ld32(a.phi_in, gy * nx + gx);
+        bad |= !__builtin_isfinite(v);
+        P[q] = v;
     }
+    if (l.flag_in && bad) atomicOr(l.flag_in, 1);
     __syncthreads();
 
     int m = 0;  // stages done
@@ -171,11 +177,15 @@ __global__ __launch_bounds__(kStepsThreads) void steps_kernel(StageArgs<T> a, St
     // the tile itself
     const int tw = x1 - x0, tcnt = tw * (y1 - y0);
     const float rtw = 1.0f / (float)tw;
+    bad = false;
     for (int q = threadIdx.x; q < tcnt; q += kStepsThreads) {
         const int qy = D == 2 ? row_of(q, rtw) : 0;
         const int x = x0 + (q - qy * tw), y = y0 + qy;
-        at32(a.out, y * nx + x) = P[(y - ry0) * w + (x - rx0)];
+        const T v = P[(y - ry0) * w + (x - rx0)];
+        bad |= !__builtin_isfinite(v);
+        at32(a.out, y * nx + x) = v;
     }
+    if (l.flag_out && bad) atomicOr(l.flag_out, 1);
 }
 
 template <typename T, int D, int SCHEME, int HAM, int M>

@@ -192,3 +192,30 @@ def test_steps_tile_validation():
     assert e.value.status == hjx.HJX_ERR_UNSUPPORTED
     # the default for a small 2-D grid is the steps variant
     assert gpu_problem(GRIDS["2d"], "f64").tile[0] == hjx.TILE_STEPS
+
+
+@pytest.mark.parametrize("tile", [(hjx.TILE_STEPS, 8, 8, 4), (hjx.TILE_STEPS, 16, 16, 1), DIRECT])
+def test_nonfinite_checks(tile):
+    """hjx_solve reports NaN/Inf in phi0 and in its result, whether the checks
+    are separate launches (direct) or run inside the first and last launches
+    of the steps variant; the result is written either way.  A finite spike
+    of +-1e308 overflows the differences of the first step."""
+    w = GRIDS["2d"]
+    P = gpu_problem(w, "f64")
+    P.tile = tile
+    t1 = 3.5 * P.dissipation()[1]
+    phi = inputs.smooth_field(w.n, 61)
+    bad_in = phi.copy()
+    bad_in[5, 7] = np.nan
+    with pytest.raises(hjx.HjxError) as e:
+        P.solve(to_dev(bad_in, torch.float64), t1)
+    assert e.value.status == hjx.HJX_ERR_NONFINITE and "phi0" in str(e.value)
+    spike = phi.copy()
+    spike[10, 10], spike[10, 11] = 1e308, -1e308
+    out = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(hjx.HjxError) as e:
+        P.solve(to_dev(spike, torch.float64), t1, out=out)
+    assert e.value.status == hjx.HJX_ERR_NONFINITE and "solution" in str(e.value)
+    assert not torch.isfinite(out).all() and torch.isfinite(out).any()
+    ok, st = P.solve(to_dev(phi, torch.float64), t1)   # a clean solve after the errors
+    assert st["steps"] == 4 and torch.isfinite(ok).all()
