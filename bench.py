@@ -750,10 +750,8 @@ def roofline(w, dtype, st, loop_ms):
     bytes_launch = stage_bytes_per_point(w.rk, w.with_target, elem) * w.points
     achieved_gbs = bytes_launch / kern_s / 1e9
     traffic = measured_traffic(w, dtype, st["tile"])
-    if st["tile"][0] == 1:
-        kernel_name = "stage_direct_kernel"
-    else:
-        kernel_name = "stage_tile_kernel" if w.dim >= 3 else "stage_kernel (plane-march)"
+    kernel_name = {1: "stage_direct_kernel", 2: "steps_kernel"}.get(
+        st["tile"][0], "stage_tile_kernel" if w.dim >= 3 else "stage_kernel (plane-march)")
     if w.scheme == "weno5":
         return {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
                 "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,

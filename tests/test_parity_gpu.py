@@ -41,6 +41,10 @@ CASES = {
     "normal2d": _w("normal2d", [-1, -2], [1, 1], [13, 29], params=(0.9,)),
     "normal3d": _w("normal3d", [-1, -1, 0], [1, 2, 1], [11, 17, 23], periodic=(1,), params=(1.1,)),
     "normal4d": _w("normal4d", [0, 0, 0, 0], [1, 1, 1, 1], [7, 9, 11, 13], periodic=(0, 3), params=(0.6,)),
+    # 3-D with a periodic axis 0 (the tile kernel's march wraps) and with a
+    # short axis 0 (every march chunk touches both ends)
+    "normal3d_per0": _w("normal3d_per0", [0, -1, 0], [1, 1, 2], [9, 7, 10], periodic=(0,), params=(0.9,)),
+    "normal3d_small0": _w("normal3d_small0", [0, 0, 0], [1, 1, 1], [5, 9, 12], params=(1.2,)),
     # axis 1 periodic with more than six lines: the 4-D tile kernel's interior
     # lines (one buffer over seven planes) and its end lines (wrapped) both run
     "normal4d_per1": _w("normal4d_per1", [0, 0, 0, 0], [1, 1, 1, 1], [6, 11, 9, 10], periodic=(1,), params=(0.8,)),
@@ -289,11 +293,13 @@ def test_repeat_runs_are_bitwise_identical():
 TILES = [(8, 8, 1), (16, 4, 3), (13, 7, 2), (32, 8, 5), (64, 4, 16), (5, 3, 1), (1, 1, 1)]
 
 
-@pytest.mark.parametrize("case", ["normal1d", "normal2d", "normal3d", "normal4d", "normal4d_per1", "dubins3", "car4"])
+@pytest.mark.parametrize("case", ["normal1d", "normal2d", "normal3d", "normal3d_per0", "normal3d_small0", "normal4d",
+                                  "normal4d_per1", "dubins3", "car4"])
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_results_do_not_depend_on_the_tile(case, scheme):
     """Every interval is evaluated by the same arithmetic whatever the launch
-    shape: results must agree bit for bit (an LDS race would show here)."""
+    shape (plane-march or tile kernel, or direct): results must agree bit for
+    bit (an LDS race would show here)."""
     w = CASES[case].with_(scheme=scheme)
     phi = inputs.rough_field(w.n, 12)
     tgt = inputs.rough_field(w.n, 13)
