@@ -538,17 +538,6 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     }
     __syncthreads();
 
-    // adjoint of the difference at half-node m (between m and m+1): the five
-    // intervals m-2 .. m+2 (those outside this tile carry zero seeds here)
-    auto ubar = [&](int m) -> T {
-        T s = T(0);
-#pragma unroll
-        for (int r = 0; r < 5; ++r) {
-            const int iv = m + 2 - r - (l0 - 3);
-            if (iv >= 0 && iv < NI) s += UB[lds_at<LX>(iv * 5 + r, ic, NI * 5, lw)];
-        }
-        return s;
-    };
     // the two half-nodes of a node of this tile, m = g - 1 and g, read the
     // intervals ip .. ip + 5, all inside the tile: no bounds checks.  Half-node
     // g - 1 + o (o = 0, 1) takes difference r of interval ip + 4 + o - r, at
@@ -562,24 +551,30 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
     };
     const int g = l0 + ip;
     if (ip < tl && g < nd && col_ok) {
-        T acc = (ubar_in(0) - ubar_in(1)) * a.inv_dx;
-        if (!per) {
-            // ghosts phi[-k] = (1+k) phi_0 - k phi_1 and
-            // phi[nd-1+k] = (1+k) phi_{nd-1} - k phi_{nd-2}, k = 1..3
-            if (g <= 1) {
-                for (int k = 1; k <= 3; ++k) {
-                    const T gb = (ubar(-k - 1) - ubar(-k)) * a.inv_dx;
-                    acc += (g == 0 ? T(1 + k) : T(-k)) * gb;
-                }
-            }
+        T uL = ubar_in(0), uR = ubar_in(1);   // adjoints of the differences left and right of g
+        if (!per && (g <= 1 || g >= nd - 2)) {
+            // Linear extrapolation makes every ghost difference beyond an end
+            // the end difference itself (half-node 0, or nd - 2), as a
+            // function of the nodes: the adjoints of the ghost differences
+            // fold onto that half-node.  They sit in six slots at each end:
+            // differences r of intervals -1 (r = 0..2), 0 (r = 0, 1) and 1
+            // (r = 0) on the left, nd - 3 (r = 4), nd - 2 (r = 3, 4) and nd - 1
+            // (r = 2..4) on the right; intervals further out carry no seeds.
+            // A node within two of an end lies in the first tile (l0 = 0) or
+            // sees intervals nd - 3 .. nd - 1 in its own tile.
+            const T *ub_col = UB + lds_at<LX>(0, ic, NI * 5, lw);
+            auto slot = [&](int iv, int r) -> T { return ub_col[lx ? iv * 5 + r : (iv * 5 + r) << lw]; };
+            T eL = T(0), eR = T(0);
+            if (g <= 1) eL = ((slot(2, 0) + slot(2, 1)) + (slot(2, 2) + slot(3, 0))) + (slot(3, 1) + slot(4, 0));
             if (g >= nd - 2) {
-                for (int k = 1; k <= 3; ++k) {
-                    const int q = nd - 1 + k;
-                    const T gb = (ubar(q - 1) - ubar(q)) * a.inv_dx;
-                    acc += (g == nd - 1 ? T(1 + k) : T(-k)) * gb;
-                }
+                const int j = nd - l0;   // interval nd - 3 of the tile
+                eR = ((slot(j, 4) + slot(j + 1, 3)) + (slot(j + 1, 4) + slot(j + 2, 2))) +
+                     (slot(j + 2, 3) + slot(j + 2, 4));
             }
+            uL = ((g == 0 ? T(0) : uL) + (g == 1 ? eL : T(0))) + (g == nd - 1 ? eR : T(0));
+            uR = ((g == nd - 1 ? T(0) : uR) + (g == 0 ? eL : T(0))) + (g == nd - 2 ? eR : T(0));
         }
+        const T acc = (uL - uR) * a.inv_dx;
         if (a.out) at32(a.out, base + g * sd) = acc;
         else at32(a.lam, base + g * sd) += acc;
     }

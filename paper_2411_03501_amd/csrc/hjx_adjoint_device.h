@@ -102,17 +102,27 @@ __device__ __forceinline__ void interval_vjp(const T *v, T inv_dx, T dx, T gm, T
         const T A0 = fmaT(T(-2), u[1], u[0] + u[2]), B0 = fmaT(T(-4), u[1], fmaT(T(3), u[2], u[0]));
         const T A1 = fmaT(T(-2), u[2], u[1] + u[3]), B1 = u[1] - u[3];
         const T A2 = fmaT(T(-2), u[3], u[2] + u[4]), B2 = fmaT(T(-4), u[3], fmaT(T(3), u[2], u[4]));
-        const T s0 = fmaT(k1312 * A0, A0, k14 * B0 * B0);
-        const T s1 = fmaT(k1312 * A1, A1, k14 * B1 * B1);
-        const T s2 = fmaT(k1312 * A2, A2, k14 * B2 * B2);
-        int km = 0;
-        T m = u[0] * u[0];
+        // S_k = cA_k A_k + cB_k B_k with cA_k = 13/12 A_k, cB_k = B_k / 4
+        const T cA0 = k1312 * A0, cA1 = k1312 * A1, cA2 = k1312 * A2;
+        const T cB0 = k14 * B0, cB1 = k14 * B1, cB2 = k14 * B2;
+        const T s0 = fmaT(cA0, A0, cB0 * B0);
+        const T s1 = fmaT(cA1, A1, cB1 * B1);
+        const T s2 = fmaT(cA2, A2, cB2 * B2);
+        // eps = 1e-6 max_k u_k^2 + floor; the lane masks c_k say where u_k^2
+        // exceeds every earlier square, so the first maximising k is the
+        // last k whose mask is set
+        T sq[5];
 #pragma unroll
-        for (int k = 1; k < 5; ++k)
-            if (u[k] * u[k] > m) {
-                m = u[k] * u[k];
-                km = k;
-            }
+        for (int k = 0; k < 5; ++k) sq[k] = u[k] * u[k];
+        const bool c1 = sq[1] > sq[0];
+        T m = c1 ? sq[1] : sq[0];
+        const bool c2 = sq[2] > m;
+        m = c2 ? sq[2] : m;
+        const bool c3 = sq[3] > m;
+        m = c3 ? sq[3] : m;
+        const bool c4 = sq[4] > m;
+        m = c4 ? sq[4] : m;
+        const bool is[5] = {!(c1 || c2 || c3 || c4), c1 && !(c2 || c3 || c4), c2 && !(c3 || c4), c3 && !c4, c4};
         const T eps = fmaT(T(1e-6), m, Arith<T>::kEpsFloor);
         const T r0 = Arith<T>::rcp(s0 + eps), r1 = Arith<T>::rcp(s1 + eps), r2 = Arith<T>::rcp(s2 + eps);
         const T q0 = r0 * r0, q1 = r1 * r1, q2 = r2 * r2;
@@ -124,44 +134,53 @@ __device__ __forceinline__ void interval_vjp(const T *v, T inv_dx, T dx, T gm, T
         const T a0 = T(0.1) * q0, a1 = T(0.6) * q1, a2 = T(0.3) * q2;
         const T iDf = Arith<T>::rcp(a0 + a1 + a2);
         const T fwd = fmaT(a0, f0, fmaT(a1, f1, a2 * f2)) * iDf;
-        const T g0 = fmaT(c13, u[4], fmaT(-c76, u[3], c116 * u[2]));
-        const T g1 = fmaT(-c16, u[3], fmaT(c56, u[2], c13 * u[1]));
-        const T g2 = fmaT(c13, u[2], fmaT(c56, u[1], -c16 * u[0]));
-        const T b0 = T(0.1) * q2, b1 = T(0.6) * q1, b2 = T(0.3) * q0;
-        const T iDr = Arith<T>::rcp(b0 + b1 + b2);
-        const T rev = fmaT(b0, g0, fmaT(b1, g1, b2 * g2)) * iDr;
+        // the mirrored substencils differ from the forward ones by half a
+        // B: g2 = f0 - B0/2, g1 = f1 + B1/2, g0 = f2 + B2/2
+        const T g0 = fmaT(T(0.5), B2, f2), g1 = fmaT(T(0.5), B1, f1), g2 = fmaT(T(-0.5), B0, f0);
+        const T b0 = T(0.1) * q2, b2 = T(0.3) * q0;   // and b1 = a1
+        const T iDr = Arith<T>::rcp(b0 + a1 + b2);
+        const T rev = fmaT(b0, g0, fmaT(a1, g1, b2 * g2)) * iDr;
         // reverse: weighted means -> substencils and weights.  With the
         // normalised weights W_k = a_k / sum a (each in [0, 1]) the
         // sensitivity of the mean to S_k is -2 W_k (f_k - mean) / (S_k + eps);
         // written this way no intermediate overflows, even at the eps floor
         // (flat data) where q_k = 1/(S_k + eps)^2 alone is near the top of
-        // the binary32 range.
+        // the binary32 range.  The seeds enter scaled by -4 (exact), so that
+        // t_k below is twice the adjoint of S_k and the factors 2 of the
+        // squares in S_k cancel.
         const T wf0 = a0 * iDf, wf1 = a1 * iDf, wf2 = a2 * iDf;
-        const T wr0 = b0 * iDr, wr1 = b1 * iDr, wr2 = b2 * iDr;
-        const T fb0 = gm * wf0, fb1 = gm * wf1, fb2 = gm * wf2;   // adjoints of f_k
-        const T gb0 = gp * wr0, gb1 = gp * wr1, gb2 = gp * wr2;   // adjoints of g_k
+        const T wr0 = b0 * iDr, wr1 = a1 * iDr, wr2 = b2 * iDr;
+        const T gmq = T(-4) * gm, gpq = T(-4) * gp;
+        const T F0 = gmq * wf0, F1 = gmq * wf1, F2 = gmq * wf2;   // -4 x the adjoints of f_k
+        const T G0 = gpq * wr0, G1 = gpq * wr1, G2 = gpq * wr2;   // -4 x the adjoints of g_k
         // b_k weights q_{2-k}: S_0 enters rev through wr2, S_2 through wr0
-        const T sb0 = T(-2) * r0 * fmaT(fb0, f0 - fwd, gb2 * (g2 - rev));
-        const T sb1 = T(-2) * r1 * fmaT(fb1, f1 - fwd, gb1 * (g1 - rev));
-        const T sb2 = T(-2) * r2 * fmaT(fb2, f2 - fwd, gb0 * (g0 - rev));
-        const T epsb = sb0 + sb1 + sb2;
-        // S_k = 13/12 A_k^2 + 1/4 B_k^2
-        const T Ab0 = T(2) * k1312 * A0 * sb0, Bb0 = T(2) * k14 * B0 * sb0;
-        const T Ab1 = T(2) * k1312 * A1 * sb1, Bb1 = T(2) * k14 * B1 * sb1;
-        const T Ab2 = T(2) * k1312 * A2 * sb2, Bb2 = T(2) * k14 * B2 * sb2;
+        const T t0 = r0 * fmaT(F0, f0 - fwd, G2 * (g2 - rev));
+        const T t1 = r1 * fmaT(F1, f1 - fwd, G1 * (g1 - rev));
+        const T t2 = r2 * fmaT(F2, f2 - fwd, G0 * (g0 - rev));
+        // adjoints of A_k and B_k; B_k also reaches the mirrored substencils
+        const T Ab0 = cA0 * t0, Ab1 = cA1 * t1, Ab2 = cA2 * t2;
+        const T Bb0 = fmaT(T(0.125), G2, cB0 * t0);
+        const T Bb1 = fmaT(T(-0.125), G1, cB1 * t1);
+        const T Bb2 = fmaT(T(-0.125), G0, cB2 * t2);
+        // eps = 1e-6 u_km^2 + floor: d/du_km = 2e-6 u_km times the sum of the
+        // adjoints of S_k, which is (t0 + t1 + t2) / 2
+        const T e = T(1e-6) * ((t0 + t1) + t2);
+        // the substencils, through f_k and the f_k inside g_{2-k}; their
+        // constants carry the -1/4 that undoes the scale of F and G
+        const T Ft0 = F0 + G2, Ft1 = F1 + G1, Ft2 = F2 + G0;
+        const T q4 = T(-0.25);
         ub[0] = Ab0 + Bb0;
         ub[1] = fmaT(T(-2), Ab0, fmaT(T(-4), Bb0, Ab1 + Bb1));
         ub[2] = Ab0 + fmaT(T(3), Bb0, fmaT(T(-2), Ab1, Ab2 + T(3) * Bb2));
         ub[3] = (Ab1 - Bb1) + fmaT(T(-2), Ab2, T(-4) * Bb2);
         ub[4] = Ab2 + Bb2;
-        // eps = 1e-6 max_k u_k^2 + floor
-        ub[km] = fmaT(T(2e-6) * epsb, u[km], ub[km]);
-        // substencils
-        ub[0] = fmaT(c13, fb0, fmaT(-c16, gb2, ub[0]));
-        ub[1] = fmaT(-c76, fb0, fmaT(-c16, fb1, fmaT(c13, gb1, fmaT(c56, gb2, ub[1]))));
-        ub[2] = fmaT(c116, fb0, fmaT(c56, fb1, fmaT(c13, fb2, fmaT(c116, gb0, fmaT(c56, gb1, fmaT(c13, gb2, ub[2]))))));
-        ub[3] = fmaT(c13, fb1, fmaT(c56, fb2, fmaT(-c76, gb0, fmaT(-c16, gb1, ub[3]))));
-        ub[4] = fmaT(-c16, fb2, fmaT(c13, gb0, ub[4]));
+        ub[0] = fmaT(q4 * c13, Ft0, ub[0]);
+        ub[1] = fmaT(q4 * -c76, Ft0, fmaT(q4 * -c16, Ft1, ub[1]));
+        ub[2] = fmaT(q4 * c116, Ft0, fmaT(q4 * c56, Ft1, fmaT(q4 * c13, Ft2, ub[2])));
+        ub[3] = fmaT(q4 * c13, Ft1, fmaT(q4 * c56, Ft2, ub[3]));
+        ub[4] = fmaT(q4 * -c16, Ft2, ub[4]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ub[k] = fmaT(is[k] ? e : T(0), u[k], ub[k]);
         // u_k = (v[k+1] - v[k]) inv_dx is applied by the caller per half-node
     } else {
         T d1[5];
