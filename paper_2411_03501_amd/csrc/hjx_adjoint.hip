@@ -465,46 +465,41 @@ __device__ __forceinline__ void axis_tile(const AdjAxisArgs<T> &a, int bx, int b
         base += by * a.g.stride[a.rest[0]];
     }
 
-    // a ghost along d: periodic wrap, else linear extrapolation from the two
-    // end nodes
-    auto phi_ghost = [&](int gpos) -> T {
-        if (per) return ld32(a.phi, base + wrap_near(gpos, nd) * sd);
-        const int e = gpos < 0 ? 0 : nd - 1, e2 = gpos < 0 ? 1 : nd - 2;
-        const T c = T(gpos < 0 ? -gpos : gpos - (nd - 1));
-        const T p0 = ld32(a.phi, base + e * sd), p1 = ld32(a.phi, base + e2 * sd);
-        return fmaT(c, p0 - p1, p0);
-    };
-
-    // stage phi and the seeds of this axis: thread (ip, ic) takes positions
-    // ip, ip + tl, ... of column ic, stepping its offset by tl strides (the
-    // line axis along the lanes is the fastest axis: stride 1)
+    // stage phi and the seeds of this axis in one pass: thread (ip, ic) takes
+    // positions ip, ip + tl, ... of column ic, stepping its offset by tl
+    // strides (the line axis along the lanes is the fastest axis: stride 1).
+    // Position p holds phi at node l0 - 5 + p and, for 2 <= p < NS + 2, the
+    // seeds of that node at seed position p - 2.  A ghost along d wraps on a
+    // periodic axis; otherwise phi is extrapolated linearly from the two end
+    // nodes and the ghost carries no seed.
     const int sdl = lx ? 1 : sd;
     const int step = tl * sdl;
     if (active) {
         int gpos = l0 - 5 + ip, off = base + gpos * sdl;
         for (int p = ip; p < NP; p += tl, gpos += tl, off += step) {
-            T v = T(0);
-            if (col_ok) v = (unsigned)gpos < (unsigned)nd ? ld32(a.phi, off) : phi_ghost(gpos);
-            PH[lds_at<LX>(p, ic, NP, lw)] = v;
-        }
-        gpos = l0 - 3 + ip;
-        off = base + gpos * sdl;
-        for (int p = ip; p < NS; p += tl, gpos += tl, off += step) {
-            T m = T(0), pl = T(0);
+            const bool seed = (unsigned)(p - 2) < (unsigned)NS;
+            T v = T(0), m = T(0), pl = T(0);
             if (col_ok) {
-                int o = off;
-                bool has = (unsigned)gpos < (unsigned)nd;
-                if (!has && per) {  // ghosts carry no seed unless they wrap
-                    o = base + wrap_near(gpos, nd) * sd;
-                    has = true;
-                }
-                if (has) {
-                    m = ld32(a.seed_m, o);
-                    pl = ld32(a.seed_p, o);
+                const bool in = (unsigned)gpos < (unsigned)nd;
+                if (in || per) {
+                    const int o = in ? off : base + wrap_near(gpos, nd) * sd;
+                    v = ld32(a.phi, o);
+                    if (seed) {
+                        m = ld32(a.seed_m, o);
+                        pl = ld32(a.seed_p, o);
+                    }
+                } else {
+                    const int e = gpos < 0 ? 0 : nd - 1, e2 = gpos < 0 ? 1 : nd - 2;
+                    const T c = T(gpos < 0 ? -gpos : gpos - (nd - 1));
+                    const T p0 = ld32(a.phi, base + e * sd), p1 = ld32(a.phi, base + e2 * sd);
+                    v = fmaT(c, p0 - p1, p0);
                 }
             }
-            SM[lds_at<LX>(p, ic, NS, lw)] = m;
-            SP[lds_at<LX>(p, ic, NS, lw)] = pl;
+            PH[lds_at<LX>(p, ic, NP, lw)] = v;
+            if (seed) {
+                SM[lds_at<LX>(p - 2, ic, NS, lw)] = m;
+                SP[lds_at<LX>(p - 2, ic, NS, lw)] = pl;
+            }
         }
     }
     __syncthreads();
