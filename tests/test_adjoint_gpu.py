@@ -181,6 +181,32 @@ def test_transposed_solve_dot_product(case):
     assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs)), (lhs, rhs)
 
 
+# axes of 3 to 5 nodes: on a linearly extrapolated axis the ghost
+# differences of both ends fold onto half-nodes 0 and n - 2, which meet or
+# share an interval here (the periodic theta axis wraps more than once)
+SHORT = {
+    "normal2d_weno5_3x4": inputs.NORMAL2D.with_(n=(3, 4), scheme="weno5", rk=3, t1=0.1),
+    "dubins3_weno5_4x3x5": inputs.DUBINS3D.with_(n=(4, 3, 5), t1=0.1),
+    "dubins3_eno3_3x5x6": inputs.DUBINS3D.with_(n=(3, 5, 6), t1=0.1, scheme="eno3", rk=2),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SHORT))
+def test_transposed_solve_dot_product_short_axes(case):
+    """The dot-product test on axes of 3 to 5 nodes."""
+    w = SHORT[case]
+    say(f"dot product {case} n={w.n}")
+    phi0, Po, eps = _setup(w)
+    lam_T = inputs.smooth_field(w.n, 93)
+    delta = inputs.smooth_field(w.n, 94)
+    _, g, _, _, _ = _gpu_grads(w, "f64", phi0, eps, dL_dphiT=lam_T)
+    _, _, _, _, tan = O.cs_solve_loss(Po, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps,
+                                      want_state=True)
+    lhs = float(np.sum(lam_T * tan))
+    rhs = float(np.sum(g * delta))
+    assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs)), (lhs, rhs)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_checkpoint_interval_does_not_change_the_gradient(dtype):
     """Segments of 1, 2, 5 and all steps: the last segment is shorter than
