@@ -316,8 +316,10 @@ hjx_status hjx_solve(hjx_problem *p, const void *phi0, const void *target, void 
  *               on the dissipation coefficients and on the CFL step (the
  *               number of steps held fixed).
  * Subgradient conventions at kinks: d|s|/ds = sign(s) with sign(0) = 0; at
- * a tie of min-with-target the evolved value is the one kept; a maximum of
- * the dissipation bound differentiates at its first maximising node. */
+ * a tie of min-with-target the evolved value is the one kept; a rate of
+ * exactly 0 under a restricted update is not clipped (derivative 1); a
+ * maximum of the dissipation bound differentiates at its first maximising
+ * node. */
 typedef struct hjx_tape hjx_tape;
 
 /* Create a tape for a solve of p from t0 to t1 (t1 >= t0) with a checkpoint
@@ -325,9 +327,11 @@ typedef struct hjx_tape hjx_tape;
  * `stream`) and allocates the checkpoints and the replay workspace: about
  * (steps/ckpt_every + 6 ckpt_every + 4 + 3 dim) arrays of the problem's size, plus
  * the derivative store of hjx_tape_set_mode.
- * Arrays must be under 4 GiB each, the scheme's restrict_update must be
- * HJX_RESTRICT_NONE and the Hamiltonian not ROCKETS (else
- * HJX_ERR_UNSUPPORTED). */
+ * Arrays must be under 4 GiB each and the Hamiltonian not ROCKETS (else
+ * HJX_ERR_UNSUPPORTED).  With a restricted update the replay also keeps, per
+ * stage, a byte per node that records where the rate was clipped: a clipped
+ * rate is the constant 0 and passes no adjoint (ckpt_every x rk more bytes
+ * per node in each of the two replay sets). */
 hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_every, void *stream,
                            hjx_tape **out);
 hjx_status hjx_tape_destroy(hjx_tape *tape);

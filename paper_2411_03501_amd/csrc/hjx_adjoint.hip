@@ -151,8 +151,11 @@ __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedN
 #pragma unroll
     for (int k = 0; k < kMaxDim; ++k)
         if (k < a.n_add) lo += s.add[k];
-    // where the target was kept, its adjoint takes lam_out
-    const bool kept = a.mask != nullptr && s.mk != 0;
+    // where the target was kept (bit 0 of the mask), its adjoint takes
+    // lam_out; where the replay clipped the rate (bit 1), the rate is the
+    // constant 0 and takes no adjoint
+    const bool kept = a.mask != nullptr && (s.mk & 1) != 0;
+    const bool clipped = a.mask != nullptr && (s.mk & 2) != 0;
     const T tg_new = s.tg_old + lo;
     if (kept) lo = T(0);
     T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
@@ -163,7 +166,7 @@ __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedN
     for (int d = 0; d < D; ++d) hhat = fmaT(-st.alpha[d], T(0.5) * (s.pp[d] - s.pm[d]), hhat);
     const T L = -hhat;
 
-    const T w = a.cb * a.h * lo;
+    const T w = clipped ? T(0) : a.cb * a.h * lo;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
@@ -173,7 +176,7 @@ __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedN
     }
 #pragma unroll
     for (int m = 0; m < NP; ++m) part[1 + D + m] += (double)(w * dmH[m]);
-    part[0] += (double)(a.cb * lo) * (double)L;
+    if (!clipped) part[0] += (double)(a.cb * lo) * (double)L;
 
     if (kept && a.lam_target) at32(a.lam_target, idx) = tg_new;
     const T cin = a.cb * lo;
@@ -333,7 +336,10 @@ __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) 
         j[0] = by / r.g.n[1];
         j[1] = by - j[0] * r.g.n[1];
     }
-    direct_node<T, D, SCHEME, HAM, STORED ? kNodeKeep : kNodePlain>(r, j);
+    // clip and mark take effect only for a restricted update (r.clip != 0):
+    // otherwise the values, and the target mask of a last stage, are those
+    // of the plain replay
+    direct_node<T, D, SCHEME, HAM, (STORED ? kNodeKeep : kNodePlain) | kNodeClip | kNodeMark>(r, j);
 }
 
 template <typename T, int D, int SCHEME, int HAM>

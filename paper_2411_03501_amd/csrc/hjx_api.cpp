@@ -1133,7 +1133,11 @@ struct hjx_tape {
     // while the reverse sweep of the next reads the other
     struct ReplaySet {
         std::vector<void *> phin, x1, xh;  // stage inputs of each step of a segment
-        std::vector<unsigned char *> mask; // where the target was the smaller
+        // the replay's decisions, a byte per node: bit 0 where the target was
+        // the smaller, bit 1 where a restricted update clipped the rate.  One
+        // array per step (its last stage) or, for a restricted update, per
+        // stage (step i, stage k at i rk + k).
+        std::vector<unsigned char *> mask;
         std::vector<void *> dp;            // p-, p+ of every stage (empty: recompute)
     } rs[2];
     void *lam[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1147,6 +1151,16 @@ struct hjx_tape {
     double *hacc = nullptr;            // pinned, kAccCount
     const void *target = nullptr;
     bool solved = false;
+    bool clip = false;                 // a restricted update: every stage keeps its mask
+
+    // the mask stage k of step i of a replay set writes (and its reverse
+    // reads), or null when that stage has no decision to keep
+    unsigned char *mask_of(const ReplaySet &r, int i, int k) const
+    {
+        const int rk = p->scheme.rk;
+        if (clip) return r.mask[(size_t)i * rk + k];
+        return k == rk - 1 && target ? r.mask[i] : nullptr;
+    }
 };
 
 namespace {
@@ -1263,8 +1277,6 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
         return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
     if (ckpt_every < 1) return fail(HJX_ERR_INVALID_ARG, "ckpt_every %d < 1", ckpt_every);
     if (!direct_ok(geometry(p), p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the adjoint needs arrays under 4 GiB");
-    if (p->scheme.restrict_update != HJX_RESTRICT_NONE)
-        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of a restricted update is not implemented");
     if (p->ham.kind == HJX_HAM_ROCKETS)
         return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the ROCKETS Hamiltonian is not implemented");
     if (p->ham.dissipation != HJX_DISS_GLOBAL)
@@ -1276,6 +1288,7 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     t->t0 = t0;
     t->t1 = t1;
     t->K = ckpt_every;
+    t->clip = p->scheme.restrict_update != HJX_RESTRICT_NONE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hjx_status st = device_alpha(p, s, t->alpha);
     if (st != HJX_OK) {
@@ -1289,7 +1302,8 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
     const int K = (int)std::min<int64_t>(t->K, std::max<int64_t>(t->steps, 1));
     {
         const int rk = p->scheme.rk;
-        const size_t sets = 2 * ((size_t)K * (1 + (rk >= 2) + (rk >= 3)) * field + (size_t)K * (size_t)p->total);
+        const size_t masks = (size_t)K * (t->clip ? rk : 1);
+        const size_t sets = 2 * ((size_t)K * (1 + (rk >= 2) + (rk >= 3)) * field + masks * (size_t)p->total);
         const size_t need = (size_t)t->nseg * field + sets + 4 * field +
                             (size_t)p->grid.dim * (p->grid.dim >= 2 ? 3 : 2) * field +
                             sizeof(double) * kAccCount * ((size_t)adj_seed_blocks(geometry(p)) + 1);
@@ -1317,7 +1331,7 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
             r.xh.assign(K, nullptr);
             for (auto &x : r.xh) grab(&x, field);
         }
-        r.mask.assign(K, nullptr);
+        r.mask.assign((size_t)K * (t->clip ? p->scheme.rk : 1), nullptr);
         for (auto &x : r.mask) grab(reinterpret_cast<void **>(&x), (size_t)p->total);
     }
     for (auto &x : t->lam) grab(&x, field);
@@ -1430,9 +1444,9 @@ hjx_status hjx_solve_taped(hjx_problem *p, hjx_tape *tape, const void *phi0, con
 
 namespace {
 
-// one forward stage for the replay, writing the min-with-target mask
 // One forward stage of a replay: out = ca phin + cb (in + h L(in)), min with
-// the target (its mask kept) when target is set, p-, p+ kept in dp (nullable).
+// the target when target is set; the stage's decisions go to mask (the
+// tape's mask_of; nullable) and p-, p+ to dp (nullable).
 struct ReplayStage {
     const void *in, *phin, *target;
     void *out;
@@ -1454,7 +1468,7 @@ StageArgs<T> replay_args(const hjx_problem *p, const double *alpha, const Replay
     a.dt = T(r.h);
     a.ca = T(r.ca);
     a.cb = T(r.cb);
-    a.mask = r.target ? r.mask : nullptr;
+    a.mask = r.mask;
     return a;
 }
 
@@ -1637,15 +1651,16 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
         for (int i = 0; i < len; ++i) {
             const double h = s0 + i == t->steps - 1 ? t->dt_last : t->dt;
             if (rk == 1) {
-                v.push_back({phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, R.mask[i], dp(i, 0)});
+                v.push_back({phin(i), nullptr, t->target, phin(i + 1), h, 0, 1, t->mask_of(R, i, 0), dp(i, 0)});
             } else if (rk == 2) {
-                v.push_back({phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0)});
-                v.push_back({R.x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, R.mask[i], dp(i, 1)});
-            } else {
-                v.push_back({phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, nullptr, dp(i, 0)});
-                v.push_back({R.x1[i], phin(i), nullptr, R.xh[i], h, 0.75, 0.25, nullptr, dp(i, 1)});
+                v.push_back({phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, t->mask_of(R, i, 0), dp(i, 0)});
                 v.push_back(
-                    {R.xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0, R.mask[i], dp(i, 2)});
+                    {R.x1[i], phin(i), t->target, phin(i + 1), h, 0.5, 0.5, t->mask_of(R, i, 1), dp(i, 1)});
+            } else {
+                v.push_back({phin(i), nullptr, nullptr, R.x1[i], h, 0, 1, t->mask_of(R, i, 0), dp(i, 0)});
+                v.push_back({R.x1[i], phin(i), nullptr, R.xh[i], h, 0.75, 0.25, t->mask_of(R, i, 1), dp(i, 1)});
+                v.push_back({R.xh[i], phin(i), t->target, phin(i + 1), h, 1.0 / 3.0, 2.0 / 3.0,
+                             t->mask_of(R, i, 2), dp(i, 2)});
             }
         }
         return v;
@@ -1674,7 +1689,7 @@ hjx_status hjx_adjoint(hjx_problem *p, hjx_tape *t, const void *dL_dphiT, void *
             void *stage_lam[2] = {t->lam[2], t->lam[3]};
             for (int k = rk - 1; k >= 0; --k) {
                 const bool last = k == rk - 1;
-                const unsigned char *mk = last && t->target ? R.mask[i] : nullptr;
+                const unsigned char *mk = t->mask_of(R, i, k);
                 void *ltgt = last && t->target ? dL_dtarget : nullptr;
                 const double ca = kCa[rk - 1][k], cb = kCb[rk - 1][k];
                 void *lin;

@@ -408,9 +408,11 @@ __device__ __forceinline__ T ham_value(const StageArgs<T> &a, const int *j, cons
 // What a stage node does besides its stage value, as bits: keep p-, p+ in
 // a.dp_out (the replay of the adjoint), clip the rate by a.clip (a restricted
 // update; a.clip may be 0 where one kernel serves clipped and unclipped
-// problems), take alpha_d at the node (local Lax-Friedrichs).  Solves that
-// use none of them never compile them.
-enum : int { kNodePlain = 0, kNodeKeep = 1, kNodeClip = 2, kNodeLocal = 4 };
+// problems), take alpha_d at the node (local Lax-Friedrichs), and mark in
+// a.mask where the rate was clipped (the replay of a restricted update; bit 1
+// of the mask byte, beside bit 0 for a kept target).  Solves that use none
+// of them never compile them.
+enum : int { kNodePlain = 0, kNodeKeep = 1, kNodeClip = 2, kNodeLocal = 4, kNodeMark = 8 };
 
 // Bound on |dH/dp_d| over the controls at node j (the local dissipation
 // coefficient; its grid maximum is the global alpha_d).
@@ -497,16 +499,35 @@ __device__ __forceinline__ T stage_result_at(const StageArgs<T> &a, const T *phi
                                              int idx)
 {
 #pragma clang fp contract(off)
-    const T L = stage_rate<T, D, HAM, MODE>(a, j, pm, pp);
-    if (a.rhs_only) return L;
-    T res = a.cb * fmaT(a.dt, L, center);
-    if (a.ca != T(0)) res = fmaT(a.ca, ld32(phi_n, idx), res);
-    if (target) {
-        const T tg = ld32(target, idx);
-        if (mask) mask[idx] = tg < res;
-        res = tg < res ? tg : res;
+    if constexpr ((MODE & kNodeMark) != 0) {
+        // the replay of a restricted update: the same value as under
+        // kNodeClip, with the clip and the target recorded in the mask byte
+        T L = stage_rate<T, D, HAM, MODE & ~kNodeClip>(a, j, pm, pp);
+        if (a.rhs_only) return L;
+        const bool clipped = (a.clip < 0 && L > T(0)) || (a.clip > 0 && L < T(0));
+        if (clipped) L = T(0);
+        T res = a.cb * fmaT(a.dt, L, center);
+        if (a.ca != T(0)) res = fmaT(a.ca, ld32(phi_n, idx), res);
+        bool kept = false;
+        if (target) {
+            const T tg = ld32(target, idx);
+            kept = tg < res;
+            res = kept ? tg : res;
+        }
+        if (mask) mask[idx] = (unsigned char)((kept ? 1 : 0) | (clipped ? 2 : 0));
+        return res;
+    } else {
+        const T L = stage_rate<T, D, HAM, MODE>(a, j, pm, pp);
+        if (a.rhs_only) return L;
+        T res = a.cb * fmaT(a.dt, L, center);
+        if (a.ca != T(0)) res = fmaT(a.ca, ld32(phi_n, idx), res);
+        if (target) {
+            const T tg = ld32(target, idx);
+            if (mask) mask[idx] = tg < res;
+            res = tg < res ? tg : res;
+        }
+        return res;
     }
-    return res;
 }
 
 template <typename T, int D, int HAM, int MODE = kNodePlain>
@@ -518,7 +539,7 @@ __device__ __forceinline__ T stage_result(const StageArgs<T> &a, const int *j, c
 
 // One node of the direct variant: gather every axis through the caches,
 // both derivative halves at the node, LF Hamiltonian, stage combination.
-// MODE: kNodePlain, kNodeKeep or kNodeClip (above).
+// MODE: the node-mode bits (above).
 template <typename T, int D, int SCHEME, int HAM, int MODE = kNodePlain>
 __device__ __forceinline__ void direct_node(const StageArgs<T> &a, const int *j)
 {

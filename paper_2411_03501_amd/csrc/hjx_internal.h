@@ -69,7 +69,7 @@ struct StageArgs {
     int clip;  // restricted update: 0 none, -1 L <- min(L, 0), +1 L <- max(L, 0) (not with rhs_only)
     int diss;  // 0: Lax-Friedrichs with alpha[d]; 1: with alpha_d at the node; 2: Godunov (normal motion)
     Tile tile;
-    unsigned char *mask;  // nullable: 1 where the target was the smaller (replay for the adjoint)
+    unsigned char *mask;  // nullable (replay for the adjoint): bit 0 where the target was the smaller, bit 1 where L was clipped
     T *dp_out;            // nullable: p-_d at dp_out + 2d dp_stride, p+_d at dp_out + (2d+1) dp_stride
     int dp_stride;
 };
@@ -85,15 +85,19 @@ enum : int {
 };
 
 // Reverse of one stage out = ca phi_n + cb (phi_in + h L(phi_in)) (then
-// min with the target when `mask` is set), given lam_out = dL/dout:
+// min with the target), given lam_out = dL/dout.  `mask` (nullable) holds
+// the replay's decisions per node: bit 0 where the target was kept, bit 1
+// where a restricted update clipped L to 0.
 //   lam_out' = lam_out where the evolved value was kept (the rest goes to
 //              the target's adjoint),
 //   lam_in  (=, or += when in_mode) cb lam_out' (+ the transposed spatial
 //              operator, added afterwards by the per-axis kernels from the
 //              seeds written here),
 //   lam_n   (=, or += when n_mode == 2) ca lam_out' when n_mode != 0,
-//   seeds   s-_d = w dL/dp-_d, s+_d = w dL/dp+_d with w = cb h lam_out',
-//   acc     dL/dh += cb lam_out' . L, dL/dalpha_d, dL/dtheta (per block).
+//   seeds   s-_d = w dL/dp-_d, s+_d = w dL/dp+_d with w = cb h lam_out'
+//              (0 where L was clipped),
+//   acc     dL/dh += cb lam_out' . L (unclipped nodes), dL/dalpha_d,
+//              dL/dtheta (per block).
 template <typename T>
 struct AdjSeedArgs {
     StageArgs<T> st;  // forward evaluation at st.phi_in (alpha, tables, parameters)

@@ -429,7 +429,7 @@ bool x2_applies(const StageArgs<T> &a)
     }
 }
 
-// One stage launch in node mode M (bits of kNodeKeep, kNodeClip, kNodeLocal).
+// One stage launch in node mode M (bits of kNodeKeep, kNodeClip, kNodeLocal, kNodeMark).
 template <typename T, int D, int SCHEME, int HAM, int M>
 hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
 {
@@ -442,9 +442,9 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
     if (D <= 2 && t.variant == kVariantPlaneMarch &&
         (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 256 || (D == 1 && t.ty != 1) || t.march < 1 || gy > 65535))
         return hipErrorInvalidConfiguration;
-    // only the direct variant keeps p-, p+; single stages of a problem whose
-    // solves take the steps variant run direct
-    if (t.variant == kVariantDirect || t.variant == kVariantSteps || (M & kNodeKeep) != 0) {
+    // only the direct variant keeps p-, p+ and marks clips; single stages of
+    // a problem whose solves take the steps variant run direct
+    if (t.variant == kVariantDirect || t.variant == kVariantSteps || (M & (kNodeKeep | kNodeMark)) != 0) {
         if (x2_applies<T, D, SCHEME>(a)) {
             const long threads = (long)a.g.n[0] * (a.g.n[1] / 2);
             const dim3 grid((unsigned)((threads + 255) / 256));
@@ -462,7 +462,7 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
             hipLaunchKernelGGL((stage_direct_kernel_f64<T, D, SCHEME, HAM, M>), grid, dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    if constexpr ((M & kNodeKeep) == 0) {
+    if constexpr ((M & (kNodeKeep | kNodeMark)) == 0) {
         if constexpr (D >= 3) {  // the tile kernel: 256 threads, up to 512 nodes of the plane tile
             if (t.tx < 1 || t.ty < 1 || t.tx * t.ty > 512 || t.march < 1) return hipErrorInvalidConfiguration;
             TileLaunch tl{};
@@ -503,14 +503,17 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-// The node mode of a stage: the replay that keeps p-, p+ (the adjoint) takes
-// neither the clip nor the local dissipation, which the adjoint rejects; the
+// The node mode of a stage: the replay for the adjoint keeps p-, p+ (when
+// the tape stores them) and, for a restricted update, marks its clips in the
+// mask; it never takes the local dissipation, which the adjoint rejects.  A
+// clipped stage with a mask is such a replay (solves pass no mask).  The
 // right-hand side alone is never clipped.  Plain stages run the kernels
-// without either.
+// without any of them.
 template <typename T, int D, int SCHEME, int HAM>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
-    const int mode = (a.dp_out ? kNodeKeep : 0) | (!a.rhs_only && a.clip != 0 ? kNodeClip : 0) |
+    const bool clip = !a.rhs_only && a.clip != 0;
+    const int mode = (a.dp_out ? kNodeKeep : 0) | (clip ? kNodeClip : 0) | (clip && a.mask ? kNodeMark : 0) |
                      (a.diss == 1 ? kNodeLocal : 0);
     if constexpr (HAM == kHamNormalGodunov) {  // no alpha, so no local form; no adjoint
         if (mode == kNodePlain) return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
@@ -521,6 +524,9 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
     case kNodePlain: return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
     case kNodeKeep: return launch_mode<T, D, SCHEME, HAM, kNodeKeep>(a, s);
     case kNodeClip: return launch_mode<T, D, SCHEME, HAM, kNodeClip>(a, s);
+    case kNodeClip | kNodeMark: return launch_mode<T, D, SCHEME, HAM, kNodeClip | kNodeMark>(a, s);
+    case kNodeKeep | kNodeClip | kNodeMark:
+        return launch_mode<T, D, SCHEME, HAM, kNodeKeep | kNodeClip | kNodeMark>(a, s);
     case kNodeLocal: return launch_mode<T, D, SCHEME, HAM, kNodeLocal>(a, s);
     case kNodeLocal | kNodeClip: return launch_mode<T, D, SCHEME, HAM, kNodeLocal | kNodeClip>(a, s);
     }

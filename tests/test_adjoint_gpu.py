@@ -41,6 +41,11 @@ CASES = {
     # long enough lines that every axis spans several LDS line tiles of the
     # transpose kernel (64 along the fastest axis, 16-32 along the others)
     "dubins3_multitile": inputs.DUBINS3D.with_(n=(69, 35, 66), t1=0.12),
+    # restricted updates (the clip of each stage is a 0/1 factor the replay
+    # records), with and without a target
+    "dubins3_weno5_rk3_nonpositive": inputs.DUBINS3D.with_(n=(17, 15, 13), t1=0.3, restrict="nonpositive"),
+    "normal2d_eno2_rk2_positive": inputs.NORMAL2D.with_(n=(25, 23), scheme="eno2", rk=2, t1=0.2,
+                                                        restrict="positive"),
 }
 
 
@@ -92,6 +97,12 @@ def test_adjoint_matches_oracle_directional_derivatives(case, dtype):
         got = float(np.sum(g * delta))
         assert abs(got - ref) <= TOL[dtype] * max(abs(ref), 1e-3 * np.abs(g).sum() * np.abs(delta).max()), \
             (case, dtype, seed, got, ref)
+        if w.restrict != "none" and seed == 81:
+            # the clips matter here: the unrestricted derivative is another
+            # number, well outside the tolerance
+            Pu = oracle_problem(w.with_(restrict="none"), decide=dtype)
+            _, plain, _ = O.cs_solve_loss(Pu, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps)
+            assert abs(plain - ref) > 5 * TOL[dtype] * abs(ref), (case, plain, ref)
     # dL/dtheta for every parameter of the Hamiltonian
     for m in range(len(w.params)):
         e = np.zeros(len(w.params))
@@ -166,7 +177,8 @@ def test_gradient_workload_against_oracle_jvps(oracle_jvps, dtype):
     assert not bad, bad
 
 
-@pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "car4_weno5_rk3", "normal2d_first_rk1"])
+@pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "car4_weno5_rk3", "normal2d_first_rk1",
+                                  "dubins3_weno5_rk3_nonpositive", "normal2d_eno2_rk2_positive"])
 def test_transposed_solve_dot_product(case):
     """<lam_T, J delta> (oracle tangent) = <J^T lam_T, delta> (GPU adjoint)."""
     w = CASES[case]
@@ -226,7 +238,8 @@ def test_checkpoint_interval_does_not_change_the_gradient(dtype):
 
 
 @pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "dubins3_eno3_rk2", "dubins3_eno2_rk1", "car4_weno5_rk3",
-                                  "normal2d_weno5_rk3", "dubins3_multitile"])
+                                  "normal2d_weno5_rk3", "dubins3_multitile", "dubins3_weno5_rk3_nonpositive",
+                                  "normal2d_eno2_rk2_positive"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_stored_and_recomputed_derivatives_give_the_same_bits(case, dtype):
     """The replay's derivative store is a cache: the reverse sweep that reads
