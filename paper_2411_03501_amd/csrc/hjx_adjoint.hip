@@ -76,7 +76,7 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[V], int lane)
 template <int HAM>
 constexpr int ham_params()
 {
-    return HAM == kHamDubins3 ? 4 : (HAM == kHamDubins4 ? 2 : 1);
+    return HAM == kHamDubins3 || HAM == kHamRockets ? 4 : (HAM == kHamDubins4 ? 2 : 1);
 }
 
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
@@ -141,7 +141,7 @@ __device__ __forceinline__ void seed_load(const AdjSeedArgs<T> &a, SeedNode<T, D
 
 // The arithmetic and stores of one node; its block-sum terms are added to
 // part: [0] dL/dh, [1..D] dL/dalpha_d, [D+1..D+NP] dL/dtheta.
-template <typename T, int D, int HAM, int V>
+template <typename T, int D, int HAM, int V, bool LOCAL>
 __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedNode<T, D> &s, double (&part)[V])
 {
     const StageArgs<T> &st = a.st;
@@ -162,18 +162,28 @@ __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedN
 #pragma unroll
     for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (s.pm[d] + s.pp[d]);
     T hhat = ham_grad<T, D, HAM>(st, s.tb, pbar, dHdp, dmH);
-#pragma unroll
-    for (int d = 0; d < D; ++d) hhat = fmaT(-st.alpha[d], T(0.5) * (s.pp[d] - s.pm[d]), hhat);
-    const T L = -hhat;
-
     const T w = clipped ? T(0) : a.cb * a.h * lo;
+    // alpha_d: the grid maximum, or (LOCAL) the bound at the node, whose
+    // parameter gradient then joins dL/dtheta here (the grid maxima only
+    // reach the parameters through the CFL step)
 #pragma unroll
     for (int d = 0; d < D; ++d) {
+        T al = st.alpha[d];
+        const T half = T(0.5) * (s.pp[d] - s.pm[d]);
+        if constexpr (LOCAL) {
+            T dbnd[8];
+            al = bound_grad<T, D, HAM>(st, s.tb, d, dbnd);
+#pragma unroll
+            for (int m = 0; m < NP; ++m) dmH[m] = fmaT(half, dbnd[m], dmH[m]);
+        } else {
+            part[1 + d] += (double)(w * half);
+        }
+        hhat = fmaT(-al, half, hhat);
         // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
-        at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * st.alpha[d]);
-        at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * st.alpha[d]);
-        part[1 + d] += (double)(w * T(0.5) * (s.pp[d] - s.pm[d]));
+        at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * al);
+        at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * al);
     }
+    const T L = -hhat;
 #pragma unroll
     for (int m = 0; m < NP; ++m) part[1 + D + m] += (double)(w * dmH[m]);
     if (!clipped) part[0] += (double)(a.cb * lo) * (double)L;
@@ -190,7 +200,7 @@ __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedN
 // Block (bx, by) of the seed pass: nodes bx*256 .. of the planes
 // by*P .. by*P+P-1 of the slow axes (P = seed_planes), gx blocks per plane.
 // Every thread of the block must call it (block reduction).
-template <typename T, int D, int SCHEME, int HAM, bool STORED>
+template <typename T, int D, int SCHEME, int HAM, bool STORED, bool LOCAL>
 __device__ __forceinline__ void seed_block(const AdjSeedArgs<T> &a, int bx, int by, int gx)
 {
     const StageArgs<T> &st = a.st;
@@ -254,7 +264,7 @@ __device__ __forceinline__ void seed_block(const AdjSeedArgs<T> &a, int bx, int 
         if (sy >= st.g.slow) break;
 #pragma unroll
         for (int k = 0; k < V; ++k) part[k] = 0.0;
-        if (ok[r]) seed_finish<T, D, HAM, V>(a, nd[r], part);
+        if (ok[r]) seed_finish<T, D, HAM, V, LOCAL>(a, nd[r], part);
         if (r > 0) __syncthreads();  // red of the plane before has been read
         const double mine = wave_reduce_scatter<V>(part, lane);
         if ((lane & ((1 << kShift) - 1)) == 0) red[wave][lane >> kShift] = mine;
@@ -269,10 +279,10 @@ __device__ __forceinline__ void seed_block(const AdjSeedArgs<T> &a, int bx, int 
     }
 }
 
-template <typename T, int D, int SCHEME, int HAM, bool STORED>
+template <typename T, int D, int SCHEME, int HAM, bool STORED, bool LOCAL>
 __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) void adj_seed_kernel(AdjSeedArgs<T> a)
 {
-    seed_block<T, D, SCHEME, HAM, STORED>(a, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+    seed_block<T, D, SCHEME, HAM, STORED, LOCAL>(a, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // The seed pass of one reversed stage and one forward stage of the replay of
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) 
 // blocks are renumbered, as in the direct stage kernel, so that each XCD
 // walks a contiguous run of them.  The stage keeps p-, p+ (dp_out) exactly
 // when the seed pass reads them.
-template <typename T, int D, int SCHEME, int HAM, bool STORED>
+template <typename T, int D, int SCHEME, int HAM, bool STORED, bool LOCAL>
 __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) void adj_seed_replay_kernel(
     AdjSeedArgs<T> a, StageArgs<T> r, int gx, int ns, int nr)
 {
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) 
         idx = seed ? groups * 8 + t : groups * 8 * P + (t - left);
     }
     if (seed) {
-        seed_block<T, D, SCHEME, HAM, STORED>(a, idx % gx, idx / gx, gx);
+        seed_block<T, D, SCHEME, HAM, STORED, LOCAL>(a, idx % gx, idx / gx, gx);
         return;
     }
     if ((nr & 7) == 0) idx = (idx & 7) * (nr >> 3) + (idx >> 3);
@@ -339,10 +349,11 @@ __global__ __launch_bounds__(kSeedThreads) __attribute__((amdgpu_num_sgpr(96))) 
     // clip and mark take effect only for a restricted update (r.clip != 0):
     // otherwise the values, and the target mask of a last stage, are those
     // of the plain replay
-    direct_node<T, D, SCHEME, HAM, (STORED ? kNodeKeep : kNodePlain) | kNodeClip | kNodeMark>(r, j);
+    direct_node<T, D, SCHEME, HAM,
+                (STORED ? kNodeKeep : kNodePlain) | kNodeClip | kNodeMark | (LOCAL ? kNodeLocal : kNodePlain)>(r, j);
 }
 
-template <typename T, int D, int SCHEME, int HAM>
+template <typename T, int D, int SCHEME, int HAM, bool LOCAL>
 hipError_t launch_seed_one(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, hipStream_t s)
 {
     const int gx = (a.st.g.plane + kSeedThreads - 1) / kSeedThreads;
@@ -357,31 +368,40 @@ hipError_t launch_seed_one(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, hip
         if (ns + nr > 0x7fffffffL) return hipErrorInvalidConfiguration;
         const dim3 grid((unsigned)(ns + nr));
         if (a.dp_in)
-            hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a,
+            hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, true, LOCAL>), grid, dim3(kSeedThreads), 0, s, a,
                                *rep, gx, (int)ns, (int)nr);
         else
-            hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, false>), grid, dim3(kSeedThreads), 0, s, a,
+            hipLaunchKernelGGL((adj_seed_replay_kernel<T, D, SCHEME, HAM, false, LOCAL>), grid, dim3(kSeedThreads), 0, s, a,
                                *rep, gx, (int)ns, (int)nr);
         return hipGetLastError();
     }
     const int P = a.dp_in ? seed_planes<T, D, true>() : seed_planes<T, D, false>();
     dim3 grid(gx, (a.st.g.slow + P - 1) / P);
     if (a.dp_in)
-        hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, true>), grid, dim3(kSeedThreads), 0, s, a);
+        hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, true, LOCAL>), grid, dim3(kSeedThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, false>), grid, dim3(kSeedThreads), 0, s, a);
+        hipLaunchKernelGGL((adj_seed_kernel<T, D, SCHEME, HAM, false, LOCAL>), grid, dim3(kSeedThreads), 0, s, a);
     return hipGetLastError();
 }
 
+template <typename T, int D, int HAM, bool LOCAL>
+hipError_t launch_seed_local(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int scheme, hipStream_t s)
+{
+    switch (scheme) {
+    case kSchemeFirst: return launch_seed_one<T, D, kSchemeFirst, HAM, LOCAL>(a, rep, s);
+    case kSchemeEno2: return launch_seed_one<T, D, kSchemeEno2, HAM, LOCAL>(a, rep, s);
+    case kSchemeEno3: return launch_seed_one<T, D, kSchemeEno3, HAM, LOCAL>(a, rep, s);
+    case kSchemeWeno5: return launch_seed_one<T, D, kSchemeWeno5, HAM, LOCAL>(a, rep, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// the global dissipation, or alpha_d at the node (a.st.diss == 1)
 template <typename T, int D, int HAM>
 hipError_t launch_seed_scheme(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int scheme, hipStream_t s)
 {
-    switch (scheme) {
-    case kSchemeFirst: return launch_seed_one<T, D, kSchemeFirst, HAM>(a, rep, s);
-    case kSchemeEno2: return launch_seed_one<T, D, kSchemeEno2, HAM>(a, rep, s);
-    case kSchemeEno3: return launch_seed_one<T, D, kSchemeEno3, HAM>(a, rep, s);
-    case kSchemeWeno5: return launch_seed_one<T, D, kSchemeWeno5, HAM>(a, rep, s);
-    }
+    if (a.st.diss == 1) return launch_seed_local<T, D, HAM, true>(a, rep, scheme, s);
+    if (a.st.diss == 0) return launch_seed_local<T, D, HAM, false>(a, rep, scheme, s);
     return hipErrorInvalidValue;
 }
 
@@ -392,6 +412,8 @@ hipError_t launch_seed(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int sch
     if (ham == kHamDubins3) return a.st.g.dim == 3 ? launch_seed_scheme<T, 3, kHamDubins3>(a, rep, scheme, s)
                                                    : hipErrorInvalidValue;
     if (ham == kHamDubins4) return a.st.g.dim == 4 ? launch_seed_scheme<T, 4, kHamDubins4>(a, rep, scheme, s)
+                                                   : hipErrorInvalidValue;
+    if (ham == kHamRockets) return a.st.g.dim == 3 ? launch_seed_scheme<T, 3, kHamRockets>(a, rep, scheme, s)
                                                    : hipErrorInvalidValue;
     switch (a.st.g.dim) {
     case 1: return launch_seed_scheme<T, 1, kHamNormal>(a, rep, scheme, s);

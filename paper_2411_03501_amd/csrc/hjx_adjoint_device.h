@@ -28,6 +28,10 @@ __device__ __forceinline__ HamTab<T> ham_tab(const StageArgs<T> &a, const int *j
         t.y = a.tab.coord[1][j[1]];
         t.c = a.tab.cosv[2][j[2]];
         t.s = a.tab.sinv[2][j[2]];
+    } else if constexpr (HAM == kHamRockets) {
+        t.x = a.tab.coord[0][j[0]];
+        t.c = a.tab.cosv[2][j[2]];
+        t.s = a.tab.sinv[2][j[2]];
     } else if constexpr (HAM == kHamDubins4) {
         t.c = a.tab.cosv[2][j[2]];
         t.s = a.tab.sinv[2][j[2]];
@@ -68,6 +72,21 @@ __device__ __forceinline__ T ham_grad(const StageArgs<T> &a, const HamTab<T> &tb
         dmH[2] = vabs(arg);                    // d(-H)/dwbar_e
         dmH[3] = -vabs(p[2]);                  // d(-H)/dwbar_p
         return -fmaT(we, vabs(arg), fmaT(-wp, vabs(p[2]), drift));
+    } else if constexpr (HAM == kHamRockets) {
+        // H = -[a p1 cos th + p2 (a sin th + a - g) + ubar_e |p1 x - p3| - ubar_p |p2 x + p3|]
+        const T x = tb.x, c = tb.c, sn = tb.s;
+        const T ac = a.hp[0], g = a.hp[1], ue = a.hp[2], up = a.hp[3];
+        const T k1 = fmaT(ac, sn, ac) - g;  // the p2 drift
+        const T e = fmaT(p[0], x, -p[2]), q = fmaT(p[1], x, p[2]);
+        const T se = vsign(e), sq = vsign(q);
+        dHdp[0] = -fmaT(ue * se, x, ac * c);
+        dHdp[1] = -fmaT(-up * sq, x, k1);
+        dHdp[2] = fmaT(ue, se, up * sq);
+        dmH[0] = fmaT(p[0], c, p[1] * (sn + T(1)));  // d(-H)/da
+        dmH[1] = -p[1];                               // d(-H)/dg
+        dmH[2] = vabs(e);                             // d(-H)/dubar_e
+        dmH[3] = -vabs(q);                            // d(-H)/dubar_p
+        return -fmaT(ue, vabs(e), fmaT(-up, vabs(q), fmaT(p[0], ac * c, p[1] * k1)));
     } else {
         const T c = tb.c, sn = tb.s;
         const T v = tb.v;
@@ -78,6 +97,65 @@ __device__ __forceinline__ T ham_grad(const StageArgs<T> &a, const HamTab<T> &tb
         dmH[0] = -vabs(p[2]);                  // d(-H)/dwbar
         dmH[1] = -vabs(p[3]);                  // d(-H)/dabar
         return fmaT(-v, fmaT(p[0], c, p[1] * sn), fmaT(a.hp[0], vabs(p[2]), a.hp[1] * vabs(p[3])));
+    }
+}
+
+// alpha_d at the node (the local dissipation coefficient, node_bound) and
+// its gradient in the Hamiltonian parameters (dbnd[m]), from the node's
+// table values; d|s|/ds = sign(s) as in ham_grad.
+template <typename T, int D, int HAM>
+__device__ __forceinline__ T bound_grad(const StageArgs<T> &a, const HamTab<T> &tb, int d, T (&dbnd)[8])
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dbnd[m] = T(0);
+    if constexpr (HAM == kHamNormal) {  // |a|
+        dbnd[0] = vsign(a.hp[0]);
+        return vabs(a.hp[0]);
+    } else if constexpr (HAM == kHamDubins3) {
+        // |-v_e + v_p cos th| + wbar_e |y|,  |v_p sin th| + wbar_e |x|,  wbar_e + wbar_p
+        const T ve = a.hp[0], vp = a.hp[1], we = a.hp[2], wp = a.hp[3];
+        if (d == 0) {
+            const T u = -ve + vp * tb.c, su = vsign(u);
+            dbnd[0] = -su;
+            dbnd[1] = su * tb.c;
+            dbnd[2] = vabs(tb.y);
+            return vabs(u) + we * vabs(tb.y);
+        }
+        if (d == 1) {
+            const T u = vp * tb.s;
+            dbnd[1] = vsign(u) * tb.s;
+            dbnd[2] = vabs(tb.x);
+            return vabs(u) + we * vabs(tb.x);
+        }
+        dbnd[2] = T(1);
+        dbnd[3] = T(1);
+        return we + wp;
+    } else if constexpr (HAM == kHamRockets) {
+        // |a cos th| + ubar_e |x|,  |a sin th + a - g| + ubar_p |x|,  ubar_e + ubar_p
+        const T ac = a.hp[0], g = a.hp[1], ue = a.hp[2], up = a.hp[3];
+        const T ax = vabs(tb.x);
+        if (d == 0) {
+            const T u = ac * tb.c;
+            dbnd[0] = vsign(u) * tb.c;
+            dbnd[2] = ax;
+            return vabs(u) + ue * ax;
+        }
+        if (d == 1) {
+            const T u = ac * tb.s + ac - g, su = vsign(u);
+            dbnd[0] = su * (tb.s + T(1));
+            dbnd[1] = -su;
+            dbnd[3] = ax;
+            return vabs(u) + up * ax;
+        }
+        dbnd[2] = T(1);
+        dbnd[3] = T(1);
+        return ue + up;
+    } else {  // |v cos th|, |v sin th|, wbar, abar
+        if (d == 0) return vabs(tb.v * tb.c);
+        if (d == 1) return vabs(tb.v * tb.s);
+        dbnd[d - 2] = T(1);
+        return a.hp[d - 2];
     }
 }
 

@@ -1258,6 +1258,26 @@ void alpha_jacobian(const hjx_problem *p, double J[kMaxDim][8])
         J[1][2] = xmax;
         J[2][2] = 1.0;
         J[2][3] = 1.0;
+    } else if (p->ham.kind == HJX_HAM_ROCKETS) {
+        // alpha_0 = max_th |a cos th| + ubar_e max_x |x|
+        // alpha_1 = max_th |a sin th + a - g| + ubar_p max_x |x|,  alpha_2 = ubar_e + ubar_p
+        // (ubar_e, ubar_p >= 0, so each maximum splits over th and x)
+        double b0 = -1, c0 = 0, b1 = -1, s1 = 0, xmax = 0;
+        for (int64_t k = 0; k < p->grid.n[2]; ++k) {
+            const double th = node(2, k), c = std::cos(th), sn = std::sin(th);
+            const double v0 = std::fabs(h[0] * c), v1 = std::fabs(h[0] * sn + h[0] - h[1]);
+            if (v0 > b0) { b0 = v0; c0 = c; }
+            if (v1 > b1) { b1 = v1; s1 = sn; }
+        }
+        for (int64_t i = 0; i < p->grid.n[0]; ++i) xmax = std::max(xmax, std::fabs(node(0, i)));
+        const double g0 = sgn(h[0] * c0), g1 = sgn(h[0] * s1 + h[0] - h[1]);
+        J[0][0] = g0 * c0;
+        J[0][2] = xmax;
+        J[1][0] = g1 * (s1 + 1.0);
+        J[1][1] = -g1;
+        J[1][3] = xmax;
+        J[2][2] = 1.0;
+        J[2][3] = 1.0;
     } else {
         // alpha_0, alpha_1 = max |v cos th|, |v sin th| (no parameters); alpha_2 = wbar, alpha_3 = abar
         J[2][0] = 1.0;
@@ -1277,10 +1297,8 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
         return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
     if (ckpt_every < 1) return fail(HJX_ERR_INVALID_ARG, "ckpt_every %d < 1", ckpt_every);
     if (!direct_ok(geometry(p), p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the adjoint needs arrays under 4 GiB");
-    if (p->ham.kind == HJX_HAM_ROCKETS)
-        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the ROCKETS Hamiltonian is not implemented");
-    if (p->ham.dissipation != HJX_DISS_GLOBAL)
-        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of the local dissipation or Godunov is not implemented");
+    if (p->ham.dissipation == HJX_DISS_GODUNOV)
+        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of Godunov's Hamiltonian is not implemented");
     hjx_tape *t = new (std::nothrow) hjx_tape;
     if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
     t->p = p;

@@ -505,10 +505,9 @@ hipError_t launch_mode(const StageArgs<T> &a, hipStream_t s)
 
 // The node mode of a stage: the replay for the adjoint keeps p-, p+ (when
 // the tape stores them) and, for a restricted update, marks its clips in the
-// mask; it never takes the local dissipation, which the adjoint rejects.  A
-// clipped stage with a mask is such a replay (solves pass no mask).  The
-// right-hand side alone is never clipped.  Plain stages run the kernels
-// without any of them.
+// mask; a clipped stage with a mask is such a replay (solves pass no mask).
+// The local dissipation combines with all of these.  The right-hand side
+// alone is never clipped.  Plain stages run the kernels without any of them.
 template <typename T, int D, int SCHEME, int HAM>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
@@ -529,6 +528,11 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
         return launch_mode<T, D, SCHEME, HAM, kNodeKeep | kNodeClip | kNodeMark>(a, s);
     case kNodeLocal: return launch_mode<T, D, SCHEME, HAM, kNodeLocal>(a, s);
     case kNodeLocal | kNodeClip: return launch_mode<T, D, SCHEME, HAM, kNodeLocal | kNodeClip>(a, s);
+    case kNodeKeep | kNodeLocal: return launch_mode<T, D, SCHEME, HAM, kNodeKeep | kNodeLocal>(a, s);
+    case kNodeLocal | kNodeClip | kNodeMark:
+        return launch_mode<T, D, SCHEME, HAM, kNodeLocal | kNodeClip | kNodeMark>(a, s);
+    case kNodeKeep | kNodeLocal | kNodeClip | kNodeMark:
+        return launch_mode<T, D, SCHEME, HAM, kNodeKeep | kNodeLocal | kNodeClip | kNodeMark>(a, s);
     }
     return hipErrorInvalidValue;
 }

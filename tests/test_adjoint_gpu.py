@@ -24,6 +24,11 @@ from paper_2411_03501_amd import hjx  # noqa: E402
 
 TDT = {"f32": torch.float32, "f64": torch.float64}
 TOL = {"f64": 1e-7, "f32": 1e-3}
+# FP32 rockets: the solve takes the signs of |p1 x - p3|, |p2 x + p3| and the
+# clip in binary32, the oracle in binary64, and with |x| up to 64 a sign
+# taken the other way at one node moves dH/dp there by up to 2 * 64 * ubar
+# (a Dubins grid spans a few units).  FP64 holds the rockets case to 1e-7.
+CASE_TOL = {("rockets_eno2_rk2_positive", "f32"): 5e-3}
 
 
 def say(*a):
@@ -46,6 +51,12 @@ CASES = {
     "dubins3_weno5_rk3_nonpositive": inputs.DUBINS3D.with_(n=(17, 15, 13), t1=0.3, restrict="nonpositive"),
     "normal2d_eno2_rk2_positive": inputs.NORMAL2D.with_(n=(25, 23), scheme="eno2", rk=2, t1=0.2,
                                                         restrict="positive"),
+    # the rockets game as configured (ENO2, RK2, the positive restricted update)
+    "rockets_eno2_rk2_positive": inputs.ROCKETS.with_(n=(15, 13, 11), t1=0.3),
+    # local Lax-Friedrichs: alpha_d at the node, whose parameter gradient
+    # joins dL/dtheta node by node
+    "dubins3_weno5_rk3_local": inputs.DUBINS3D.with_(n=(17, 15, 13), t1=0.3, dissipation="local"),
+    "car4_weno5_rk3_local": inputs.CAR4D.with_(n=(9, 9, 8, 7), t1=0.3, dissipation="local"),
 }
 
 
@@ -82,6 +93,7 @@ def _gpu_grads(w, dtype, phi0, eps, ckpt=3, dL_dphiT=None, mode=None):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_matches_oracle_directional_derivatives(case, dtype):
     w = CASES[case]
+    tol = CASE_TOL.get((case, dtype), TOL[dtype])
     phi0, Po, eps = _setup(w, dtype)
     say(f"adjoint {case} {dtype} n={w.n}")
     loss, g, dp, st, out = _gpu_grads(w, dtype, phi0, eps)
@@ -95,20 +107,25 @@ def test_adjoint_matches_oracle_directional_derivatives(case, dtype):
         delta = inputs.smooth_field(w.n, seed)
         _, ref, _ = O.cs_solve_loss(Po, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps)
         got = float(np.sum(g * delta))
-        assert abs(got - ref) <= TOL[dtype] * max(abs(ref), 1e-3 * np.abs(g).sum() * np.abs(delta).max()), \
+        assert abs(got - ref) <= tol * max(abs(ref), 1e-3 * np.abs(g).sum() * np.abs(delta).max()), \
             (case, dtype, seed, got, ref)
         if w.restrict != "none" and seed == 81:
             # the clips matter here: the unrestricted derivative is another
             # number, well outside the tolerance
             Pu = oracle_problem(w.with_(restrict="none"), decide=dtype)
             _, plain, _ = O.cs_solve_loss(Pu, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps)
-            assert abs(plain - ref) > 5 * TOL[dtype] * abs(ref), (case, plain, ref)
+            assert abs(plain - ref) > 5 * tol * abs(ref), (case, plain, ref)
+        if w.dissipation == "local" and seed == 81:
+            # and so does the node's bound: the global form is another number
+            Pg = oracle_problem(w.with_(dissipation="global"), decide=dtype)
+            _, glob, _ = O.cs_solve_loss(Pg, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps)
+            assert abs(glob - ref) > 5 * tol * abs(ref), (case, glob, ref)
     # dL/dtheta for every parameter of the Hamiltonian
     for m in range(len(w.params)):
         e = np.zeros(len(w.params))
         e[m] = 1.0
         _, ref, _ = O.cs_solve_loss(Po, phi0, w.t1, dparams=e, with_target=w.with_target, eps_h=eps)
-        assert abs(dp[m] - ref) <= TOL[dtype] * max(abs(ref), 1e-2), (case, dtype, m, dp[m], ref)
+        assert abs(dp[m] - ref) <= tol * max(abs(ref), 1e-2), (case, dtype, m, dp[m], ref)
     assert all(v == 0.0 for v in dp[len(w.params):])
 
 
@@ -178,7 +195,8 @@ def test_gradient_workload_against_oracle_jvps(oracle_jvps, dtype):
 
 
 @pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "car4_weno5_rk3", "normal2d_first_rk1",
-                                  "dubins3_weno5_rk3_nonpositive", "normal2d_eno2_rk2_positive"])
+                                  "dubins3_weno5_rk3_nonpositive", "normal2d_eno2_rk2_positive",
+                                  "rockets_eno2_rk2_positive", "dubins3_weno5_rk3_local"])
 def test_transposed_solve_dot_product(case):
     """<lam_T, J delta> (oracle tangent) = <J^T lam_T, delta> (GPU adjoint)."""
     w = CASES[case]
@@ -239,7 +257,8 @@ def test_checkpoint_interval_does_not_change_the_gradient(dtype):
 
 @pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "dubins3_eno3_rk2", "dubins3_eno2_rk1", "car4_weno5_rk3",
                                   "normal2d_weno5_rk3", "dubins3_multitile", "dubins3_weno5_rk3_nonpositive",
-                                  "normal2d_eno2_rk2_positive"])
+                                  "normal2d_eno2_rk2_positive", "rockets_eno2_rk2_positive",
+                                  "dubins3_weno5_rk3_local", "car4_weno5_rk3_local"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_stored_and_recomputed_derivatives_give_the_same_bits(case, dtype):
     """The replay's derivative store is a cache: the reverse sweep that reads

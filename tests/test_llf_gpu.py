@@ -3,7 +3,8 @@ at each node; HJX_DISS_LOCAL) through the C ABI, against the oracle element
 by element: every Hamiltonian with a node-dependent bound, every scheme and
 RK order in both precisions, with a target and with the restricted update,
 every launch shape, one full-size step; identity with the global form for
-normal motion; the tape and the batch reject it."""
+normal motion; the batch rejects it (its adjoint is tested in
+test_adjoint_gpu.py)."""
 import sys
 
 import numpy as np
@@ -114,11 +115,8 @@ def test_full_size_dubins3d_local_step():
     P.close()
 
 
-def test_tape_and_batch_reject_the_local_dissipation():
+def test_the_batch_rejects_the_local_dissipation():
     P = gpu_problem(CASES["dubins3d"], "f32")
-    with pytest.raises(hjx.HjxError) as e:
-        P.tape(0.01)
-    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "local dissipation" in str(e.value)
     with pytest.raises(hjx.HjxError) as e:
         hjx.Batch([P])
     assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "local dissipation" in str(e.value)
