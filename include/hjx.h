@@ -144,9 +144,11 @@ typedef struct {
  *                     max(-min(p-_d, 0), max(p+_d, 0)) for a < 0 (not in the
  *                     paper).
  * The CFL step uses the grid maximum of the partial bound in every case.
- * hjx_tape_create rejects HJX_DISS_GODUNOV and hjx_batch_create accepts
- * HJX_DISS_GLOBAL only (HJX_ERR_UNSUPPORTED).  The adjoint of the local form
- * differentiates each node's bound in the parameters (d|s|/ds = sign(s)). */
+ * hjx_batch_create accepts HJX_DISS_GLOBAL only (HJX_ERR_UNSUPPORTED).  The
+ * adjoint of the local form differentiates each node's bound in the
+ * parameters (d|s|/ds = sign(s)); that of Godunov's follows the one-sided
+ * values the forward selected (ties as the forward breaks them), with
+ * d|q|/dq = 0 at q = 0. */
 typedef enum { HJX_DISS_GLOBAL = 0, HJX_DISS_LOCAL = 1, HJX_DISS_GODUNOV = 2 } hjx_dissipation_kind;
 
 typedef struct {
@@ -327,8 +329,7 @@ typedef struct hjx_tape hjx_tape;
  * `stream`) and allocates the checkpoints and the replay workspace: about
  * (steps/ckpt_every + 6 ckpt_every + 4 + 3 dim) arrays of the problem's size, plus
  * the derivative store of hjx_tape_set_mode.
- * Arrays must be under 4 GiB each and the dissipation not Godunov's (else
- * HJX_ERR_UNSUPPORTED).  With a restricted update the replay also keeps, per
+ * Arrays must be under 4 GiB each (else HJX_ERR_UNSUPPORTED).  With a restricted update the replay also keeps, per
  * stage, a byte per node that records where the rate was clipped: a clipped
  * rate is the constant 0 and passes no adjoint (ckpt_every x rk more bytes
  * per node in each of the two replay sets). */

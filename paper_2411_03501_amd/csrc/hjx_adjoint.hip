@@ -158,30 +158,70 @@ __device__ __forceinline__ void seed_finish(const AdjSeedArgs<T> &a, const SeedN
     const bool clipped = a.mask != nullptr && (s.mk & 2) != 0;
     const T tg_new = s.tg_old + lo;
     if (kept) lo = T(0);
-    T pbar[D], dHdp[kMaxDim] = {}, dmH[8] = {};
-#pragma unroll
-    for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (s.pm[d] + s.pp[d]);
-    T hhat = ham_grad<T, D, HAM>(st, s.tb, pbar, dHdp, dmH);
+    T dmH[8] = {};
+    T hhat;
     const T w = clipped ? T(0) : a.cb * a.h * lo;
-    // alpha_d: the grid maximum, or (LOCAL) the bound at the node, whose
-    // parameter gradient then joins dL/dtheta here (the grid maxima only
-    // reach the parameters through the CFL step)
+    if constexpr (HAM == kHamNormalGodunov) {
+        // Godunov's Hamiltonian for a|p|: Hhat = a |q| with q_d the one-sided
+        // value each axis selects (as stage_rate selects it, ties alike), so
+        // dHhat/dp-_d, dHhat/dp+_d = (a q_d / |q|) dq_d/dp-_d, dq_d/dp+_d
+        // (0 where q = 0), and d(-Hhat)/da = -|q|.  No alpha.
+        const T av = st.hp[0];
+        T q[D], gm[D], gp[D];
+        T ss = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        T al = st.alpha[d];
-        const T half = T(0.5) * (s.pp[d] - s.pm[d]);
-        if constexpr (LOCAL) {
-            T dbnd[8];
-            al = bound_grad<T, D, HAM>(st, s.tb, d, dbnd);
-#pragma unroll
-            for (int m = 0; m < NP; ++m) dmH[m] = fmaT(half, dbnd[m], dmH[m]);
-        } else {
-            part[1 + d] += (double)(w * half);
+        for (int d = 0; d < D; ++d) {
+            const T pm = s.pm[d], pp = s.pp[d];
+            if (av >= T(0)) {
+                const T up = pm > T(0) ? pm : T(0), dn = pp < T(0) ? -pp : T(0);
+                const bool takedn = dn > up;
+                q[d] = takedn ? dn : up;
+                gm[d] = !takedn && pm > T(0) ? T(1) : T(0);
+                gp[d] = takedn && pp < T(0) ? T(-1) : T(0);
+            } else {
+                const T dn = pm < T(0) ? -pm : T(0), up = pp > T(0) ? pp : T(0);
+                const bool takeup = up > dn;
+                q[d] = takeup ? up : dn;
+                gm[d] = !takeup && pm < T(0) ? T(-1) : T(0);
+                gp[d] = takeup && pp > T(0) ? T(1) : T(0);
+            }
+            ss = fmaT(q[d], q[d], ss);
         }
-        hhat = fmaT(-al, half, hhat);
-        // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
-        at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * al);
-        at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * al);
+        const T nq = sqrt(ss);
+        hhat = av * nq;
+        const T inv = nq > T(0) ? av / nq : T(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const T dq = inv * q[d];  // dHhat/dq_d; L = -Hhat
+            at32(a.seed_m[d], idx) = w * (-dq * gm[d]);
+            at32(a.seed_p[d], idx) = w * (-dq * gp[d]);
+        }
+        dmH[0] = -nq;
+    } else {
+        T pbar[D], dHdp[kMaxDim] = {};
+#pragma unroll
+        for (int d = 0; d < D; ++d) pbar[d] = T(0.5) * (s.pm[d] + s.pp[d]);
+        hhat = ham_grad<T, D, HAM>(st, s.tb, pbar, dHdp, dmH);
+        // alpha_d: the grid maximum, or (LOCAL) the bound at the node, whose
+        // parameter gradient then joins dL/dtheta here (the grid maxima only
+        // reach the parameters through the CFL step)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            T al = st.alpha[d];
+            const T half = T(0.5) * (s.pp[d] - s.pm[d]);
+            if constexpr (LOCAL) {
+                T dbnd[8];
+                al = bound_grad<T, D, HAM>(st, s.tb, d, dbnd);
+#pragma unroll
+                for (int m = 0; m < NP; ++m) dmH[m] = fmaT(half, dbnd[m], dmH[m]);
+            } else {
+                part[1 + d] += (double)(w * half);
+            }
+            hhat = fmaT(-al, half, hhat);
+            // L = -H(pbar) + sum alpha (p+ - p-)/2, pbar = (p- + p+)/2
+            at32(a.seed_m[d], idx) = w * (T(-0.5) * dHdp[d] - T(0.5) * al);
+            at32(a.seed_p[d], idx) = w * (T(-0.5) * dHdp[d] + T(0.5) * al);
+        }
     }
     const T L = -hhat;
 #pragma unroll
@@ -400,6 +440,7 @@ hipError_t launch_seed_local(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, i
 template <typename T, int D, int HAM>
 hipError_t launch_seed_scheme(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int scheme, hipStream_t s)
 {
+    if constexpr (HAM == kHamNormalGodunov) return launch_seed_local<T, D, HAM, false>(a, rep, scheme, s);
     if (a.st.diss == 1) return launch_seed_local<T, D, HAM, true>(a, rep, scheme, s);
     if (a.st.diss == 0) return launch_seed_local<T, D, HAM, false>(a, rep, scheme, s);
     return hipErrorInvalidValue;
@@ -415,6 +456,15 @@ hipError_t launch_seed(const AdjSeedArgs<T> &a, const StageArgs<T> *rep, int sch
                                                    : hipErrorInvalidValue;
     if (ham == kHamRockets) return a.st.g.dim == 3 ? launch_seed_scheme<T, 3, kHamRockets>(a, rep, scheme, s)
                                                    : hipErrorInvalidValue;
+    if (a.st.diss == 2) {  // Godunov's numerical Hamiltonian for normal motion
+        switch (a.st.g.dim) {
+        case 1: return launch_seed_scheme<T, 1, kHamNormalGodunov>(a, rep, scheme, s);
+        case 2: return launch_seed_scheme<T, 2, kHamNormalGodunov>(a, rep, scheme, s);
+        case 3: return launch_seed_scheme<T, 3, kHamNormalGodunov>(a, rep, scheme, s);
+        case 4: return launch_seed_scheme<T, 4, kHamNormalGodunov>(a, rep, scheme, s);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (a.st.g.dim) {
     case 1: return launch_seed_scheme<T, 1, kHamNormal>(a, rep, scheme, s);
     case 2: return launch_seed_scheme<T, 2, kHamNormal>(a, rep, scheme, s);

@@ -1297,8 +1297,6 @@ hjx_status hjx_tape_create(hjx_problem *p, double t0, double t1, int32_t ckpt_ev
         return fail(HJX_ERR_INVALID_ARG, "time span [%g, %g] is not finite and increasing", t0, t1);
     if (ckpt_every < 1) return fail(HJX_ERR_INVALID_ARG, "ckpt_every %d < 1", ckpt_every);
     if (!direct_ok(geometry(p), p->elem)) return fail(HJX_ERR_UNSUPPORTED, "the adjoint needs arrays under 4 GiB");
-    if (p->ham.dissipation == HJX_DISS_GODUNOV)
-        return fail(HJX_ERR_UNSUPPORTED, "the adjoint of Godunov's Hamiltonian is not implemented");
     hjx_tape *t = new (std::nothrow) hjx_tape;
     if (!t) return fail(HJX_ERR_OOM, "host allocation failed");
     t->p = p;

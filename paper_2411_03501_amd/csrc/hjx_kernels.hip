@@ -514,9 +514,15 @@ hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
     const bool clip = !a.rhs_only && a.clip != 0;
     const int mode = (a.dp_out ? kNodeKeep : 0) | (clip ? kNodeClip : 0) | (clip && a.mask ? kNodeMark : 0) |
                      (a.diss == 1 ? kNodeLocal : 0);
-    if constexpr (HAM == kHamNormalGodunov) {  // no alpha, so no local form; no adjoint
-        if (mode == kNodePlain) return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
-        if (mode == kNodeClip) return launch_mode<T, D, SCHEME, HAM, kNodeClip>(a, s);
+    if constexpr (HAM == kHamNormalGodunov) {  // no alpha, so no local form
+        switch (mode) {
+        case kNodePlain: return launch_mode<T, D, SCHEME, HAM, kNodePlain>(a, s);
+        case kNodeClip: return launch_mode<T, D, SCHEME, HAM, kNodeClip>(a, s);
+        case kNodeKeep: return launch_mode<T, D, SCHEME, HAM, kNodeKeep>(a, s);
+        case kNodeClip | kNodeMark: return launch_mode<T, D, SCHEME, HAM, kNodeClip | kNodeMark>(a, s);
+        case kNodeKeep | kNodeClip | kNodeMark:
+            return launch_mode<T, D, SCHEME, HAM, kNodeKeep | kNodeClip | kNodeMark>(a, s);
+        }
         return hipErrorInvalidValue;
     }
     switch (mode) {

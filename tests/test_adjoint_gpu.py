@@ -57,6 +57,12 @@ CASES = {
     # joins dL/dtheta node by node
     "dubins3_weno5_rk3_local": inputs.DUBINS3D.with_(n=(17, 15, 13), t1=0.3, dissipation="local"),
     "car4_weno5_rk3_local": inputs.CAR4D.with_(n=(9, 9, 8, 7), t1=0.3, dissipation="local"),
+    # Godunov's Hamiltonian for normal motion, both signs of the speed
+    "normal2d_weno5_rk3_godunov": inputs.NORMAL2D.with_(n=(25, 23), scheme="weno5", rk=3, t1=0.2,
+                                                        dissipation="godunov"),
+    "normal3d_eno3_rk2_godunov_neg": inputs.NORMAL2D.with_(n=(13, 11, 12), gmin=(-1, -1, -1), gmax=(1, 1, 1),
+                                                           scheme="eno3", rk=2, t1=0.15, params=(-0.9,),
+                                                           dissipation="godunov"),
 }
 
 
@@ -115,8 +121,8 @@ def test_adjoint_matches_oracle_directional_derivatives(case, dtype):
             Pu = oracle_problem(w.with_(restrict="none"), decide=dtype)
             _, plain, _ = O.cs_solve_loss(Pu, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps)
             assert abs(plain - ref) > 5 * tol * abs(ref), (case, plain, ref)
-        if w.dissipation == "local" and seed == 81:
-            # and so does the node's bound: the global form is another number
+        if w.dissipation in ("local", "godunov") and seed == 81:
+            # and so does the dissipation's form: the global one is another number
             Pg = oracle_problem(w.with_(dissipation="global"), decide=dtype)
             _, glob, _ = O.cs_solve_loss(Pg, phi0, w.t1, dphi0=delta, with_target=w.with_target, eps_h=eps)
             assert abs(glob - ref) > 5 * tol * abs(ref), (case, glob, ref)
@@ -196,7 +202,8 @@ def test_gradient_workload_against_oracle_jvps(oracle_jvps, dtype):
 
 @pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "car4_weno5_rk3", "normal2d_first_rk1",
                                   "dubins3_weno5_rk3_nonpositive", "normal2d_eno2_rk2_positive",
-                                  "rockets_eno2_rk2_positive", "dubins3_weno5_rk3_local"])
+                                  "rockets_eno2_rk2_positive", "dubins3_weno5_rk3_local",
+                                  "normal3d_eno3_rk2_godunov_neg"])
 def test_transposed_solve_dot_product(case):
     """<lam_T, J delta> (oracle tangent) = <J^T lam_T, delta> (GPU adjoint)."""
     w = CASES[case]
@@ -258,7 +265,8 @@ def test_checkpoint_interval_does_not_change_the_gradient(dtype):
 @pytest.mark.parametrize("case", ["dubins3_weno5_rk3", "dubins3_eno3_rk2", "dubins3_eno2_rk1", "car4_weno5_rk3",
                                   "normal2d_weno5_rk3", "dubins3_multitile", "dubins3_weno5_rk3_nonpositive",
                                   "normal2d_eno2_rk2_positive", "rockets_eno2_rk2_positive",
-                                  "dubins3_weno5_rk3_local", "car4_weno5_rk3_local"])
+                                  "dubins3_weno5_rk3_local", "car4_weno5_rk3_local", "normal2d_weno5_rk3_godunov",
+                                  "normal3d_eno3_rk2_godunov_neg"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_stored_and_recomputed_derivatives_give_the_same_bits(case, dtype):
     """The replay's derivative store is a cache: the reverse sweep that reads

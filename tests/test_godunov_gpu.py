@@ -3,7 +3,7 @@
 1-D to 4-D, every scheme and RK order, both signs of the speed, both
 precisions, with a target and with the restricted update, the two-node,
 direct and plane-march kernels, and the 101^2 workload's full solve; the
-tape and the batch reject it."""
+batch rejects it (its adjoint is tested in test_adjoint_gpu.py)."""
 import sys
 
 import numpy as np
@@ -106,11 +106,8 @@ def test_full_normal2d_solve_with_godunov():
     assert_close(to_host(got), ref, "f64", w.periodic, "normal2d godunov")
 
 
-def test_tape_and_batch_reject_godunov():
+def test_the_batch_rejects_godunov():
     P = gpu_problem(CASES["2d"], "f32")
-    with pytest.raises(hjx.HjxError) as e:
-        P.tape(0.01)
-    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "Godunov" in str(e.value)
     with pytest.raises(hjx.HjxError) as e:
         hjx.Batch([P])
     assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "Godunov" in str(e.value)
