@@ -108,8 +108,7 @@ typedef enum {
  *       H = -[a p1 cos th + p2 (a sin th + a - g)
  *             + ubar_e |p1 x - p3| - ubar_p |p2 x + p3|],
  *       alpha = (|a cos th| + ubar_e|x|, |a sin th + a - g| + ubar_p|x|,
- *                ubar_e + ubar_p).  Requires ubar_e, ubar_p >= 0.  Not
- *       available to hjx_batch_create (HJX_ERR_UNSUPPORTED). */
+ *                ubar_e + ubar_p).  Requires ubar_e, ubar_p >= 0. */
 typedef enum {
     HJX_HAM_NORMAL = 0,
     HJX_HAM_DUBINS3_PE = 1,
@@ -144,8 +143,7 @@ typedef struct {
  *                     max(-min(p-_d, 0), max(p+_d, 0)) for a < 0 (not in the
  *                     paper).
  * The CFL step uses the grid maximum of the partial bound in every case.
- * hjx_batch_create accepts HJX_DISS_GLOBAL only (HJX_ERR_UNSUPPORTED).  The
- * adjoint of the local form differentiates each node's bound in the
+ * The adjoint of the local form differentiates each node's bound in the
  * parameters (d|s|/ds = sign(s)); that of Godunov's follows the one-sided
  * values the forward selected (ties as the forward breaks them), with
  * d|q|/dq = 0 at q = 0. */
@@ -393,8 +391,10 @@ typedef struct hjx_batch hjx_batch;
 /* Create a batch of n >= 1 problems (host array of handles, each used once).
  * Runs the dissipation reduction of every member and fixes its CFL step
  * (synchronises `stream`).  The launch shape defaults to the resident
- * block count and 1024-node items.  Members with the ROCKETS Hamiltonian are
- * rejected (HJX_ERR_UNSUPPORTED). */
+ * block count and 1024-node items.  Any Hamiltonian, dissipation form and
+ * restricted update may be mixed; a batch with a ROCKETS member or a local
+ * or Godunov dissipation runs a kernel that carries those too (and has its
+ * own occupancy). */
 hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *stream, hjx_batch **out);
 hjx_status hjx_batch_destroy(hjx_batch *b);
 

@@ -1801,6 +1801,7 @@ struct hjx_batch {
     int device = 0;
     int dtype = 0, deriv = 0, rk = 0;
     int clip = 0;                     // some member has a restricted update
+    int ext = 0;                      // some member plays the rockets game or takes the local form or Godunov
     size_t elem = 0, inst_bytes = 0;
     std::vector<hjx_problem *> probs;
     std::vector<double> alpha;        // n * kMaxDim
@@ -1857,11 +1858,11 @@ hipError_t batch_launch(const hjx_batch *b, int n_active, int s, int stage, hipS
     const int items = b->item0[n_active];
     if (b->dtype == HJX_F32) {
         BatchArgs<float> a{static_cast<const BatchInst<float> *>(b->dinst), b->dflag, n_active, items, s, stage,
-                           b->rk, b->item_nodes, b->clip};
+                           b->rk, b->item_nodes, b->clip, b->ext};
         return launch_batch_f32(a, b->deriv, b->blocks, st);
     }
     BatchArgs<double> a{static_cast<const BatchInst<double> *>(b->dinst), b->dflag, n_active, items, s, stage,
-                        b->rk, b->item_nodes, b->clip};
+                        b->rk, b->item_nodes, b->clip, b->ext};
     return launch_batch_f64(a, b->deriv, b->blocks, st);
 }
 
@@ -1994,10 +1995,6 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
         if (p->device != p0->device) return fail(HJX_ERR_INVALID_ARG, "problems[%d] is on another device", i);
         if (!direct_ok(geometry(p), p->elem))
             return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: arrays of 4 GiB or more", i);
-        if (p->ham.kind == HJX_HAM_ROCKETS)
-            return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: the batch kernel has no ROCKETS Hamiltonian", i);
-        if (p->ham.dissipation != HJX_DISS_GLOBAL)
-            return fail(HJX_ERR_UNSUPPORTED, "problems[%d]: the batch kernel has no local dissipation or Godunov", i);
     }
     {
         const size_t need = (p0->scheme.dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>)) *
@@ -2013,7 +2010,10 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
     b->dtype = p0->scheme.dtype;
     b->deriv = p0->scheme.deriv;
     b->rk = p0->scheme.rk;
-    for (int i = 0; i < n; ++i) b->clip |= problems[i]->scheme.restrict_update != HJX_RESTRICT_NONE;
+    for (int i = 0; i < n; ++i) {
+        b->clip |= problems[i]->scheme.restrict_update != HJX_RESTRICT_NONE;
+        b->ext |= problems[i]->ham.kind == HJX_HAM_ROCKETS || problems[i]->ham.dissipation != HJX_DISS_GLOBAL;
+    }
     b->elem = p0->elem;
     b->inst_bytes = b->dtype == HJX_F32 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
     b->probs.assign(problems, problems + n);
@@ -2044,7 +2044,7 @@ hjx_status hjx_batch_create(int32_t n, hjx_problem *const *problems, void *strea
         return fail(e == hipErrorOutOfMemory ? HJX_ERR_OOM : HJX_ERR_DEVICE, "batch allocation: %s",
                     hipGetErrorString(e));
     }
-    const int per_cu = batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv, b->clip);
+    const int per_cu = batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv, b->clip, b->ext);
     b->blocks_max = std::max(1, cus) * per_cu;
     b->blocks = b->blocks_max;
     *out = b;
@@ -2137,7 +2137,7 @@ hjx_status hjx_batch_tune(hjx_batch *b, const void *const *phi0, const void *con
     if (reps < 1) return fail(HJX_ERR_INVALID_ARG, "reps must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int cus =
-        std::max(1, b->blocks_max / std::max(1, batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv, b->clip)));
+        std::max(1, b->blocks_max / std::max(1, batch_blocks_per_cu(b->dtype == HJX_F64, b->deriv, b->clip, b->ext)));
     std::vector<std::pair<int, int>> cand;
     for (int items : {256, 1024, 4096}) {
         for (int per_cu : {1, 2, 4}) {

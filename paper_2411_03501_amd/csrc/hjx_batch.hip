@@ -91,8 +91,11 @@ __device__ __forceinline__ void batch_run(const StageArgs<T> &a, int f0, int f1)
 }
 
 // CLIP: some instance has a restricted update (each applies its own a.clip,
-// which may be 0); batches without one never compile the clip.
-template <typename T, int SCHEME, bool CLIP>
+// which may be 0); batches without one never compile the clip.  EXT: some
+// instance plays the rockets game or takes the local dissipation or
+// Godunov's Hamiltonian (a.diss); batches without one never compile those,
+// whose registers would set the occupancy of every batch.
+template <typename T, int SCHEME, bool CLIP, bool EXT>
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst<T> *__restrict__ inst, BatchArgs<T> b)
 {
     constexpr int M = CLIP ? kNodeClip : kNodePlain;
@@ -128,6 +131,39 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst<T>
             continue;
         }
         const StageArgs<T> a = batch_stage(I, b.s, b.stage, b.rk);
+        if constexpr (EXT) {
+            if (a.diss == 2) {  // Godunov's Hamiltonian for normal motion
+                switch (a.g.dim) {
+                case 1: batch_run<T, 1, SCHEME, kHamNormalGodunov, M>(a, f0, f1); break;
+                case 2: batch_run<T, 2, SCHEME, kHamNormalGodunov, M>(a, f0, f1); break;
+                case 3: batch_run<T, 3, SCHEME, kHamNormalGodunov, M>(a, f0, f1); break;
+                default: batch_run<T, 4, SCHEME, kHamNormalGodunov, M>(a, f0, f1); break;
+                }
+                continue;
+            }
+            if (a.diss == 1) {  // alpha_d at the node
+                constexpr int ML = M | kNodeLocal;
+                if (I.ham == kHamDubins3) {
+                    batch_run<T, 3, SCHEME, kHamDubins3, ML>(a, f0, f1);
+                } else if (I.ham == kHamDubins4) {
+                    batch_run<T, 4, SCHEME, kHamDubins4, ML>(a, f0, f1);
+                } else if (I.ham == kHamRockets) {
+                    batch_run<T, 3, SCHEME, kHamRockets, ML>(a, f0, f1);
+                } else {
+                    switch (a.g.dim) {
+                    case 1: batch_run<T, 1, SCHEME, kHamNormal, ML>(a, f0, f1); break;
+                    case 2: batch_run<T, 2, SCHEME, kHamNormal, ML>(a, f0, f1); break;
+                    case 3: batch_run<T, 3, SCHEME, kHamNormal, ML>(a, f0, f1); break;
+                    default: batch_run<T, 4, SCHEME, kHamNormal, ML>(a, f0, f1); break;
+                    }
+                }
+                continue;
+            }
+            if (I.ham == kHamRockets) {
+                batch_run<T, 3, SCHEME, kHamRockets, M>(a, f0, f1);
+                continue;
+            }
+        }
         if (I.ham == kHamDubins3) {
             batch_run<T, 3, SCHEME, kHamDubins3, M>(a, f0, f1);
         } else if (I.ham == kHamDubins4) {
@@ -143,42 +179,42 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst<T>
     }
 }
 
-template <typename T, int SCHEME, bool CLIP>
+template <typename T, int SCHEME, bool CLIP, bool EXT>
 int occupancy()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, SCHEME, CLIP>, kBatchThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<T, SCHEME, CLIP, EXT>, kBatchThreads, 0) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename T, bool CLIP>
+template <typename T, bool CLIP, bool EXT>
 int occupancy_t(int scheme)
 {
     switch (scheme) {
-    case kSchemeFirst: return occupancy<T, kSchemeFirst, CLIP>();
-    case kSchemeEno2: return occupancy<T, kSchemeEno2, CLIP>();
-    case kSchemeEno3: return occupancy<T, kSchemeEno3, CLIP>();
-    default: return occupancy<T, kSchemeWeno5, CLIP>();
+    case kSchemeFirst: return occupancy<T, kSchemeFirst, CLIP, EXT>();
+    case kSchemeEno2: return occupancy<T, kSchemeEno2, CLIP, EXT>();
+    case kSchemeEno3: return occupancy<T, kSchemeEno3, CLIP, EXT>();
+    default: return occupancy<T, kSchemeWeno5, CLIP, EXT>();
     }
 }
 
-template <typename T, bool CLIP>
+template <typename T, bool CLIP, bool EXT>
 hipError_t launch_batch_t(const BatchArgs<T> &a, int scheme, dim3 grid, hipStream_t s)
 {
     switch (scheme) {
     case kSchemeFirst:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeFirst, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeFirst, CLIP, EXT>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
         break;
     case kSchemeEno2:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno2, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno2, CLIP, EXT>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
         break;
     case kSchemeEno3:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno3, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeEno3, CLIP, EXT>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
         break;
     case kSchemeWeno5:
-        hipLaunchKernelGGL((batch_kernel<T, kSchemeWeno5, CLIP>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
+        hipLaunchKernelGGL((batch_kernel<T, kSchemeWeno5, CLIP, EXT>), grid, dim3(kBatchThreads), 0, s, a.inst, a);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -190,7 +226,9 @@ hipError_t launch_batch(const BatchArgs<T> &a, int scheme, int blocks, hipStream
 {
     if (a.items <= 0) return hipSuccess;
     const dim3 grid(blocks < a.items ? blocks : a.items);
-    return a.clip ? launch_batch_t<T, true>(a, scheme, grid, s) : launch_batch_t<T, false>(a, scheme, grid, s);
+    if (a.ext) return a.clip ? launch_batch_t<T, true, true>(a, scheme, grid, s)
+                             : launch_batch_t<T, false, true>(a, scheme, grid, s);
+    return a.clip ? launch_batch_t<T, true, false>(a, scheme, grid, s) : launch_batch_t<T, false, false>(a, scheme, grid, s);
 }
 
 }  // namespace
@@ -203,10 +241,14 @@ hipError_t launch_batch_f64(const BatchArgs<double> &a, int scheme, int blocks, 
 {
     return launch_batch<double>(a, scheme, blocks, s);
 }
-int batch_blocks_per_cu(int dtype_f64, int scheme, int clip)
+int batch_blocks_per_cu(int dtype_f64, int scheme, int clip, int ext)
 {
-    if (clip) return dtype_f64 ? occupancy_t<double, true>(scheme) : occupancy_t<float, true>(scheme);
-    return dtype_f64 ? occupancy_t<double, false>(scheme) : occupancy_t<float, false>(scheme);
+    if (ext) {
+        if (clip) return dtype_f64 ? occupancy_t<double, true, true>(scheme) : occupancy_t<float, true, true>(scheme);
+        return dtype_f64 ? occupancy_t<double, false, true>(scheme) : occupancy_t<float, false, true>(scheme);
+    }
+    if (clip) return dtype_f64 ? occupancy_t<double, true, false>(scheme) : occupancy_t<float, true, false>(scheme);
+    return dtype_f64 ? occupancy_t<double, false, false>(scheme) : occupancy_t<float, false, false>(scheme);
 }
 
 }  // namespace hjx

@@ -200,13 +200,14 @@ struct BatchArgs {
     int *flags;
     int n_active, items, s, stage, rk, item_nodes;
     int clip;  // some instance has a restricted update
+    int ext;   // some instance plays the rockets game or takes the local dissipation or Godunov's Hamiltonian
 };
 
 hipError_t launch_batch_f32(const BatchArgs<float> &a, int scheme, int blocks, hipStream_t s);
 hipError_t launch_batch_f64(const BatchArgs<double> &a, int scheme, int blocks, hipStream_t s);
 // resident blocks of the batch kernel on one CU (occupancy); clip: the
 // kernel for batches with a restricted update
-int batch_blocks_per_cu(int dtype_f64, int scheme, int clip);
+int batch_blocks_per_cu(int dtype_f64, int scheme, int clip, int ext);
 
 // The seed pass; with rep (nullable) one forward stage of the replay (same
 // grid; p-, p+ kept exactly when a.dp_in is set) runs in the same launch.

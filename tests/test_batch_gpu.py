@@ -2,8 +2,9 @@
 bit for bit as its own hjx_solve, whatever the launch shape, for every RK
 order (forward Euler with odd and even step counts), with members of zero
 steps, with and without targets, across graph replays and re-captures, and
-on the full uneven 256-member workload.  One small FP64 member is also
-checked against the oracle directly."""
+on the full uneven 256-member workload, and with members that play the
+rockets game or take the local dissipation or Godunov's Hamiltonian.  One
+small FP64 member is also checked against the oracle directly."""
 import sys
 
 import numpy as np
@@ -84,6 +85,39 @@ def test_batch_equals_single_solves(dtype, scheme, rk):
     check_equal(got, [r[0] for r in ref], st, [r[1] for r in ref], f"{dtype} {scheme} rk{rk}")
     assert [s["steps"] for s in st] == steps
     assert torch.equal(got[2], phi0[2])   # zero steps: phi0 itself
+    B.close()
+
+
+def ext_members(scheme, rk):
+    """Members that need the extended batch kernel (the rockets game, the
+    local dissipation, Godunov's Hamiltonian), some restricted, beside plain
+    ones."""
+    N2, D3, C4, R = inputs.NORMAL2D, inputs.DUBINS3D, inputs.CAR4D, inputs.ROCKETS
+    return [w.with_(scheme=scheme, rk=rk) for w in [
+        R.with_(n=(15, 13, 11), restrict="none"),
+        D3.with_(n=(17, 15, 13), dissipation="local"),
+        N2.with_(n=(25, 23), dissipation="godunov"),
+        C4.with_(n=(9, 9, 8, 7), dissipation="local", restrict="nonpositive"),
+        N2.with_(n=(13, 11, 12), gmin=(-1, -1, -1), gmax=(1, 1, 1), params=(-0.9,), dissipation="godunov",
+                 restrict="positive"),
+        R.with_(n=(11, 12, 9), dissipation="local"),
+        D3.with_(n=(12, 17, 9)),
+        N2.with_(n=(37, 29)),
+    ]]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("scheme,rk", [("weno5", 3), ("eno2", 2)])
+def test_batch_with_rockets_local_and_godunov_members_equals_single_solves(dtype, scheme, rk):
+    ws = ext_members(scheme, rk)
+    steps = [5, 4, 6, 3, 7, 2, 5, 4]
+    say(f"batch ext {dtype} {scheme} rk{rk}")
+    probs, phi0, t1, target = setup(ws, dtype, steps)
+    B = hjx.Batch(probs)
+    got, st = B.solve(phi0, t1, target=target)
+    ref = singles(probs, phi0, t1, target)
+    check_equal(got, [r[0] for r in ref], st, [r[1] for r in ref], f"ext {dtype} {scheme} rk{rk}")
+    assert [s["steps"] for s in st] == steps
     B.close()
 
 

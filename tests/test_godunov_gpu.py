@@ -2,8 +2,9 @@
 (HJX_DISS_GODUNOV) through the C ABI, against the oracle element by element:
 1-D to 4-D, every scheme and RK order, both signs of the speed, both
 precisions, with a target and with the restricted update, the two-node,
-direct and plane-march kernels, and the 101^2 workload's full solve; the
-batch rejects it (its adjoint is tested in test_adjoint_gpu.py)."""
+direct and plane-march kernels, and the 101^2 workload's full solve.  Its
+adjoint and its place in a batch are tested in test_adjoint_gpu.py and
+test_batch_gpu.py."""
 import sys
 
 import numpy as np
@@ -104,11 +105,3 @@ def test_full_normal2d_solve_with_godunov():
     got, st = gpu_problem(w, "f64").solve(to_dev(phi0, torch.float64), w.t1)
     assert st["steps"] == n_ref == 40
     assert_close(to_host(got), ref, "f64", w.periodic, "normal2d godunov")
-
-
-def test_the_batch_rejects_godunov():
-    P = gpu_problem(CASES["2d"], "f32")
-    with pytest.raises(hjx.HjxError) as e:
-        hjx.Batch([P])
-    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "Godunov" in str(e.value)
-    P.close()

@@ -3,8 +3,8 @@ at each node; HJX_DISS_LOCAL) through the C ABI, against the oracle element
 by element: every Hamiltonian with a node-dependent bound, every scheme and
 RK order in both precisions, with a target and with the restricted update,
 every launch shape, one full-size step; identity with the global form for
-normal motion; the batch rejects it (its adjoint is tested in
-test_adjoint_gpu.py)."""
+normal motion.  Its adjoint and its place in a batch are tested in
+test_adjoint_gpu.py and test_batch_gpu.py."""
 import sys
 
 import numpy as np
@@ -112,12 +112,4 @@ def test_full_size_dubins3d_local_step():
     P = gpu_problem(w, "f64")
     got = P.step(to_dev(phi0, torch.float64), dt, target=to_dev(phi0, torch.float64))
     assert_close(to_host(got), ref, "f64", w.periodic, "101^3 local")
-    P.close()
-
-
-def test_the_batch_rejects_the_local_dissipation():
-    P = gpu_problem(CASES["dubins3d"], "f32")
-    with pytest.raises(hjx.HjxError) as e:
-        hjx.Batch([P])
-    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "local dissipation" in str(e.value)
     P.close()

@@ -2,8 +2,8 @@
 oracle element by element: every derivative scheme and RK order, both
 precisions, ragged sizes, with and without the listing's positive restricted
 update and a target, every launch shape, and one step of the full 100^3
-workload at every node.  The batch rejects the Hamiltonian; its adjoint is
-tested in test_adjoint_gpu.py."""
+workload at every node.  Its adjoint and its place in a batch are tested in
+test_adjoint_gpu.py and test_batch_gpu.py."""
 import sys
 
 import numpy as np
@@ -100,13 +100,4 @@ def test_full_size_rockets_step(dtype):
     got = P.step(to_dev(phi0, TDT[dtype]), dt)
     assert_close(to_host(got), ref, dtype, w.periodic, f"rockets 100^3 {dtype}")
     assert (ref >= phi0 - 1e-12).all() and (ref > phi0 + 1e-6).any()
-    P.close()
-
-
-def test_rockets_is_rejected_by_the_batch():
-    w = small(restrict="none")
-    P = gpu_problem(w, "f32")
-    with pytest.raises(hjx.HjxError) as e:
-        hjx.Batch([P])
-    assert e.value.status == hjx.HJX_ERR_UNSUPPORTED and "ROCKETS" in str(e.value)
     P.close()
